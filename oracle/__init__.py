@@ -1,0 +1,206 @@
+"""FP64 CPU oracle for hybrid-dealiased complex convolutions.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product library
+(``paper_2303_17510_amd``) never imports it, and it imports nothing from the
+product: the two share no code, kernels, headers, tables or helpers.  Inputs
+reach both sides from the seeded generators, which hold none of the method's
+arithmetic.
+
+Functions (Murasko & Bowman, arXiv 2303.17510):
+
+* :func:`conv_direct` -- O1, the definition of Sec. 2 (and its d-dimensional
+  form, Sec. 5) evaluated as a compensated direct sum: the first ``L`` outputs
+  per dimension of the linear convolution of the ``A`` inputs (``mult`` is the
+  pointwise product of the ``A`` transforms, ``B = 1``).  Optional ``idx``
+  evaluates only selected flat output indices (for large sizes).
+* :func:`conv_explicit` -- O2, explicit zero padding to a power of two
+  ``N' >= A(L-1)+1`` (the minimal padding of Sec. 2), this package's own FFT,
+  pointwise product, inverse, truncation to the first ``L`` per dimension.
+* :func:`padded_dft` -- the padded DFT of Sec. 2,
+  ``F_k = sum_{j<L} zeta_N^{kj} f_j`` with ``zeta_N = exp(+2 pi i/N)``.
+* :func:`fft` / :func:`fft_nd` -- the unnormalised transform
+  ``X_k = sum_j x_j exp(sign 2 pi i jk/N)`` (power-of-two sizes).
+
+Parity status: every function here is pinned by ``tests/test_oracle.py``
+against closed forms, library routines and invariants.  None is "parity
+unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "conv.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dblp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = False, out: str | None = None, defines=()) -> str:
+    """Compile ``conv.c`` into ``liboracle.so`` with gcc (FP64, OpenMP)."""
+    target = out or _LIB
+    if force or out or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
+        tmp = target + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11",
+               "-fno-fast-math", "-ffp-contract=off"] + ["-D" + d for d in defines] + \
+              [_SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, target)
+    return target
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    lib.oracle_direct2.argtypes = [_dblp, _dblp, ctypes.c_int, _i64p, _i64p, ctypes.c_int64, _dblp]
+    lib.oracle_fft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int]
+    lib.oracle_fft_nd.argtypes = [_dblp, ctypes.c_int, _i64p, ctypes.c_int]
+    lib.oracle_explicit.argtypes = [ctypes.POINTER(_dblp), ctypes.c_int, ctypes.c_int, _i64p, _dblp]
+    lib.oracle_padded_dft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _dblp]
+    lib.oracle_num_threads.argtypes = []
+    for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit",
+               "oracle_padded_dft", "oracle_num_threads"):
+        getattr(lib, fn).restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            _lib = _bind(_LIB)
+    return _lib
+
+
+def use_library(path: str | None) -> None:
+    """Bind the functions to another build of ``conv.c`` (``None``: the default).
+
+    Only the pin-strength test uses this, to load builds with planted
+    mistakes."""
+    global _lib
+    with _lock:
+        _lib = None
+    if path is not None:
+        global _LIB
+        saved = _LIB
+        try:
+            _LIB = path
+            with _lock:
+                _lib = _bind(path)
+        finally:
+            _LIB = saved
+
+
+def _c128(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_dblp)
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(_i64p)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().oracle_num_threads())
+
+
+def _direct2(f: np.ndarray, g: np.ndarray, idx: np.ndarray | None) -> np.ndarray:
+    shape = f.shape
+    L = np.array(shape, dtype=np.int64)
+    if idx is None:
+        idx = np.arange(f.size, dtype=np.int64)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).ravel())
+    out = np.empty(idx.size, dtype=np.complex128)
+    rc = _load().oracle_direct2(_dp(f), _dp(g), len(shape), _ip(L), _ip(idx), idx.size, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_direct2 failed (%d)" % rc)
+    return out
+
+
+def conv_direct(inputs, idx=None) -> np.ndarray:
+    """O1: first ``L`` outputs (per dimension) of the linear convolution.
+
+    ``inputs`` is a list of ``A`` (2 or 3) complex arrays of one shape
+    (1, 2 or 3 dimensions, row-major).  With ``idx`` (flat indices) only those
+    outputs are returned (A = 2 only); otherwise the full array.
+    """
+    ins = [_c128(x) for x in inputs]
+    if len(ins) not in (2, 3) or any(x.shape != ins[0].shape for x in ins):
+        raise ValueError("need 2 or 3 inputs of one shape")
+    if ins[0].ndim not in (1, 2, 3):
+        raise ValueError("1 to 3 dimensions")
+    if len(ins) == 2:
+        out = _direct2(ins[0], ins[1], idx)
+        return out if idx is not None else out.reshape(ins[0].shape)
+    if idx is not None:
+        raise ValueError("sampled outputs are for A = 2")
+    # A = 3: indices are non-negative, so truncating the first product to the
+    # output box loses nothing the second product needs.
+    t = _direct2(ins[0], ins[1], None).reshape(ins[0].shape)
+    return _direct2(t, ins[2], None).reshape(ins[0].shape)
+
+
+def conv_explicit(inputs) -> np.ndarray:
+    """O2: explicitly zero-padded FFT convolution, first ``L`` per dimension."""
+    ins = [_c128(x) for x in inputs]
+    if len(ins) not in (2, 3) or any(x.shape != ins[0].shape for x in ins):
+        raise ValueError("need 2 or 3 inputs of one shape")
+    shape = ins[0].shape
+    L = np.array(shape, dtype=np.int64)
+    ptrs = (_dblp * len(ins))(*[_dp(x) for x in ins])
+    out = np.empty(shape, dtype=np.complex128)
+    rc = _load().oracle_explicit(ptrs, len(ins), len(shape), _ip(L), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_explicit failed (%d)" % rc)
+    return out
+
+
+def padded_dft(f, N: int, ks) -> np.ndarray:
+    """Padded DFT ``F_k = sum_{j<L} exp(2 pi i k j / N) f_j`` at the given ``ks``."""
+    f = _c128(f).ravel()
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
+    out = np.empty(ks.size, dtype=np.complex128)
+    rc = _load().oracle_padded_dft(_dp(f), f.size, int(N), _ip(ks), ks.size, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_padded_dft failed (%d)" % rc)
+    return out
+
+
+def fft(x, sign: int = +1) -> np.ndarray:
+    """Unnormalised 1D transform with kernel ``exp(sign 2 pi i jk/N)``."""
+    y = _c128(x).copy()
+    rc = _load().oracle_fft(_dp(y), y.size, int(sign))
+    if rc != 0:
+        raise ValueError("oracle_fft failed (%d)" % rc)
+    return y
+
+
+def fft_nd(x, sign: int = +1) -> np.ndarray:
+    """Unnormalised n-D transform (row-column), power-of-two extents."""
+    y = _c128(x).copy()
+    N = np.array(y.shape, dtype=np.int64)
+    rc = _load().oracle_fft_nd(_dp(y), y.ndim, _ip(N), int(sign))
+    if rc != 0:
+        raise ValueError("oracle_fft_nd failed (%d)" % rc)
+    return y
+
+
+def rel_l2(y, ref) -> float:
+    """Relative L2 error ``||y - ref|| / ||ref||`` computed in FP64."""
+    y = np.asarray(y, dtype=np.complex128).ravel()
+    ref = np.asarray(ref, dtype=np.complex128).ravel()
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(y - ref) / (den if den > 0 else 1.0))

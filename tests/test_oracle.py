@@ -1,0 +1,215 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each check ties an oracle function to mathematics or a library routine that
+does not share its code: numpy's FFT and convolution, scipy's direct
+convolution, closed forms of the linear convolution (delta, all-ones,
+geometric sequences, separable products), and invariants (linearity,
+commutativity, shift equivariance).  The definition being pinned is the
+linear convolution of Sec. 2 (its first L outputs, which Algorithm 1 returns)
+and the padded DFT with zeta_N = exp(+2 pi i/N) (Sec. 2).
+"""
+import numpy as np
+import pytest
+import scipy.signal
+
+import oracle
+from paper_2303_17510_amd import synth
+
+
+def rnd(shape, seed):
+    return synth.unit_disk(shape, seed)
+
+
+# ---------------------------------------------------------------- FFT ------
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 64, 1024, 4096])
+def test_fft_matches_numpy_both_signs(n):
+    x = rnd(n, 11 + n)
+    # numpy's fft uses exp(-2 pi i jk/N); n * ifft uses exp(+2 pi i jk/N).
+    np.testing.assert_allclose(oracle.fft(x, -1), np.fft.fft(x), rtol=0, atol=1e-12 * max(1, n))
+    np.testing.assert_allclose(oracle.fft(x, +1), n * np.fft.ifft(x), rtol=0, atol=1e-12 * max(1, n))
+
+
+def test_fft_closed_forms():
+    n = 256
+    d = np.zeros(n, complex)
+    d[0] = 1
+    np.testing.assert_allclose(oracle.fft(d, +1), np.ones(n), atol=1e-15)
+    # shifted delta -> exp(+2 pi i k s / n): fixes the sign convention
+    s = 5
+    d = np.zeros(n, complex)
+    d[s] = 1
+    k = np.arange(n)
+    np.testing.assert_allclose(oracle.fft(d, +1), np.exp(2j * np.pi * k * s / n), atol=1e-13)
+    # Parseval
+    x = rnd(n, 3)
+    X = oracle.fft(x, +1)
+    assert abs(np.vdot(X, X).real - n * np.vdot(x, x).real) < 1e-9 * n
+
+
+def test_fft_nd_matches_numpy():
+    x = rnd((8, 16, 4), 5)
+    np.testing.assert_allclose(oracle.fft_nd(x, -1), np.fft.fftn(x), atol=1e-11)
+    np.testing.assert_allclose(oracle.fft_nd(x, +1), x.size * np.fft.ifftn(x), atol=1e-11)
+
+
+def test_fft_rejects_non_power_of_two():
+    with pytest.raises(ValueError):
+        oracle.fft(np.ones(12), +1)
+
+
+# ------------------------------------------------------- padded DFT -------
+@pytest.mark.parametrize("L,N", [(1, 1), (6, 12), (6, 11), (100, 256), (37, 37), (64, 96)])
+def test_padded_dft_matches_zero_padded_library_dft(L, N):
+    f = rnd(L, 7 * L + N)
+    fp = np.zeros(N, complex)
+    fp[:L] = f
+    ref = N * np.fft.ifft(fp)          # sum_j exp(+2 pi i jk/N) f_j
+    ks = np.arange(N)
+    np.testing.assert_allclose(oracle.padded_dft(f, N, ks), ref, atol=1e-12 * L)
+    # periodic in k
+    np.testing.assert_allclose(oracle.padded_dft(f, N, ks + 3 * N), ref, atol=1e-12 * L)
+
+
+def test_padded_dft_residue_block_structure():
+    # eq. forStan: F_{q l + r} for one residue r equals the m-point DFT of the
+    # pre-processed sequence W_s = sum_t zeta_{qm}^{r(tm+s)} f_{tm+s}.  Here the
+    # pre-processing is evaluated with numpy, independent of the oracle.
+    L, m, q = 10, 4, 5
+    p = -(-L // m)
+    f = rnd(L, 99)
+    fp = np.zeros(p * m, complex)
+    fp[:L] = f
+    for r in range(q):
+        W = np.zeros(m, complex)
+        for s in range(m):
+            for t in range(p):
+                j = t * m + s
+                W[s] += np.exp(2j * np.pi * r * j / (q * m)) * fp[j]
+        block = m * np.fft.ifft(W)      # + sign m-point DFT
+        got = oracle.padded_dft(f, q * m, q * np.arange(m) + r)
+        np.testing.assert_allclose(got, block, atol=1e-12)
+
+
+# ------------------------------------------------------- direct sums ------
+@pytest.mark.parametrize("L", [1, 2, 3, 7, 64, 257, 1024])
+def test_direct_1d_matches_numpy_convolve(L):
+    f, g = rnd(L, 1000 + L), rnd(L, 2000 + L)
+    ref = np.convolve(f, g)[:L]
+    np.testing.assert_allclose(oracle.conv_direct([f, g]), ref, rtol=0, atol=1e-13 * L)
+
+
+def test_direct_1d_closed_forms():
+    L = 50
+    # delta * delta = delta at a+b (if inside the first L outputs), else zero
+    for a, b in [(0, 0), (3, 9), (20, 29), (30, 25)]:
+        f = np.zeros(L, complex)
+        g = np.zeros(L, complex)
+        f[a] = 1
+        g[b] = 1
+        ref = np.zeros(L, complex)
+        if a + b < L:
+            ref[a + b] = 1
+        np.testing.assert_array_equal(oracle.conv_direct([f, g]), ref)
+    # ones * ones: c_j = j + 1
+    o = np.ones(L, complex)
+    np.testing.assert_array_equal(oracle.conv_direct([o, o]), np.arange(1, L + 1))
+    # geometric: a^k * b^k -> (a^{j+1} - b^{j+1}) / (a - b)
+    a, b = 0.9 * np.exp(0.3j), 0.7 * np.exp(-1.1j)
+    k = np.arange(L)
+    ref = (a ** (k + 1) - b ** (k + 1)) / (a - b)
+    np.testing.assert_allclose(oracle.conv_direct([a ** k, b ** k]), ref, rtol=1e-13, atol=1e-15)
+    # equal ratios: (j + 1) a^j
+    np.testing.assert_allclose(oracle.conv_direct([a ** k, a ** k]), (k + 1) * a ** k, rtol=1e-13, atol=1e-15)
+
+
+def test_direct_triple_closed_form():
+    L = 40
+    a, b, c = 0.95 * np.exp(0.2j), 0.8 * np.exp(1.3j), 0.6 * np.exp(-2.0j)
+    k = np.arange(L)
+    ref = sum(x ** (k + 2) / np.prod([x - y for y in (a, b, c) if y is not x]) for x in (a, b, c))
+    got = oracle.conv_direct([a ** k, b ** k, c ** k])
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+    f, g, h = rnd(L, 1), rnd(L, 2), rnd(L, 3)
+    ref = np.convolve(np.convolve(f, g), h)[:L]
+    np.testing.assert_allclose(oracle.conv_direct([f, g, h]), ref, atol=1e-12)
+
+
+def test_direct_sampled_indices():
+    L = 300
+    f, g = rnd(L, 5), rnd(L, 6)
+    full = oracle.conv_direct([f, g])
+    idx = np.array([0, 1, 17, 150, L - 2, L - 1])
+    np.testing.assert_array_equal(oracle.conv_direct([f, g], idx=idx), full[idx])
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (16, 16), (3, 33)])
+def test_direct_2d_matches_scipy(shape):
+    f, g = rnd(shape, 10), rnd(shape, 11)
+    ref = scipy.signal.convolve(f, g, method="direct")[: shape[0], : shape[1]]
+    np.testing.assert_allclose(oracle.conv_direct([f, g]), ref, atol=1e-12)
+
+
+def test_direct_3d_matches_scipy_and_separable():
+    shape = (4, 5, 6)
+    f, g = rnd(shape, 12), rnd(shape, 13)
+    ref = scipy.signal.convolve(f, g, method="direct")[:4, :5, :6]
+    np.testing.assert_allclose(oracle.conv_direct([f, g]), ref, atol=1e-12)
+    # separable: (x1 y1 z1) * (x2 y2 z2) = (x1*x2)(y1*y2)(z1*z2)
+    xs = [rnd(n, 20 + n) for n in shape]
+    ys = [rnd(n, 40 + n) for n in shape]
+    F = np.einsum("i,j,k->ijk", *xs)
+    G = np.einsum("i,j,k->ijk", *ys)
+    parts = [np.convolve(x, y)[: len(x)] for x, y in zip(xs, ys)]
+    np.testing.assert_allclose(oracle.conv_direct([F, G]), np.einsum("i,j,k->ijk", *parts), atol=1e-12)
+
+
+def test_direct_invariants():
+    L = 128
+    f, g, h = rnd(L, 31), rnd(L, 32), rnd(L, 33)
+    al, be = 0.3 - 1.2j, -0.7 + 0.1j
+    cf = oracle.conv_direct([f, g])
+    # commutativity
+    np.testing.assert_allclose(oracle.conv_direct([g, f]), cf, atol=1e-13)
+    # linearity in the first input
+    np.testing.assert_allclose(oracle.conv_direct([al * f + be * h, g]),
+                               al * cf + be * oracle.conv_direct([h, g]), atol=1e-12)
+    # shift equivariance: delta_s * f = f shifted by s, truncated
+    s = 17
+    d = np.zeros(L, complex)
+    d[s] = 1
+    ref = np.zeros(L, complex)
+    ref[s:] = f[: L - s]
+    np.testing.assert_array_equal(oracle.conv_direct([d, f]), ref)
+
+
+# --------------------------------------------------- explicit FFT conv ----
+@pytest.mark.parametrize("L", [1, 2, 5, 64, 100, 1024, 1500])
+def test_explicit_matches_direct_1d(L):
+    f, g = rnd(L, 300 + L), rnd(L, 400 + L)
+    ref = oracle.conv_direct([f, g])
+    assert oracle.rel_l2(oracle.conv_explicit([f, g]), ref) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (13, 21), (3, 4, 5)])
+def test_explicit_matches_direct_nd(shape):
+    f, g = rnd(shape, 7), rnd(shape, 8)
+    assert oracle.rel_l2(oracle.conv_explicit([f, g]), oracle.conv_direct([f, g])) < 1e-14
+
+
+def test_explicit_triple():
+    L = 90
+    f, g, h = rnd(L, 1), rnd(L, 2), rnd(L, 3)
+    assert oracle.rel_l2(oracle.conv_explicit([f, g, h]), oracle.conv_direct([f, g, h])) < 1e-14
+
+
+def test_explicit_closed_form_geometric_large():
+    L = 1 << 14
+    a, b = 0.9999 * np.exp(0.001j), 0.9995 * np.exp(-0.002j)
+    k = np.arange(L)
+    ref = (a ** (k + 1) - b ** (k + 1)) / (a - b)
+    assert oracle.rel_l2(oracle.conv_explicit([a ** k, b ** k]), ref) < 1e-12
+
+
+def test_rel_l2():
+    assert oracle.rel_l2([1, 0], [1, 0]) == 0
+    assert abs(oracle.rel_l2([1, 1], [1, 0]) - 1.0) < 1e-15
