@@ -1,0 +1,143 @@
+/*
+ * hdconv.h -- C ABI of the MI355X (gfx950) hybrid-dealiased convolution
+ * library (libhdconv.so).
+ *
+ * The operation is the one defined in Sec. 2 of Murasko & Bowman, "Hybrid
+ * Dealiasing of Complex Convolutions" (arXiv 2303.17510): A complex inputs of
+ * equal length L (per dimension), each zero padded to at least M, and
+ * B = 1 output whose DFT is the pointwise product of the A padded DFTs
+ * (the multiplication operator of Sec. 2).  The library returns the first L
+ * outputs per dimension, which are the outputs Algorithm 1 accumulates,
+ * i.e. for A = 2
+ *     h_j = sum_{i=0}^{j} f_i g_{j-i},   j = 0 .. L-1,
+ * and the box-truncated d-dimensional analogue for d = 2, 3 (Sec. 5).
+ *
+ * Data: dense, row-major arrays of prod(L) complex words, interleaved
+ * (re, im); dimension 0 is the slowest.  HDCONV_C64 = float pairs,
+ * HDCONV_C128 = double pairs.  All data pointers are device pointers.
+ *
+ * Threading: a plan owns device workspace and is not re-entrant; use one
+ * plan per concurrent stream.  Separate plans are independent.  Errors never
+ * throw across the ABI: functions return a status (or NULL) and
+ * hdconv_last_error() gives the calling thread's last message.
+ */
+#ifndef HDCONV_H
+#define HDCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types */
+enum { HDCONV_C64 = 0, HDCONV_C128 = 1 };
+
+/* status codes */
+enum {
+  HDCONV_OK = 0,
+  HDCONV_EINVAL = -1,      /* invalid argument (sizes, pointers, geometry) */
+  HDCONV_ENOMEM = -2,      /* device allocation failed or exceeds the cap  */
+  HDCONV_EDEVICE = -3,     /* a HIP call failed; message has its text       */
+  HDCONV_EUNSUPPORTED = -4,/* valid request outside what this build runs    */
+  HDCONV_ENODEV = -5       /* no HIP device is available                    */
+};
+
+/* method: hybrid dealiasing (Sec. 2.1) or conventional explicit padding
+ * (inputs materialised zero-padded to a {2,3}-smooth size >= M, full FFTs,
+ * product, inverse FFT, first L copied out: the baseline the paper compares
+ * against, Sec. 7). */
+enum { HDCONV_METHOD_AUTO = 0, HDCONV_METHOD_HYBRID = 1, HDCONV_METHOD_EXPLICIT = 2 };
+
+/* per-dimension kernel variant */
+enum {
+  HDCONV_VARIANT_AUTO = 0,
+  HDCONV_VARIANT_FUSED = 1,     /* innermost dim, p <= 2: whole row in one workgroup (Alg. 3-6) */
+  HDCONV_VARIANT_MULTIPASS = 2, /* innermost dim, inner-loop form (Sec. 6.1), three passes      */
+  HDCONV_VARIANT_OUTER = 3      /* outer dim of a 2D/3D convolution, p <= 2 (Sec. 5)            */
+};
+
+/* plan flags */
+enum {
+  HDCONV_PLAN_HOST_ONLY = 1 /* plan geometry only: no device memory, cannot execute */
+};
+
+typedef struct hdconv_options {
+  int method;        /* HDCONV_METHOD_*                                         */
+  int flags;         /* HDCONV_PLAN_*                                           */
+  int64_t m[3];      /* forced subtransform size per dimension (0: choose)      */
+  int64_t p[3];      /* forced explicit block count, >= ceil(L/m) (0: minimal)  */
+  int64_t D[3];      /* residues per block, innermost multipass dim (0: all)    */
+  int variant[3];    /* HDCONV_VARIANT_* per dimension                          */
+  int reserved[8];   /* zero                                                    */
+} hdconv_options;
+
+typedef struct hdconv_dim_info {
+  int64_t L, M;      /* lengths the engine works on in this dimension           */
+  int64_t m, p, n, q;/* paper's subtransform size, explicit blocks, residues, q */
+  int64_t D;         /* residues per block                                      */
+  int variant;       /* HDCONV_VARIANT_*                                        */
+  int E_m, E_p;      /* points per lane of the m- and p-point transforms        */
+  int S;             /* columns per workgroup (column / outer kernels)          */
+  int rows_per_block;/* rows per workgroup (row kernels)                        */
+} hdconv_dim_info_t;
+
+typedef struct hdconv_plan_info {
+  int dims, A, B, dtype, method;
+  int64_t L[3], M[3];            /* the user's problem                           */
+  hdconv_dim_info_t dim[3];
+  int64_t npad[3];               /* explicit method: padded extents, else 0      */
+  size_t workspace_bytes;        /* device workspace owned by the plan           */
+  size_t table_bytes;            /* device twiddle tables owned by the plan      */
+  double compulsory_bytes;       /* (A+B) prod(L) word bytes: read inputs, write output once */
+  double traffic_bytes;          /* bytes the plan's kernels read + write by design */
+  int launches;                  /* kernel launches per execute                  */
+} hdconv_plan_info_t;
+
+/* Fill *opt with defaults (AUTO everywhere, nothing forced). */
+void hdconv_options_init(hdconv_options* opt);
+
+/* Create a plan on the current HIP device.  L[d], M[d] for d < dims
+ * (dims in {1,2,3}); A in {2,3}; B = 1; dtype HDCONV_C64 or HDCONV_C128.
+ * Requires L[d] >= 1 and M[d] >= A (L[d]-1) + 1 (the padding that keeps the
+ * product of A inputs unaliased, Sec. 2).  Allocates twiddle tables (FP64
+ * generated, stored in dtype) and workspace with hipMalloc.  Returns NULL on
+ * error (hdconv_last_error gives the reason). */
+void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype);
+void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                     const hdconv_options* opt);
+
+/* Run the convolution asynchronously on `stream` (a hipStream_t; NULL = the
+ * null stream).  inputs: A device pointers, outputs: B device pointers, each
+ * to prod(L) words of dtype.  outputs[0] may equal one of the inputs
+ * (in place, as in Algorithm 1); any other overlap is HDCONV_EINVAL.  The
+ * inputs are not modified unless aliased by the output.  Returns the launch
+ * status; no synchronisation is done. */
+int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, void* stream);
+
+/* Plan geometry and sizes. */
+int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out);
+
+/* Release a plan (synchronises the device first).  NULL is ignored. */
+void hdconv_destroy(void* plan);
+
+/* The paper's geometry rules for one dimension and a given m (Algorithm 1,
+ * eq. pqdef1, Sec. 6.1): p = max(ceil(L/m), p_min); if p <= 2 and not
+ * force_inner: q = n = ceil(M/m); else n = ceil(M/(p m)), q = n p.  Host only.
+ * Fills out->{L,M,m,p,n,q,D=n,variant} (variant FUSED for the direct form,
+ * MULTIPASS for the inner form). */
+int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner,
+                    hdconv_dim_info_t* out);
+
+/* Copy the calling thread's last error message into msg (NUL terminated,
+ * truncated to cap) and return its status code (HDCONV_OK if none). */
+int hdconv_last_error(char* msg, size_t cap);
+
+/* Library version string. */
+const char* hdconv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDCONV_H */

@@ -1,0 +1,100 @@
+"""ctypes binding of libhdconv.so (the C ABI in include/hdconv.h).
+
+Argument marshalling only: every step of a convolution runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the library
+is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdconv.so")
+
+C64, C128 = 0, 1
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENODEV = 0, -1, -2, -3, -4, -5
+METHOD_AUTO, METHOD_HYBRID, METHOD_EXPLICIT = 0, 1, 2
+VARIANT_AUTO, VARIANT_FUSED, VARIANT_MULTIPASS, VARIANT_OUTER = 0, 1, 2, 3
+PLAN_HOST_ONLY = 1
+
+VARIANT_NAMES = {0: "auto", 1: "fused", 2: "multipass", 3: "outer"}
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENODEV"}
+
+_i64 = ctypes.c_int64
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("flags", ctypes.c_int),
+                ("m", _i64 * 3), ("p", _i64 * 3), ("D", _i64 * 3),
+                ("variant", ctypes.c_int * 3), ("reserved", ctypes.c_int * 8)]
+
+
+class DimInfo(ctypes.Structure):
+    _fields_ = [("L", _i64), ("M", _i64), ("m", _i64), ("p", _i64), ("n", _i64), ("q", _i64),
+                ("D", _i64), ("variant", ctypes.c_int), ("E_m", ctypes.c_int), ("E_p", ctypes.c_int),
+                ("S", ctypes.c_int), ("rows_per_block", ctypes.c_int)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int), ("A", ctypes.c_int), ("B", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("method", ctypes.c_int), ("L", _i64 * 3), ("M", _i64 * 3), ("dim", DimInfo * 3),
+                ("npad", _i64 * 3), ("workspace_bytes", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
+                ("compulsory_bytes", ctypes.c_double), ("traffic_bytes", ctypes.c_double),
+                ("launches", ctypes.c_int)]
+
+
+# every symbol include/hdconv.h declares, with its signature
+SIGNATURES = {
+    "hdconv_options_init": (None, [ctypes.POINTER(Options)]),
+    "hdconv_plan": (ctypes.c_void_p, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int]),
+    "hdconv_plan_ex": (ctypes.c_void_p, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]),
+    "hdconv_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
+    "hdconv_destroy": (None, [ctypes.c_void_p]),
+    "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),
+    "hdconv_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+    "hdconv_version": (ctypes.c_char_p, []),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class HdconvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("libhdconv.so is not built (run python -m paper_2303_17510_amd.build): %s"
+                                  % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def last_error():
+    buf = ctypes.create_string_buffer(512)
+    code = lib().hdconv_last_error(buf, 512)
+    return code, buf.value.decode(errors="replace")
+
+
+def check(rc: int):
+    if rc != OK:
+        code, msg = last_error()
+        raise HdconvError(rc, msg)

@@ -1,0 +1,709 @@
+// hd_api.cpp -- C ABI of libhdconv: plans, device tables, workspace and the
+// launch sequence of one convolution.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hdconv.h"
+#include "hd_engine.hpp"
+#include "hd_plan.hpp"
+
+using namespace hd;
+
+// ---------------------------------------------------------------------------
+// thread-local last error
+namespace {
+thread_local int g_err_code = HDCONV_OK;
+thread_local char g_err_msg[512] = {0};
+
+int set_err(int code, const char* fmt, ...) {
+  g_err_code = code;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err_msg, sizeof(g_err_msg), fmt, ap);
+  va_end(ap);
+  return code;
+}
+void clear_err() {
+  g_err_code = HDCONV_OK;
+  g_err_msg[0] = 0;
+}
+int hip_err(hipError_t e, const char* what) {
+  return set_err(HDCONV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device copy of the per-dimension tables.
+struct DimDev {
+  void* fft_m = nullptr;  // stage twiddles of the m-point transform
+  void* fft_p = nullptr;  // stage twiddles of the p-point transform
+  void* zq = nullptr;     // zeta_q^k, k < q (inner form)
+  void* zlo = nullptr;    // two-level table of zeta_{qm}
+  void* zhi = nullptr;
+  int kbits = 0;
+};
+
+}  // namespace
+
+struct Plan {
+  int dims = 0, A = 0, B = 0, dtype = 0, method = 0, flags = 0;
+  int64_t L[3] = {1, 1, 1}, M[3] = {1, 1, 1};
+  int64_t npad[3] = {0, 0, 0};
+  DimPlan dp[3];
+  int device = -1;
+  bool host_only = false;
+  // device memory
+  char* table_mem = nullptr;
+  size_t table_bytes = 0;
+  DimDev dd[3];
+  char* work_mem = nullptr;
+  size_t work_bytes = 0;
+  void* pad_in[kMaxA] = {nullptr, nullptr, nullptr};  // explicit method
+  void* lvl[2][kMaxA] = {{nullptr}};                  // outer-level buffers W_d
+  void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
+  double* acc64 = nullptr;                            // multi-block accumulator
+  int launches = 0;
+};
+
+// ---------------------------------------------------------------------------
+// planning
+
+static int tbytes_of(int dtype) { return dtype == HDCONV_C64 ? 4 : 8; }
+
+static int build_dims(Plan* P, const hdconv_options* opt) {
+  const int tb = tbytes_of(P->dtype);
+  for (int d = 0; d < P->dims; ++d) {
+    const bool contiguous = (d == P->dims - 1);
+    int64_t Le = P->L[d], Me = P->M[d];
+    if (P->method == HDCONV_METHOD_EXPLICIT) Le = Me = P->npad[d];
+    DimPlan& dp = P->dp[d];
+    std::string why;
+    const int64_t fm = opt ? opt->m[d] : 0;
+    const int64_t fp = opt ? opt->p[d] : 0;
+    int fv = opt ? opt->variant[d] : 0;
+    if (fm == 0 && fp == 0 && fv == 0) {
+      if (P->method == HDCONV_METHOD_EXPLICIT) {
+        // one full-length transform per dimension: p = q = 1 (or inner form with n = 1)
+        dp = DimPlan{};
+        dp.L = Le;
+        dp.M = Me;
+        if (!contiguous || Le <= kMaxFusedM) {
+          dp.m = Le;
+          dp.p = dp.q = dp.n = dp.D = 1;
+          dp.variant = contiguous ? VAR_FUSED : VAR_OUTER;
+        } else {
+          // largest m up to 8192 (c64) / 4096 (c128), then any m, with p = N'/m valid
+          int64_t m = 0;
+          for (int pass = 0; pass < 2 && m == 0; ++pass) {
+            const int64_t mmax = pass == 0 ? (tb == 4 ? 8192 : 4096) : kMaxRowM;
+            for (int64_t c = mmax; c >= 8 && m == 0; --c)
+              if (fft_size_ok(c) && Le % c == 0 && fft_size_ok(Le / c) && Le / c <= kMaxColP) m = c;
+          }
+          if (m == 0) return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d: no split of N'=%lld", d, (long long)Le);
+          dp.m = m;
+          dp.p = Le / m;
+          dp.n = dp.D = 1;
+          dp.q = dp.p;
+          dp.variant = VAR_MULTI;
+        }
+        if (!finish_dim(&dp, tb, &why))
+          return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
+      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, &dp, &why)) {
+        return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
+      }
+    } else {
+      if (fv == HDCONV_VARIANT_AUTO) {
+        Geometry g = geometry(Le, Me, fm ? fm : next_fft_size(Le), fp, false);
+        fv = contiguous ? (g.inner ? VAR_MULTI : VAR_FUSED) : VAR_OUTER;
+      }
+      if (contiguous && fv == VAR_OUTER) return set_err(HDCONV_EINVAL, "dim %d: outer variant on the innermost dimension", d);
+      if (!contiguous && fv != VAR_OUTER) return set_err(HDCONV_EUNSUPPORTED, "dim %d: outer dimensions use the outer variant", d);
+      int64_t m = fm ? fm : next_fft_size(fv == VAR_MULTI ? cdiv(Le, std::max<int64_t>(fp, 4)) : Le);
+      Geometry g = geometry(Le, Me, m, fp, fv == VAR_MULTI);
+      if (g.inner && fv != VAR_MULTI)
+        return set_err(HDCONV_EINVAL, "dim %d: m=%lld gives p=%lld > 2, which needs the multipass variant", d,
+                       (long long)m, (long long)g.p);
+      if (fv == VAR_MULTI && !fft_size_ok(g.p)) {
+        g = geometry(Le, Me, m, next_col_size(g.p), true);
+      }
+      dp = DimPlan{};
+      dp.L = Le;
+      dp.M = Me;
+      dp.m = g.m;
+      dp.p = g.p;
+      dp.n = g.n;
+      dp.q = g.q;
+      dp.D = (opt && opt->D[d] > 0) ? std::min<int64_t>(opt->D[d], g.n) : g.n;
+      dp.variant = fv;
+      if (!finish_dim(&dp, tb, &why))
+        return set_err(HDCONV_EUNSUPPORTED, "dim %d (m=%lld, p=%lld, q=%lld): %s", d, (long long)dp.m,
+                       (long long)dp.p, (long long)dp.q, why.c_str());
+    }
+  }
+  return HDCONV_OK;
+}
+
+// bytes moved by the kernels of one execute, by design (reads + writes)
+static double plan_traffic(const Plan* P, int* launches) {
+  const double w = 2.0 * tbytes_of(P->dtype);
+  const int A = P->A, B = P->B;
+  double bytes = 0;
+  int nl = 0;
+  int64_t Le[3];
+  for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
+  double ltot = 1, etot = 1;
+  for (int d = 0; d < P->dims; ++d) {
+    ltot *= (double)P->L[d];
+    etot *= (double)Le[d];
+  }
+  if (P->method == HDCONV_METHOD_EXPLICIT) {
+    bytes += A * (ltot + etot) * w;  // padding copies
+    bytes += B * (etot + ltot) * w;  // truncating copy
+    nl += A + 1;
+  }
+  double nb = 1;  // planes entering the current level
+  for (int d = 0; d + 1 < P->dims; ++d) {
+    const DimPlan& dp = P->dp[d];
+    double rest = 1;
+    for (int e = d + 1; e < P->dims; ++e) rest *= (double)Le[e];
+    const double in_el = nb * Le[d] * rest, out_el = nb * dp.q * dp.m * rest;
+    bytes += A * (in_el + out_el) * w + B * (out_el + in_el) * w;  // forward + backward
+    nl += 2;
+    nb *= (double)(dp.q * dp.m);
+  }
+  const DimPlan& dl = P->dp[P->dims - 1];
+  const double rows = nb, Lr = (double)Le[P->dims - 1];
+  if (dl.variant == VAR_FUSED) {
+    bytes += rows * (A + B) * Lr * w;
+    nl += 1;
+  } else {
+    const int64_t blocks = cdiv(dl.n, dl.D);
+    const double wk = rows * (double)dl.q * dl.m;  // all residues' rows
+    bytes += blocks * rows * A * Lr * w + A * wk * w;  // K1: read inputs per block, write work
+    bytes += (A + B) * wk * w;                         // K2
+    bytes += B * wk * w + rows * B * Lr * w;           // K3
+    if (blocks > 1) bytes += (2.0 * blocks - 2) * rows * B * Lr * 16.0;  // FP64 accumulator round trips
+    nl += 3 * (int)blocks;
+  }
+  if (launches) *launches = nl;
+  return bytes;
+}
+
+template <typename T>
+static void to_dtype(const std::vector<double>& v, std::vector<char>* out) {
+  out->resize(v.size() * sizeof(T));
+  T* p = reinterpret_cast<T*>(out->data());
+  for (size_t i = 0; i < v.size(); ++i) p[i] = (T)v[i];
+}
+
+static int alloc_tables(Plan* P) {
+  // host images of every table, concatenated with 256-byte alignment
+  std::vector<std::vector<double>> parts;
+  struct Ref { int dim, kind; };
+  std::vector<Ref> refs;
+  for (int d = 0; d < P->dims; ++d) {
+    DimPlan& dp = P->dp[d];
+    parts.push_back(stage_twiddles(&dp.fd_m));
+    refs.push_back({d, 0});
+    if (dp.variant == VAR_MULTI) {
+      parts.push_back(stage_twiddles(&dp.fd_p));
+      refs.push_back({d, 1});
+      std::vector<double> zq(2 * dp.q);
+      for (int64_t k = 0; k < dp.q; ++k) root(dp.q, k, &zq[2 * k], &zq[2 * k + 1]);
+      parts.push_back(zq);
+      refs.push_back({d, 2});
+    }
+    const int64_t qm = dp.q * dp.m;
+    int kb = 0;
+    while ((int64_t(1) << (2 * kb)) < qm) ++kb;  // K ~ sqrt(qm)
+    P->dd[d].kbits = kb;
+    const int64_t K = int64_t(1) << kb;
+    std::vector<double> lo(2 * K), hi(2 * cdiv(qm, K));
+    for (int64_t e = 0; e < K; ++e) root(qm, e, &lo[2 * e], &lo[2 * e + 1]);
+    for (int64_t h = 0; h < cdiv(qm, K); ++h) root(qm, h * K, &hi[2 * h], &hi[2 * h + 1]);
+    parts.push_back(lo);
+    refs.push_back({d, 3});
+    parts.push_back(hi);
+    refs.push_back({d, 4});
+  }
+  const int tb = tbytes_of(P->dtype);
+  std::vector<size_t> off;
+  size_t total = 0;
+  for (auto& v : parts) {
+    off.push_back(total);
+    total += ((v.size() * tb + 255) / 256) * 256 + 256;
+  }
+  P->table_bytes = total;
+  if (P->host_only) return HDCONV_OK;
+  hipError_t e = hipMalloc((void**)&P->table_mem, total);
+  if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(tables, %zu): %s", total, hipGetErrorString(e));
+  std::vector<char> host(total, 0);
+  for (size_t i = 0; i < parts.size(); ++i) {
+    std::vector<char> img;
+    if (tb == 4) to_dtype<float>(parts[i], &img);
+    else to_dtype<double>(parts[i], &img);
+    if (!img.empty()) memcpy(host.data() + off[i], img.data(), img.size());
+    void* ptr = P->table_mem + off[i];
+    DimDev& dd = P->dd[refs[i].dim];
+    switch (refs[i].kind) {
+      case 0: dd.fft_m = ptr; break;
+      case 1: dd.fft_p = ptr; break;
+      case 2: dd.zq = ptr; break;
+      case 3: dd.zlo = ptr; break;
+      case 4: dd.zhi = ptr; break;
+    }
+  }
+  e = hipMemcpy(P->table_mem, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_err(e, "hipMemcpy(tables)");
+  return HDCONV_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static int alloc_workspace(Plan* P) {
+  const size_t w = 2 * (size_t)tbytes_of(P->dtype);
+  int64_t Le[3];
+  for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
+  std::vector<std::pair<void**, size_t>> want;
+  if (P->method == HDCONV_METHOD_EXPLICIT) {
+    size_t n = 1;
+    for (int d = 0; d < P->dims; ++d) n *= (size_t)P->npad[d];
+    for (int a = 0; a < P->A; ++a) want.push_back({&P->pad_in[a], n * w});
+  }
+  size_t nb = 1;
+  for (int d = 0; d + 1 < P->dims; ++d) {
+    size_t rest = 1;
+    for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)Le[e];
+    nb *= (size_t)(P->dp[d].q * P->dp[d].m);
+    for (int a = 0; a < P->A; ++a) want.push_back({&P->lvl[d][a], nb * rest * w});
+  }
+  const DimPlan& dl = P->dp[P->dims - 1];
+  if (dl.variant == VAR_MULTI) {
+    const size_t rowsz = nb * (size_t)(dl.D * dl.p * dl.m);
+    for (int a = 0; a < P->A; ++a) want.push_back({&P->rowwork[a], rowsz * w});
+    if (dl.D < dl.n) want.push_back({(void**)&P->acc64, nb * (size_t)Le[P->dims - 1] * 16});
+  }
+  size_t total = 0;
+  for (auto& x : want) total += align256(x.second);
+  P->work_bytes = total;
+  if (P->host_only || total == 0) return HDCONV_OK;
+  const char* cap = getenv("HDCONV_WORKSPACE_CAP");
+  if (cap && (size_t)atoll(cap) < total)
+    return set_err(HDCONV_ENOMEM, "workspace of %zu bytes exceeds HDCONV_WORKSPACE_CAP=%s", total, cap);
+  hipError_t e = hipMalloc((void**)&P->work_mem, total);
+  if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(workspace, %zu): %s", total, hipGetErrorString(e));
+  size_t o = 0;
+  for (auto& x : want) {
+    *x.first = P->work_mem + o;
+    o += align256(x.second);
+  }
+  return HDCONV_OK;
+}
+
+static void free_plan(Plan* P) {
+  if (!P) return;
+  if (P->table_mem || P->work_mem) (void)hipDeviceSynchronize();
+  if (P->table_mem) (void)hipFree(P->table_mem);
+  if (P->work_mem) (void)hipFree(P->work_mem);
+  delete P;
+}
+
+// ---------------------------------------------------------------------------
+// execution
+
+template <typename T>
+static RootTable<T> rtab(const Plan* P, int d) {
+  RootTable<T> r;
+  r.lo = (const cpx<T>*)P->dd[d].zlo;
+  r.hi = (const cpx<T>*)P->dd[d].zhi;
+  r.N = P->dp[d].q * P->dp[d].m;
+  r.kbits = P->dd[d].kbits;
+  return r;
+}
+
+// rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L
+template <typename T>
+static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s) {
+  const int d = P->dims - 1;
+  const DimPlan& dp = P->dp[d];
+  const int A = P->A;
+  hipError_t e;
+  if (dp.variant == VAR_FUSED) {
+    FusedArgs<T> a{};
+    for (int i = 0; i < A; ++i) a.in[i] = in[i];
+    a.out = out;
+    a.in_stride = a.out_stride = dp.L;
+    a.nrows = nrows;
+    a.L = dp.L;
+    a.m = (int)dp.m;
+    a.q = (int)dp.q;
+    a.rows_per_block = dp.rows_per_block;
+    a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+    a.fd = dp.fd_m;
+    a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+    a.zqm = rtab<T>(P, d);
+    e = launch_fused1d<T>(a, dp.E_m, (int)dp.p, A, s);
+    if (e != hipSuccess) return hip_err(e, "fused1d launch");
+    return HDCONV_OK;
+  }
+  // inner form, blocks of D residues
+  const int64_t nblk = cdiv(dp.n, dp.D);
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int v0 = (int)(blk * dp.D);
+    const int D = (int)std::min<int64_t>(dp.D, dp.n - v0);
+    ColFwdArgs<T> k1{};
+    for (int i = 0; i < A; ++i) {
+      k1.in[i] = in[i];
+      k1.work[i] = (cpx<T>*)P->rowwork[i];
+    }
+    k1.in_stride = dp.L;
+    k1.nrows = nrows;
+    k1.L = dp.L;
+    k1.m = (int)dp.m;
+    k1.p = (int)dp.p;
+    k1.q = (int)dp.q;
+    k1.v0 = v0;
+    k1.D = D;
+    k1.S = dp.S;
+    k1.fd = dp.fd_p;
+    k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+    k1.zq = (const cpx<T>*)P->dd[d].zq;
+    e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
+    if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
+
+    RowConvArgs<T> k2{};
+    for (int i = 0; i < A; ++i) k2.work[i] = (cpx<T>*)P->rowwork[i];
+    k2.nrows = nrows * D * dp.p;
+    k2.m = (int)dp.m;
+    k2.p = (int)dp.p;
+    k2.n = (int)dp.n;
+    k2.v0 = v0;
+    k2.D = D;
+    k2.rows_per_block = dp.rows_per_block;
+    k2.qm = dp.q * dp.m;
+    k2.fd = dp.fd_m;
+    k2.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+    k2.zqm = rtab<T>(P, d);
+    e = launch_rows_conv<T>(k2, dp.E_m, A, s);
+    if (e != hipSuccess) return hip_err(e, "rows_conv launch");
+
+    ColBwdArgs<T> k3{};
+    k3.work = (const cpx<T>*)P->rowwork[0];
+    k3.out = out;
+    k3.acc = P->acc64;
+    k3.acc_mode = nblk == 1 ? ACC_WRITE : (blk == 0 ? ACC_FIRST : (blk == nblk - 1 ? ACC_LAST : ACC_ADD));
+    k3.out_stride = dp.L;
+    k3.nrows = nrows;
+    k3.L = dp.L;
+    k3.m = (int)dp.m;
+    k3.p = (int)dp.p;
+    k3.q = (int)dp.q;
+    k3.v0 = v0;
+    k3.D = D;
+    k3.S = dp.S;
+    k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+    k3.fd = dp.fd_p;
+    k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+    k3.zq = (const cpx<T>*)P->dd[d].zq;
+    e = launch_cols_bwd<T>(k3, dp.E_p, s);
+    if (e != hipSuccess) return hip_err(e, "cols_bwd launch");
+  }
+  return HDCONV_OK;
+}
+
+template <typename T>
+static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t s) {
+  const int A = P->A;
+  hipError_t e;
+  int64_t Le[3];
+  for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
+  const cpx<T>* cur[kMaxA];
+  cpx<T>* final_out = (cpx<T>*)out_v;
+  if (P->method == HDCONV_METHOD_EXPLICIT) {
+    for (int a = 0; a < A; ++a) {
+      BoxCopyArgs<T> b{};
+      b.src = (const cpx<T>*)inputs[a];
+      b.dst = (cpx<T>*)P->pad_in[a];
+      for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
+      for (int d = 0; d < P->dims; ++d) {
+        b.L[3 - P->dims + d] = P->L[d];
+        b.N[3 - P->dims + d] = P->npad[d];
+      }
+      b.pad = 1;
+      e = launch_box_copy<T>(b, s);
+      if (e != hipSuccess) return hip_err(e, "pad launch");
+      cur[a] = (const cpx<T>*)P->pad_in[a];
+    }
+    final_out = (cpx<T>*)P->pad_in[0];
+  } else {
+    for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)inputs[a];
+  }
+  // outer dimensions, forward
+  int64_t nb = 1;
+  for (int d = 0; d + 1 < P->dims; ++d) {
+    const DimPlan& dp = P->dp[d];
+    int64_t rest = 1;
+    for (int k = d + 1; k < P->dims; ++k) rest *= Le[k];
+    OuterFwdArgs<T> o{};
+    for (int a = 0; a < A; ++a) {
+      o.in[a] = cur[a];
+      o.out[a] = (cpx<T>*)P->lvl[d][a];
+    }
+    o.nb = nb;
+    o.in_bstride = Le[d] * rest;
+    o.R = rest;
+    o.L = Le[d];
+    o.m = (int)dp.m;
+    o.q = (int)dp.q;
+    o.r0 = 0;
+    o.D = (int)dp.q;
+    o.S = dp.S;
+    o.fd = dp.fd_m;
+    o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+    o.zqm = rtab<T>(P, d);
+    e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, A, s);
+    if (e != hipSuccess) return hip_err(e, "outer_fwd launch");
+    for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
+    nb *= dp.q * dp.m;
+  }
+  // innermost rows
+  {
+    cpx<T>* rows_out = P->dims == 1 ? final_out : (cpx<T>*)P->lvl[P->dims - 2][0];
+    int rc = run_rows<T>(P, cur, rows_out, nb, s);
+    if (rc != HDCONV_OK) return rc;
+  }
+  // outer dimensions, backward
+  for (int d = P->dims - 2; d >= 0; --d) {
+    const DimPlan& dp = P->dp[d];
+    nb /= dp.q * dp.m;
+    int64_t rest = 1;
+    for (int k = d + 1; k < P->dims; ++k) rest *= Le[k];
+    OuterBwdArgs<T> o{};
+    o.y = (const cpx<T>*)P->lvl[d][0];
+    o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
+    o.acc = nullptr;
+    o.acc_mode = ACC_WRITE;
+    o.nb = nb;
+    o.out_bstride = Le[d] * rest;
+    o.R = rest;
+    o.L = Le[d];
+    o.m = (int)dp.m;
+    o.q = (int)dp.q;
+    o.r0 = 0;
+    o.D = (int)dp.q;
+    o.S = dp.S;
+    o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+    o.fd = dp.fd_m;
+    o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+    o.zqm = rtab<T>(P, d);
+    e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
+    if (e != hipSuccess) return hip_err(e, "outer_bwd launch");
+  }
+  if (P->method == HDCONV_METHOD_EXPLICIT) {
+    BoxCopyArgs<T> b{};
+    b.src = (const cpx<T>*)P->pad_in[0];
+    b.dst = (cpx<T>*)out_v;
+    for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
+    for (int d = 0; d < P->dims; ++d) {
+      b.L[3 - P->dims + d] = P->L[d];
+      b.N[3 - P->dims + d] = P->npad[d];
+    }
+    b.pad = 0;
+    e = launch_box_copy<T>(b, s);
+    if (e != hipSuccess) return hip_err(e, "truncate launch");
+  }
+  return HDCONV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+void hdconv_options_init(hdconv_options* opt) {
+  if (opt) memset(opt, 0, sizeof(*opt));
+}
+
+const char* hdconv_version(void) { return "hdconv 0.1 (gfx950)"; }
+
+int hdconv_last_error(char* msg, size_t cap) {
+  if (msg && cap) {
+    strncpy(msg, g_err_msg, cap - 1);
+    msg[cap - 1] = 0;
+  }
+  return g_err_code;
+}
+
+int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner, hdconv_dim_info_t* out) {
+  clear_err();
+  if (!out) return set_err(HDCONV_EINVAL, "out is NULL");
+  if (L < 1 || M < 1 || m < 1 || p_min < 0) return set_err(HDCONV_EINVAL, "need L, M, m >= 1 and p_min >= 0");
+  Geometry g = geometry(L, M, m, p_min, force_inner != 0);
+  memset(out, 0, sizeof(*out));
+  out->L = L;
+  out->M = M;
+  out->m = g.m;
+  out->p = g.p;
+  out->n = g.n;
+  out->q = g.q;
+  out->D = g.n;
+  out->variant = g.inner ? HDCONV_VARIANT_MULTIPASS : HDCONV_VARIANT_FUSED;
+  return HDCONV_OK;
+}
+
+void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                     const hdconv_options* opt) {
+  clear_err();
+  if (!L || !M) {
+    set_err(HDCONV_EINVAL, "L and M must not be NULL");
+    return nullptr;
+  }
+  if (dims < 1 || dims > 3) {
+    set_err(HDCONV_EINVAL, "dims must be 1, 2 or 3 (got %d)", dims);
+    return nullptr;
+  }
+  if (A < 2 || A > 3) {
+    set_err(HDCONV_EUNSUPPORTED, "A must be 2 or 3 (got %d)", A);
+    return nullptr;
+  }
+  if (B != 1) {
+    set_err(HDCONV_EUNSUPPORTED, "only B = 1 (product of the inputs) is supported (got %d)", B);
+    return nullptr;
+  }
+  if (dtype != HDCONV_C64 && dtype != HDCONV_C128) {
+    set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128 (got %d)", dtype);
+    return nullptr;
+  }
+  for (int d = 0; d < dims; ++d) {
+    if (L[d] < 1 || L[d] > (int64_t(1) << 31)) {
+      set_err(HDCONV_EINVAL, "L[%d] = %lld out of range", d, (long long)L[d]);
+      return nullptr;
+    }
+    if (M[d] < (int64_t)A * (L[d] - 1) + 1) {
+      set_err(HDCONV_EINVAL, "M[%d] = %lld is below A(L-1)+1 = %lld, so the product would alias", d,
+              (long long)M[d], (long long)(A * (L[d] - 1) + 1));
+      return nullptr;
+    }
+  }
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) {
+    set_err(HDCONV_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  P->dims = dims;
+  P->A = A;
+  P->B = B;
+  P->dtype = dtype;
+  P->method = (opt && opt->method == HDCONV_METHOD_EXPLICIT) ? HDCONV_METHOD_EXPLICIT : HDCONV_METHOD_HYBRID;
+  P->flags = opt ? opt->flags : 0;
+  P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
+  for (int d = 0; d < dims; ++d) {
+    P->L[d] = L[d];
+    P->M[d] = M[d];
+    if (P->method == HDCONV_METHOD_EXPLICIT) P->npad[d] = std::max<int64_t>(8, next_fft_size(M[d]));
+  }
+  int rc = build_dims(P, opt);
+  if (rc != HDCONV_OK) {
+    free_plan(P);
+    return nullptr;
+  }
+  if (!P->host_only) {
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+      set_err(HDCONV_ENODEV, "no HIP device available (%s)", hipGetErrorString(e));
+      free_plan(P);
+      return nullptr;
+    }
+    e = hipGetDevice(&P->device);
+    if (e != hipSuccess) {
+      hip_err(e, "hipGetDevice");
+      free_plan(P);
+      return nullptr;
+    }
+  }
+  if ((rc = alloc_tables(P)) != HDCONV_OK || (rc = alloc_workspace(P)) != HDCONV_OK) {
+    free_plan(P);
+    return nullptr;
+  }
+  plan_traffic(P, &P->launches);
+  return P;
+}
+
+void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype) {
+  return hdconv_plan_ex(L, M, A, B, dims, dtype, nullptr);
+}
+
+int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
+  clear_err();
+  if (!plan || !out) return set_err(HDCONV_EINVAL, "plan and out must not be NULL");
+  const Plan* P = (const Plan*)plan;
+  memset(out, 0, sizeof(*out));
+  out->dims = P->dims;
+  out->A = P->A;
+  out->B = P->B;
+  out->dtype = P->dtype;
+  out->method = P->method;
+  double ltot = 1;
+  for (int d = 0; d < 3; ++d) {
+    out->L[d] = d < P->dims ? P->L[d] : 0;
+    out->M[d] = d < P->dims ? P->M[d] : 0;
+    out->npad[d] = P->npad[d];
+    if (d >= P->dims) continue;
+    ltot *= (double)P->L[d];
+    const DimPlan& dp = P->dp[d];
+    hdconv_dim_info_t& di = out->dim[d];
+    di.L = dp.L;
+    di.M = dp.M;
+    di.m = dp.m;
+    di.p = dp.p;
+    di.n = dp.n;
+    di.q = dp.q;
+    di.D = dp.D;
+    di.variant = dp.variant;
+    di.E_m = dp.E_m;
+    di.E_p = dp.E_p;
+    di.S = dp.S;
+    di.rows_per_block = dp.rows_per_block;
+  }
+  out->workspace_bytes = P->work_bytes;
+  out->table_bytes = P->table_bytes;
+  out->compulsory_bytes = (double)(P->A + P->B) * ltot * 2.0 * tbytes_of(P->dtype);
+  out->traffic_bytes = plan_traffic(P, &out->launches);
+  return HDCONV_OK;
+}
+
+int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, void* stream) {
+  clear_err();
+  if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
+  Plan* P = (Plan*)plan;
+  if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
+  size_t bytes = 2 * (size_t)tbytes_of(P->dtype);
+  for (int d = 0; d < P->dims; ++d) bytes *= (size_t)P->L[d];
+  for (int a = 0; a < P->A; ++a)
+    if (!inputs[a]) return set_err(HDCONV_EINVAL, "inputs[%d] is NULL", a);
+  if (!outputs[0]) return set_err(HDCONV_EINVAL, "outputs[0] is NULL");
+  const char* o = (const char*)outputs[0];
+  for (int a = 0; a < P->A; ++a) {
+    const char* i = (const char*)inputs[a];
+    if (i != o && i < o + bytes && o < i + bytes)
+      return set_err(HDCONV_EINVAL, "outputs[0] partially overlaps inputs[%d]", a);
+  }
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != P->device) return set_err(HDCONV_EINVAL, "plan belongs to device %d, current device is %d", P->device, cur);
+  hipStream_t s = (hipStream_t)stream;
+  if (P->dtype == HDCONV_C64) return run_plan<float>(P, inputs, outputs[0], s);
+  return run_plan<double>(P, inputs, outputs[0], s);
+}
+
+void hdconv_destroy(void* plan) { free_plan((Plan*)plan); }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// hd_common.hpp -- complex arithmetic and small helpers shared by the HIP
+// kernels of the hybrid-dealiasing engine (device and host).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
+  return mk(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) {
+  return mk(a.x - b.x, a.y - b.y);
+}
+// a * b
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __host__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) {
+  return mk(a.x * s, a.y * s);
+}
+// a * (S i), S = +1 or -1
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+  return S > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+// a * w when S = +1, a * conj(w) when S = -1
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> cmul_s(cpx<T> a, cpx<T> w) {
+  return S > 0 ? cmul(a, w) : cmulc(a, w);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> czero() {
+  return mk(T(0), T(0));
+}
+
+// Two-level table of the powers of one root of unity:
+//   zeta_N^e = lo[e & (K-1)] * hi[e >> kbits],  0 <= e < N,  K = 2^kbits.
+// Both halves are rounded from FP64 values, so an entry is within about two
+// ulps of the exact root.
+template <typename T>
+struct RootTable {
+  const cpx<T>* lo;
+  const cpx<T>* hi;
+  int64_t N;
+  int kbits;
+  __device__ __forceinline__ cpx<T> get(int64_t e) const {
+    cpx<T> a = lo[e & ((int64_t(1) << kbits) - 1)];
+    int64_t h = e >> kbits;
+    return h == 0 ? a : cmul(a, hi[h]);
+  }
+  // zeta_N^{(a*b) mod N} for non-negative a, b with a*b < 2^63
+  __device__ __forceinline__ cpx<T> pow_prod(int64_t a, int64_t b) const {
+    return get((int64_t)((uint64_t)(a * b) % (uint64_t)N));
+  }
+};
+
+}  // namespace hd

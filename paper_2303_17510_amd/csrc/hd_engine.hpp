@@ -1,0 +1,162 @@
+// hd_engine.hpp -- argument blocks and launchers of the hybrid-dealiasing
+// HIP kernels.  Host code fills these structs from a plan; the kernels live in
+// hd_kernels.hip.
+//
+// Notation (Murasko & Bowman, arXiv 2303.17510): a dimension of length L is
+// padded to at least M; m is the subtransform size, the input is explicitly
+// padded to p*m and implicitly to q*m; zeta_N = exp(2 pi i/N).
+//  * direct form (Algorithms 3-6, p <= 2): q residues r, each an m-point
+//    FFT of W_s = sum_t zeta_{qm}^{r(tm+s)} f_{tm+s};
+//  * inner form (Sec. 6.1, q = n p): n residues v of size p*m; the sum over t
+//    becomes p-point DFTs of zeta_q^{vt} f_{tm+s}, then zeta_{qm}^{(un+v)s}
+//    and an m-point FFT per u.
+#pragma once
+#include "hd_common.hpp"
+#include "hd_fft.hpp"
+
+namespace hd {
+
+constexpr int kMaxA = 3;
+
+// Accumulation of one residue block into the output (blocks of D residues):
+//   ACC_WRITE : out  = sum * scale              (single block)
+//   ACC_FIRST : acc  = sum                      (first of several blocks)
+//   ACC_ADD   : acc += sum
+//   ACC_LAST  : out  = (acc + sum) * scale      (last block)
+// acc is an FP64 buffer laid out like out.
+enum AccMode { ACC_WRITE = 0, ACC_FIRST = 1, ACC_ADD = 2, ACC_LAST = 3 };
+
+// Whole 1D convolutions along contiguous rows, direct form with p <= 2.
+// One group of G lanes per row; rows_per_block rows per workgroup.
+template <typename T>
+struct FusedArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out;
+  int64_t in_stride, out_stride;  // elements between consecutive rows
+  int64_t nrows;
+  int64_t L;
+  int m, q;
+  int rows_per_block;
+  T scale;  // 1/(q m)
+  FftDesc fd;
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;  // powers of zeta_{qm}
+};
+
+// Inner form, pass 1: for a tile of S consecutive columns s of the p x m
+// view f_{tm+s} of each row, the p-point DFT over t of zeta_q^{vt} f_{tm+s}
+// for residues v0 .. v0+D-1.  Output work[a][(row D + dv) p + u][s].
+template <typename T>
+struct ColFwdArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* work[kMaxA];
+  int64_t in_stride;
+  int64_t nrows;
+  int64_t L;
+  int m, p, q, v0, D, S;
+  FftDesc fd;  // p points
+  const cpx<T>* fft_tw;
+  const cpx<T>* zq;  // zeta_q^k, k < q
+};
+
+// Inner form, pass 2: per row (v,u): pre-twiddle zeta_{qm}^{(un+v)s}, m-point
+// FFT of each input, pointwise product, inverse FFT, post-twiddle; the result
+// replaces work[0]'s row.
+template <typename T>
+struct RowConvArgs {
+  cpx<T>* work[kMaxA];
+  int64_t nrows;  // rows of the work buffer (= batch * D * p)
+  int m, p, n, v0, D;
+  int rows_per_block;
+  int64_t qm;
+  FftDesc fd;  // m points
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;
+};
+
+// Inner form, pass 3: p-point inverse DFT over u of each column, times
+// zeta_q^{-vt}, accumulated over the block's residues, scaled by 1/(qm) and
+// truncated to L.
+template <typename T>
+struct ColBwdArgs {
+  const cpx<T>* work;
+  cpx<T>* out;
+  double* acc;  // FP64 accumulator (interleaved), for multi-block plans
+  int acc_mode;
+  int64_t out_stride;
+  int64_t nrows;
+  int64_t L;
+  int m, p, q, v0, D, S;
+  T scale;
+  FftDesc fd;  // p points
+  const cpx<T>* fft_tw;
+  const cpx<T>* zq;
+};
+
+// Outer dimension of a multidimensional convolution (Sec. 5), direct form:
+// data viewed as [nb][L][R] (R contiguous columns).  Forward writes, for
+// residues r0 .. r0+D-1, out[a][((b D + dr) m + l) R + c].
+template <typename T>
+struct OuterFwdArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out[kMaxA];
+  int64_t nb, in_bstride, R;
+  int64_t L;
+  int m, q, r0, D, S;
+  FftDesc fd;
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;
+};
+
+template <typename T>
+struct OuterBwdArgs {
+  const cpx<T>* y;  // [nb][D][m][R]
+  cpx<T>* out;      // out[b * out_bstride + x R + c], x < L
+  double* acc;
+  int acc_mode;
+  int64_t nb, out_bstride, R;
+  int64_t L;
+  int m, q, r0, D, S;
+  T scale;
+  FftDesc fd;
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;
+};
+
+// Zero padding / truncation copies between a dense box L[0..2] and a dense
+// box N[0..2] (the explicit method's materialised padding).
+template <typename T>
+struct BoxCopyArgs {
+  const cpx<T>* src;
+  cpx<T>* dst;
+  int64_t L[3], N[3];  // leading unused extents are 1
+  int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
+};
+
+// Launchers (return the launch status).  E, P and A select the template
+// instance; the host checks that the plan's geometry fits before calling.
+template <typename T>
+hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_t s);
+template <typename T>
+hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s);
+template <typename T>
+hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s);
+template <typename T>
+hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s);
+template <typename T>
+hipError_t launch_outer_fwd(const OuterFwdArgs<T>& a, int E, int P, int A, hipStream_t s);
+template <typename T>
+hipError_t launch_outer_bwd(const OuterBwdArgs<T>& a, int E, int P, hipStream_t s);
+template <typename T>
+hipError_t launch_box_copy(const BoxCopyArgs<T>& a, hipStream_t s);
+
+// LDS bytes each launcher requests (host-side sizing and validation).
+size_t lds_fused1d(int m, int rows_per_block, int tbytes);
+size_t lds_cols(int p, int S, int tbytes);
+size_t lds_rows(int m, int rows_per_block, int tbytes);
+size_t lds_outer(int m, int S, int tbytes);
+
+// True when the radix set of d fits the template instance E.
+bool fft_fits(const FftDesc& d, int E);
+
+}  // namespace hd

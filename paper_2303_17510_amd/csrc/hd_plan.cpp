@@ -1,0 +1,279 @@
+// hd_plan.cpp -- geometry rules and kernel-shape choices (host only).
+#include "hd_plan.hpp"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace hd {
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+Geometry geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inner) {
+  Geometry g{};
+  g.m = m;
+  g.p = std::max(cdiv(L, m), p_min);
+  if (g.p <= 2 && !force_inner) {
+    // Algorithm 1, p = 1 or 2: q = n = ceil(M/m) residues of size m
+    g.n = g.q = cdiv(M, m);
+    g.inner = false;
+  } else {
+    // Sec. 6.1: q is the smallest multiple of p with q m >= M
+    g.n = cdiv(M, g.p * m);
+    g.q = g.n * g.p;
+    g.inner = true;
+  }
+  return g;
+}
+
+bool fft_size_ok(int64_t N) {
+  if (N < 1) return false;
+  if ((N & (N - 1)) == 0) return true;
+  if (N % 3 == 0) {
+    int64_t t = N / 3;
+    return (t & (t - 1)) == 0 && t >= 8;
+  }
+  return false;
+}
+
+int64_t next_fft_size(int64_t n) {
+  int64_t best = 1;
+  while (best < n) best <<= 1;
+  for (int64_t t = 8; 3 * t < best; t <<= 1)
+    if (3 * t >= n) return 3 * t;
+  return best;
+}
+
+int64_t next_col_size(int64_t n) { return next_fft_size(n); }
+
+bool make_fft_desc(int64_t N, int E, FftDesc* d) {
+  *d = FftDesc{};
+  if (N < 1 || E < 1 || N % E != 0 || N / E > kMaxThreads) return false;
+  d->N = (int)N;
+  d->G = (int)(N / E);
+  int64_t rem = N;
+  int st = 0;
+  while (rem % 3 == 0) {
+    if (E % 3 != 0 || st >= 12) return false;
+    d->radix[st++] = 3;
+    rem /= 3;
+  }
+  int rmax = 1;
+  while (rmax < 16 && E % (rmax * 2) == 0) rmax *= 2;
+  while (rem > 1) {
+    if (rem & 1) return false;
+    int r = rmax;
+    while (rem % r != 0) r /= 2;
+    if (r < 2 || st >= 12) return false;
+    d->radix[st++] = r;
+    rem /= r;
+  }
+  d->nst = st;
+  return true;
+}
+
+static int pow2_floor(int64_t x) {
+  int r = 1;
+  while ((int64_t)r * 2 <= x) r *= 2;
+  return r;
+}
+
+// Points per lane of a row transform: enough that a row of m points needs at
+// most kMaxThreads lanes, few enough to stay in registers.
+static bool pick_e_row(int64_t m, bool fused, int tbytes, int* E) {
+  (void)tbytes;
+  if (m % 3 == 0) {
+    *E = 24;
+    return m % 24 == 0 && m / 24 <= kMaxThreads;
+  }
+  if (fused) {
+    *E = m <= 2048 ? 8 : (m <= 8192 ? 16 : 32);
+  } else {
+    *E = m < 16 ? 8 : (m <= 8192 ? 16 : 32);
+  }
+  return m >= *E && m / *E <= kMaxThreads;
+}
+
+static bool pick_e_col(int64_t p, int* E) {
+  if (p % 3 == 0) {
+    *E = 24;
+    return p % 24 == 0;
+  }
+  if (p <= 8) {
+    *E = (int)p;
+    return p == 1 || p == 2 || p == 4 || p == 8;
+  }
+  *E = (p >= 256) ? 16 : 8;
+  return true;
+}
+
+bool finish_dim(DimPlan* dp, int tbytes, std::string* why) {
+  const int cb = 2 * tbytes;  // bytes per complex word
+  auto fail = [&](const char* s) {
+    if (why) *why = s;
+    return false;
+  };
+  if (dp->m < 1 || dp->p < 1 || dp->q < dp->p || dp->q * dp->m < dp->M)
+    return fail("invalid geometry: need q >= p and q m >= M");
+  if (dp->p * dp->m < dp->L) return fail("invalid geometry: need p m >= L");
+  if (!fft_size_ok(dp->m)) return fail("m must be 2^a or 3*2^a (a >= 3)");
+  if (dp->D < 1) dp->D = dp->n;
+  if (dp->D > dp->n) return fail("D exceeds the number of residues");
+  switch (dp->variant) {
+    case VAR_FUSED: {
+      if (dp->p > 2) return fail("fused variant needs p <= 2");
+      if (dp->m > kMaxFusedM) return fail("fused variant needs m <= 8192");
+      if (dp->D != dp->n) return fail("fused variant processes all residues");
+      if (!pick_e_row(dp->m, true, tbytes, &dp->E_m)) return fail("unsupported m for the fused variant");
+      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
+      int rpb = std::max(1, 256 / dp->fd_m.G);
+      while (rpb > 1 && (size_t)rpb * (dp->m + (dp->m >> 4)) * cb > 65536) rpb /= 2;
+      if ((size_t)rpb * (dp->m + (dp->m >> 4)) * cb > kLdsBudget) return fail("row does not fit in LDS");
+      dp->rows_per_block = rpb;
+      return true;
+    }
+    case VAR_MULTI: {
+      if (dp->q != dp->n * dp->p) return fail("inner form needs q = n p");
+      if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 16384");
+      if (dp->p > kMaxColP || !fft_size_ok(dp->p)) return fail("unsupported p for the column passes");
+      if (!pick_e_row(dp->m, false, tbytes, &dp->E_m)) return fail("unsupported m for the row pass");
+      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
+      int rpb = std::max(1, 256 / dp->fd_m.G);
+      while (rpb > 1 && (size_t)rpb * (dp->m + (dp->m >> 4)) * cb > 65536) rpb /= 2;
+      if ((size_t)rpb * (dp->m + (dp->m >> 4)) * cb > kLdsBudget) return fail("row does not fit in LDS");
+      dp->rows_per_block = rpb;
+      if (!pick_e_col(dp->p, &dp->E_p)) return fail("unsupported p for the column passes");
+      if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p");
+      int S = 64;
+      while (S > 1 && (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || (size_t)dp->p * S * cb > 65536))
+        S /= 2;
+      if (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || (size_t)dp->p * S * cb > kLdsBudget)
+        return fail("column tile does not fit");
+      dp->S = S;
+      return true;
+    }
+    case VAR_OUTER: {
+      if (dp->p > 2) return fail("outer variant needs p <= 2");
+      if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
+      if (dp->D != dp->n) return fail("outer variant processes all residues");
+      if (dp->m % 3 == 0) {
+        dp->E_m = 24;
+        if (dp->m % 24) return fail("unsupported m");
+      } else {
+        dp->E_m = dp->m < 16 ? 8 : (dp->m <= 1024 ? 16 : 32);
+        if (dp->m < 8) return fail("outer variant needs m >= 8");
+      }
+      if (dp->m / dp->E_m > kMaxThreads) return fail("outer column too long");
+      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
+      int S = pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G));
+      S = std::min(S, 64);
+      while (S > 1 && (size_t)dp->m * S * cb > 128 * 1024) S /= 2;
+      if ((size_t)dp->m * S * cb > kLdsBudget) return fail("outer column does not fit in LDS");
+      dp->S = S;
+      return true;
+    }
+    default:
+      return fail("unknown variant");
+  }
+}
+
+static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min, int variant) {
+  Geometry g = geometry(L, M, m, p_min, variant == VAR_MULTI);
+  if ((variant == VAR_FUSED || variant == VAR_OUTER) && g.inner) return false;
+  dp->L = L;
+  dp->M = M;
+  dp->m = g.m;
+  dp->p = g.p;
+  dp->n = g.n;
+  dp->q = g.q;
+  dp->D = g.n;
+  dp->variant = variant;
+  return true;
+}
+
+bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPlan* dp, std::string* why) {
+  (void)A;
+  std::string w;
+  if (contiguous) {
+    int64_t m = std::max<int64_t>(8, next_fft_size(L));
+    if (m <= kMaxFusedM && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, tbytes, &w)) return true;
+    // large rows: inner form with m near 8192 (c64) / 4096 (c128)
+    int64_t mm = tbytes == 4 ? 8192 : 4096;
+    while (mm > 16 && mm / 2 >= L) mm /= 2;
+    for (; mm <= kMaxRowM; mm *= 2) {
+      int64_t p = next_col_size(cdiv(L, mm));
+      if (p > kMaxColP) continue;
+      if (set_geom(dp, L, M, mm, p, VAR_MULTI) && finish_dim(dp, tbytes, &w)) return true;
+    }
+    if (why) *why = "no supported plan for this length: " + w;
+    return false;
+  }
+  int64_t m = std::max<int64_t>(8, next_fft_size(L));
+  if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, tbytes, &w)) return true;
+  m = std::max<int64_t>(8, next_fft_size(cdiv(L, 2)));
+  if (set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, tbytes, &w)) return true;
+  if (why) *why = "no supported plan for this outer length: " + w;
+  return false;
+}
+
+std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous) {
+  (void)A;
+  std::vector<DimPlan> out;
+  std::vector<int64_t> sizes;
+  for (int64_t s = 8; s <= kMaxRowM; s <<= 1) {
+    sizes.push_back(s);
+    if (s >= 8 && 3 * s <= kMaxRowM) sizes.push_back(3 * s);
+  }
+  std::sort(sizes.begin(), sizes.end());
+  for (int64_t m : sizes) {
+    if (m > next_fft_size(M) && m > 8) break;
+    DimPlan dp;
+    std::string w;
+    if (contiguous) {
+      if (set_geom(&dp, L, M, m, 0, VAR_FUSED) && finish_dim(&dp, tbytes, &w)) out.push_back(dp);
+      DimPlan d2;
+      int64_t p = next_col_size(cdiv(L, m));
+      if (m >= 16 && p <= kMaxColP && set_geom(&d2, L, M, m, p, VAR_MULTI) && finish_dim(&d2, tbytes, &w))
+        out.push_back(d2);
+    } else {
+      if (set_geom(&dp, L, M, m, 0, VAR_OUTER) && finish_dim(&dp, tbytes, &w)) out.push_back(dp);
+    }
+  }
+  return out;
+}
+
+void root(int64_t N, int64_t e, double* re, double* im) {
+  e %= N;
+  if (e < 0) e += N;
+  // exact octant symmetries first, then one long-double evaluation
+  const long double pi = 3.141592653589793238462643383279502884L;
+  long double a = 2.0L * pi * (long double)e / (long double)N;
+  *re = (double)cosl(a);
+  *im = (double)sinl(a);
+  if (4 * e == N) { *re = 0.0; *im = 1.0; }
+  if (2 * e == N) { *re = -1.0; *im = 0.0; }
+  if (4 * e == 3 * N) { *re = 0.0; *im = -1.0; }
+  if (e == 0) { *re = 1.0; *im = 0.0; }
+}
+
+std::vector<double> stage_twiddles(FftDesc* d) {
+  std::vector<double> v;
+  int64_t Ns = 1;
+  for (int st = 0; st < d->nst; ++st) {
+    const int R = d->radix[st];
+    d->twoff[st] = (int)(v.size() / 2);
+    if (Ns > 1) {
+      for (int64_t k = 0; k < Ns; ++k)
+        for (int i = 1; i < R; ++i) {
+          double re, im;
+          root(Ns * R, k * i, &re, &im);
+          v.push_back(re);
+          v.push_back(im);
+        }
+    }
+    Ns *= R;
+  }
+  return v;
+}
+
+}  // namespace hd

@@ -1,0 +1,77 @@
+// hd_plan.hpp -- host-side planning of a hybrid-dealiased convolution.
+// Integer logic only; no device calls (usable without a GPU).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "hd_fft.hpp"
+
+namespace hd {
+
+enum Variant {
+  VAR_AUTO = 0,
+  VAR_FUSED = 1,  // whole 1D convolution per row, direct form (p <= 2)
+  VAR_MULTI = 2,  // inner-loop form, three passes over HBM
+  VAR_OUTER = 3   // outer dimension of a multidimensional convolution, direct form
+};
+
+// Limits of the kernels (see hd_kernels.hip).
+constexpr int kMaxThreads = 512;
+constexpr int64_t kMaxFusedM = 8192;   // m of the fused and outer kernels
+constexpr int64_t kMaxRowM = 16384;    // m of the row-convolution pass
+constexpr int64_t kMaxColP = 4096;     // p of the column passes
+constexpr size_t kLdsBudget = 160 * 1024;
+
+struct DimPlan {
+  int64_t L = 0, M = 0;       // lengths the engine sees in this dimension
+  int64_t m = 0, p = 0, n = 0, q = 0, D = 0;
+  int variant = VAR_AUTO;
+  FftDesc fd_m{};             // m-point transform
+  int E_m = 0;
+  FftDesc fd_p{};             // p-point transform (inner form)
+  int E_p = 0;
+  int S = 0;                  // columns per workgroup (column / outer kernels)
+  int rows_per_block = 0;     // rows per workgroup (fused / row kernels)
+};
+
+// Paper's geometry rules for a given m (Algorithm 1, Sec. 2.1, Sec. 6.1):
+//   p = ceil(L/m) (or the caller's larger p_min), then
+//   p <= 2 (direct):  q = n = ceil(M/m), residues of size m;
+//   p  > 2 (inner):   n = ceil(M/(p m)), q = n p, residues of size p m.
+struct Geometry {
+  int64_t m, p, n, q;
+  bool inner;
+};
+Geometry geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inner);
+
+bool fft_size_ok(int64_t N);            // 2^a, or 3 * 2^a with a >= 3
+int64_t next_fft_size(int64_t n);       // smallest size >= n accepted by fft_size_ok
+int64_t next_col_size(int64_t n);       // smallest p >= n the column passes accept
+
+// Factor N into stage radices that divide E (largest first; a factor 3 first).
+// Returns false when impossible.
+bool make_fft_desc(int64_t N, int E, FftDesc* d);
+
+// Choose template widths, tiles and rows per block for a dimension whose
+// (m, p, n, q, variant) are set.  tbytes = sizeof(real).  On failure returns
+// false with a reason.
+bool finish_dim(DimPlan* dp, int tbytes, std::string* why);
+
+// Default (heuristic) choice for one dimension.  `contiguous` marks the
+// innermost dimension (rows), others are outer dimensions.
+bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPlan* dp,
+                std::string* why);
+
+// Candidates for the autotuner: every supported (m, variant) of a dimension.
+std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous);
+
+// FP64 stage twiddle tables of a descriptor: fills d->twoff and returns the
+// values (interleaved re, im) of w_{Ns R}^{k i}, k < Ns, 1 <= i < R.
+std::vector<double> stage_twiddles(FftDesc* d);
+
+// Roots of unity in FP64 (long double internally), zeta_N^e for e in [0, N).
+void root(int64_t N, int64_t e, double* re, double* im);
+
+}  // namespace hd

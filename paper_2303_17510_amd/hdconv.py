@@ -1,0 +1,165 @@
+"""Python front end of libhdconv: plans and execution on torch tensors.
+
+Only marshalling lives here.  Tensors supply device pointers, the current
+torch stream supplies the hipStream_t, and the library's kernels do all the
+arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+from . import _lib as _L
+
+_METHODS = {"auto": _L.METHOD_AUTO, "hybrid": _L.METHOD_HYBRID, "explicit": _L.METHOD_EXPLICIT}
+_VARIANTS = {None: 0, "auto": 0, "fused": 1, "multipass": 2, "outer": 3}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(dtype) -> int:
+    torch = _torch()
+    if dtype in (torch.complex64, "c64", "complex64"):
+        return _L.C64
+    if dtype in (torch.complex128, "c128", "complex128"):
+        return _L.C128
+    raise ValueError("dtype must be complex64 or complex128")
+
+
+def _tup(x, dims, default=0):
+    if x is None:
+        return (default,) * dims
+    if isinstance(x, int):
+        return (x,) * dims
+    x = tuple(int(v) for v in x)
+    if len(x) != dims:
+        raise ValueError("expected %d values" % dims)
+    return x
+
+
+def geometry(L: int, M: int, m: int, p_min: int = 0, force_inner: bool = False) -> dict:
+    """The paper's (p, n, q) for one dimension and a given m (host only)."""
+    out = _L.DimInfo()
+    _L.check(_L.lib().hdconv_geometry(int(L), int(M), int(m), int(p_min), int(bool(force_inner)),
+                                       ctypes.byref(out)))
+    return {"L": out.L, "M": out.M, "m": out.m, "p": out.p, "n": out.n, "q": out.q,
+            "variant": _L.VARIANT_NAMES[out.variant]}
+
+
+class Plan:
+    """A planned convolution of ``A`` inputs of shape ``L`` padded to ``M``.
+
+    ``method``: "hybrid" (default) or "explicit" (materialised zero padding).
+    ``m``, ``p``, ``D``, ``variant`` force per-dimension choices (None: the
+    planner decides).  ``host_only`` plans geometry without device memory.
+    """
+
+    def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
+                 dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
+                 host_only: bool = False):
+        L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
+        dims = len(L)
+        if M is None:
+            M = tuple(A * l for l in L)
+        M = (int(M),) if isinstance(M, int) else tuple(int(v) for v in M)
+        self.L, self.M, self.A, self.B, self.dims = L, M, A, B, dims
+        self.dtype_code = dtype_code(dtype)
+        opt = _L.Options()
+        _L.lib().hdconv_options_init(ctypes.byref(opt))
+        opt.method = _METHODS[method]
+        opt.flags = _L.PLAN_HOST_ONLY if host_only else 0
+        if dims > 3 or len(M) != dims:
+            raise ValueError("L and M need 1 to 3 matching dimensions")
+        for d, v in enumerate(_tup(m, dims)):
+            opt.m[d] = v
+        for d, v in enumerate(_tup(p, dims)):
+            opt.p[d] = v
+        for d, v in enumerate(_tup(D, dims)):
+            opt.D[d] = v
+        vs = variant if isinstance(variant, (list, tuple)) else [variant] * dims
+        for d, v in enumerate(vs):
+            opt.variant[d] = _VARIANTS[v]
+        Ls = (ctypes.c_int64 * 3)(*(list(L) + [1] * (3 - dims)))
+        Ms = (ctypes.c_int64 * 3)(*(list(M) + [1] * (3 - dims)))
+        h = _L.lib().hdconv_plan_ex(Ls, Ms, A, B, dims, self.dtype_code, ctypes.byref(opt))
+        if not h:
+            code, msg = _L.last_error()
+            raise _L.HdconvError(code, msg)
+        self._h = h
+        self.host_only = host_only
+
+    # -- info -----------------------------------------------------------
+    def info(self) -> dict:
+        out = _L.PlanInfo()
+        _L.check(_L.lib().hdconv_plan_info(self._h, ctypes.byref(out)))
+        dims = []
+        for d in range(out.dims):
+            di = out.dim[d]
+            dims.append({"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
+                         "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p,
+                         "S": di.S, "rows_per_block": di.rows_per_block})
+        return {"dims": dims, "A": out.A, "B": out.B, "dtype": "c64" if out.dtype == 0 else "c128",
+                "method": {1: "hybrid", 2: "explicit"}.get(out.method, "auto"),
+                "npad": list(out.npad)[: out.dims], "workspace_bytes": out.workspace_bytes,
+                "table_bytes": out.table_bytes, "compulsory_bytes": out.compulsory_bytes,
+                "traffic_bytes": out.traffic_bytes, "launches": out.launches}
+
+    # -- execution --------------------------------------------------------
+    def _check_tensor(self, t, name):
+        torch = _torch()
+        want = torch.complex64 if self.dtype_code == _L.C64 else torch.complex128
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+        if t.dtype != want or tuple(t.shape) != self.L or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
+                             % (name, want, self.L, t.dtype, tuple(t.shape)))
+
+    def execute(self, inputs, out, stream=None):
+        """Run asynchronously on ``stream`` (default: torch's current stream)."""
+        torch = _torch()
+        if len(inputs) != self.A:
+            raise ValueError("expected %d inputs" % self.A)
+        for i, t in enumerate(inputs):
+            self._check_tensor(t, "inputs[%d]" % i)
+        self._check_tensor(out, "out")
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        ins = (ctypes.c_void_p * self.A)(*[t.data_ptr() for t in inputs])
+        outs = (ctypes.c_void_p * 1)(out.data_ptr())
+        _L.check(_L.lib().hdconv_execute(self._h, ins, outs, ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def __call__(self, *inputs):
+        torch = _torch()
+        out = torch.empty_like(inputs[0])
+        return self.execute(inputs, out)
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _L.lib().hdconv_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def convolve(*inputs, M=None, **kw):
+    """One-shot convolution of equal-shape complex CUDA tensors (first L outputs)."""
+    L = tuple(inputs[0].shape)
+    with Plan(L, M, A=len(inputs), dtype=inputs[0].dtype, **kw) as p:
+        out = p(*inputs)
+        import torch
+        torch.cuda.current_stream(out.device).synchronize()
+    return out
