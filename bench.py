@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Throughput of hybrid-dealiased complex convolution on one MI355X.
+
+Workload (default): 1D complex convolution, A = 2 inputs, B = 1 output,
+L = 2^20, M = 2^21 (padding ratio 1/2), complex64 entries uniform in the unit
+disk from a fixed seed; hybrid dealiasing as planned by libhdconv.  A step is
+one hdconv_execute over inputs resident in HBM.
+
+Printed as ONE JSON line: outputs/s (value), the roofline of the dominant
+kernel (algorithmic bytes per launch / its average HIP-event duration, against
+the 8 TB/s HBM peak), comparison legs on the same GPU (explicit padding, FP64,
+L = 1,500,000), and the FP64 CPU oracle timed on the host cores as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "conv outputs/s + %HBM roofline: hybrid vs explicit pad, FP32 vs FP64 (err≤1e-5)"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["hd_kernels.hip", "hd_fft.hpp", "hd_common.hpp", "hd_engine.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_17510_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    if name == "c2":
+        return {"workload": "1D complex conv, A=2, B=1, L=2^20, M=2^21, complex64, unit disk, hybrid",
+                "L": [1 << 20], "M": [1 << 21], "A": 2, "dtype": "c64", "config_id": 1}
+    if name == "c2_1p5m":
+        return {"workload": "1D complex conv, A=2, B=1, L=1500000, M=2999999, complex64, unit disk, hybrid",
+                "L": [1500000], "M": [2999999], "A": 2, "dtype": "c64", "config_id": 1}
+    if name == "c4":
+        return {"workload": "2D complex conv, A=2, B=1, 2048x2048, M=4096x4096, complex64, Gaussian, hybrid",
+                "L": [2048, 2048], "M": [4096, 4096], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss"}
+    if name == "c5_3d":
+        return {"workload": "3D complex conv, A=2, B=1, 256^3, M=512^3, complex64, unit disk, hybrid",
+                "L": [256] * 3, "M": [512] * 3, "A": 2, "dtype": "c64", "config_id": 4}
+    raise SystemExit("unknown workload " + name)
+
+
+def make_inputs(wl, dtype):
+    import numpy as np
+    import torch
+    from paper_2303_17510_amd import synth
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    xs = synth.inputs(wl["config_id"], wl["A"], tuple(wl["L"]), wl.get("dist", "disk"), dtype=npdt)
+    return xs, [torch.from_numpy(x).cuda() for x in xs]
+
+
+def time_plan(plan, dev, steps, warmup):
+    """ms per execute over `steps` back-to-back executes, plus per-launch event stats."""
+    import torch
+    out = torch.empty_like(dev[0])
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.execute(dev, out)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        plan.execute(dev, out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # per-kernel durations: events recorded by the library on the same stream
+    plan.profile_begin(steps)
+    for _ in range(steps):
+        plan.execute(dev, out)
+    torch.cuda.synchronize()
+    stats = plan.profile_end()
+    return ms, stats, out
+
+
+def dominant(stats):
+    agg = {}
+    for s in stats:
+        a = agg.setdefault(s["name"], {"total_ms": 0.0, "launches": 0, "bytes": 0.0, "slots": 0})
+        a["total_ms"] += s["total_ms"]
+        a["launches"] += s["launches"]
+        a["bytes"] += s["bytes_per_launch"] * s["launches"]
+        a["slots"] += 1
+    name = max(agg, key=lambda k: agg[k]["total_ms"])
+    a = agg[name]
+    avg_ms = a["total_ms"] / a["launches"]
+    bpl = a["bytes"] / a["launches"]
+    return name, avg_ms, bpl, agg
+
+
+def read_traffic(kernel: str, wlname: str, khash: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, wlname))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_src") != khash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def leg(wl, dtype, method, steps, warmup):
+    from paper_2303_17510_amd import Plan
+    xs, dev = make_inputs(wl, dtype)
+    with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method) as p:
+        info = p.info()
+        ms, stats, out = time_plan(p, dev, steps, warmup)
+    name, avg_ms, bpl, agg = dominant(stats)
+    n_out = 1
+    for l in wl["L"]:
+        n_out *= l
+    r = {"dtype": dtype, "method": method, "ms": ms, "outputs_per_s": n_out / (ms * 1e-3),
+         "plan": [(d["variant"], d["m"], d["p"], d["n"], d["q"]) for d in info["dims"]],
+         "traffic_by_design_GBps": info["traffic_bytes"] / (ms * 1e-3) / 1e9,
+         "compulsory_frac": info["compulsory_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+         "dominant": {"kernel": name, "avg_ms": avg_ms,
+                      "frac": bpl / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+         "kernels": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                         "GBps": (v["bytes"] / v["launches"]) / (v["total_ms"] / v["launches"] * 1e-3) / 1e9}
+                     for k, v in agg.items()}}
+    return r, xs, out
+
+
+def cpu_baseline(wl, xs_by_dtype, outs_by_dtype, budget_s):
+    """Time the FP64 oracle (explicit FFT convolution) on the workload; errors of the GPU results."""
+    import oracle
+    from paper_2303_17510_amd import synth
+    res = {}
+    errs = {}
+    n_out = 1
+    for l in wl["L"]:
+        n_out *= l
+    runs, t_total = 0, 0.0
+    for dtype, xs in xs_by_dtype.items():
+        ins = [synth.as_oracle(x) for x in xs]
+        t0 = time.perf_counter()
+        ref = oracle.conv_explicit(ins)
+        dt = time.perf_counter() - t0
+        runs += 1
+        t_total += dt
+        for key, out in outs_by_dtype.get(dtype, {}).items():
+            errs[key] = oracle.rel_l2(out.cpu().numpy(), ref)
+    # more runs on the first input set until the time budget is used
+    xs = next(iter(xs_by_dtype.values()))
+    ins = [synth.as_oracle(x) for x in xs]
+    while t_total < budget_s:
+        t0 = time.perf_counter()
+        oracle.conv_explicit(ins)
+        t_total += time.perf_counter() - t0
+        runs += 1
+    res = {"value": n_out * runs / t_total, "unit": "outputs/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "%d full runs of the workload through the FP64 oracle's explicitly padded FFT "
+                     "convolution (own radix-2 FFT, OpenMP), %.1f s total" % (runs, t_total)}
+    return res, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2_1p5m", "c4", "c5_3d"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-compare", action="store_true", help="skip explicit / FP64 / other-size legs")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the hybrid-dealiasing path here runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); run without --gpus or with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    wl = workload(args.workload)
+    khash = kernel_hash()
+    log("workload:", wl["workload"])
+    main_leg, xs32, out32 = leg(wl, wl["dtype"], "hybrid", args.steps, args.warmup)
+    log("hybrid c64: %.4f ms, %.3e outputs/s, dominant %s" % (main_leg["ms"], main_leg["outputs_per_s"],
+                                                               main_leg["dominant"]))
+    compare = {}
+    outs = {"c64": {"hybrid_c64": out32}}
+    xs_by = {"c64": xs32}
+    if not args.no_compare:
+        r, _, o = leg(wl, "c64", "explicit", max(10, args.steps // 4), 5)
+        compare["explicit_c64"] = r
+        outs["c64"]["explicit_c64"] = o
+        r, xs64, o = leg(wl, "c128", "hybrid", max(10, args.steps // 4), 5)
+        compare["hybrid_c128"] = r
+        outs["c128"] = {"hybrid_c128": o}
+        xs_by["c128"] = xs64
+        r, _, o = leg(wl, "c128", "explicit", max(10, args.steps // 4), 5)
+        compare["explicit_c128"] = r
+        outs["c128"]["explicit_c128"] = o
+        if args.workload == "c2":
+            r, _, _ = leg(workload("c2_1p5m"), "c64", "hybrid", max(10, args.steps // 4), 5)
+            compare["L1500000_hybrid_c64"] = r
+            r, _, _ = leg(workload("c2_1p5m"), "c64", "explicit", max(10, args.steps // 4), 5)
+            compare["L1500000_explicit_c64"] = r
+        for k, v in compare.items():
+            log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
+                                                                     v["dominant"]["kernel"], v["dominant"]["frac"]))
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        cpu, errs = cpu_baseline(wl, xs_by, outs, args.cpu_budget)
+        log("cpu oracle:", cpu, "errors:", errs)
+
+    dom = main_leg["dominant"]
+    agg_bytes = None
+    for k, v in main_leg["kernels"].items():
+        if k == dom["kernel"]:
+            agg_bytes = v["GBps"]
+    achieved = agg_bytes
+    traffic = read_traffic(dom["kernel"], args.workload, khash)
+    n_out = 1
+    for l in wl["L"]:
+        n_out *= l
+    line = {
+        "metric": METRIC,
+        "value": main_leg["outputs_per_s"],
+        "unit": "outputs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl["dtype"] == "c64" else "f64",
+        "data": "synthetic (seeded, unit disk)",
+        "config": {"workload": wl["workload"], "L": wl["L"], "M": wl["M"], "A": wl["A"], "B": 1,
+                   "plan": main_leg["plan"], "kernel_src": khash},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": traffic, "avg_ms": dom["avg_ms"]},
+        "cpu_baseline": cpu,
+        "err_rel_l2": errs,
+        "compulsory_frac": main_leg["compulsory_frac"],
+        "traffic_by_design_GBps": main_leg["traffic_by_design_GBps"],
+        "kernels": main_leg["kernels"],
+        "compare": compare,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,10 @@ typedef struct hdconv_options {
   int64_t p[3];      /* forced explicit block count, >= ceil(L/m) (0: minimal)  */
   int64_t D[3];      /* residues per block, innermost multipass dim (0: all)    */
   int variant[3];    /* HDCONV_VARIANT_* per dimension                          */
+  int E_m[3];        /* points per lane of the m-point transform (0: choose)    */
+  int E_p[3];        /* points per lane of the p-point transform (0: choose)    */
+  int S[3];          /* columns per workgroup of column/outer kernels (0: choose) */
+  int rows_per_block[3]; /* rows per workgroup of row kernels (0: choose)       */
   int reserved[8];   /* zero                                                    */
 } hdconv_options;
 
@@ -129,6 +133,24 @@ void hdconv_destroy(void* plan);
  * MULTIPASS for the inner form). */
 int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner,
                     hdconv_dim_info_t* out);
+
+/* Per-launch timing.  hdconv_profile_begin(plan, n) creates HIP events for
+ * the next n executes of `plan`; each of those executes records an event
+ * pair around every kernel it launches, on the execute stream (the events
+ * add no synchronisation).  hdconv_profile_end waits for the events, writes
+ * one record per launch slot of an execute (in launch order) into out[0..cap)
+ * and the slot count into *count, and releases the events.  bytes_per_launch
+ * is the launch's algorithmic traffic: the words its contract reads once
+ * plus the words it writes once. */
+typedef struct hdconv_kernel_stat {
+  char name[32];            /* "fused1d", "cols_fwd", "rows_conv", "cols_bwd", "outer_fwd", ... */
+  int64_t launches;         /* executes that timed this slot                  */
+  double total_ms;          /* summed event-to-event time                     */
+  double bytes_per_launch;  /* algorithmic bytes read + written per launch     */
+} hdconv_kernel_stat_t;
+
+int hdconv_profile_begin(void* plan, int max_executes);
+int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* count);
 
 /* Copy the calling thread's last error message into msg (NUL terminated,
  * truncated to cap) and return its status code (HDCONV_OK if none). */

@@ -28,7 +28,8 @@ _i64 = ctypes.c_int64
 class Options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("flags", ctypes.c_int),
                 ("m", _i64 * 3), ("p", _i64 * 3), ("D", _i64 * 3),
-                ("variant", ctypes.c_int * 3), ("reserved", ctypes.c_int * 8)]
+                ("variant", ctypes.c_int * 3), ("E_m", ctypes.c_int * 3), ("E_p", ctypes.c_int * 3),
+                ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("reserved", ctypes.c_int * 8)]
 
 
 class DimInfo(ctypes.Structure):
@@ -45,6 +46,11 @@ class PlanInfo(ctypes.Structure):
                 ("launches", ctypes.c_int)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _i64), ("total_ms", ctypes.c_double),
+                ("bytes_per_launch", ctypes.c_double)]
+
+
 # every symbol include/hdconv.h declares, with its signature
 SIGNATURES = {
     "hdconv_options_init": (None, [ctypes.POINTER(Options)]),
@@ -57,6 +63,9 @@ SIGNATURES = {
     "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hdconv_destroy": (None, [ctypes.c_void_p]),
     "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),
+    "hdconv_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hdconv_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]),
     "hdconv_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "hdconv_version": (ctypes.c_char_p, []),
 }

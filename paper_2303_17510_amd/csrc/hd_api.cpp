@@ -70,6 +70,39 @@ struct Plan {
   void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
   double* acc64 = nullptr;                            // multi-block accumulator
   int launches = 0;
+  // per-launch event timing (hdconv_profile_begin / hdconv_profile_end)
+  struct Prof {
+    bool on = false;
+    int max_exec = 0, used = 0, slot = 0, nslots = 0;
+    std::vector<hipEvent_t> ev;  // [exec][slot][start, end]
+    std::vector<std::string> names;
+    std::vector<double> bytes;
+  } prof;
+};
+
+// Records an event pair around one kernel launch when profiling is on.
+struct ProfScope {
+  Plan* P;
+  hipStream_t s;
+  int idx = -1;
+  ProfScope(Plan* P_, hipStream_t s_, const char* name, double bytes) : P(P_), s(s_) {
+    Plan::Prof& f = P->prof;
+    if (!f.on || f.used >= f.max_exec || f.slot >= f.nslots) return;
+    if ((int)f.names.size() <= f.slot) {
+      f.names.resize(f.slot + 1);
+      f.bytes.resize(f.slot + 1);
+    }
+    f.names[f.slot] = name;
+    f.bytes[f.slot] = bytes;
+    idx = (f.used * f.nslots + f.slot) * 2;
+    (void)hipEventRecord(f.ev[idx], s);
+  }
+  ~ProfScope() {
+    if (idx >= 0) {
+      (void)hipEventRecord(P->prof.ev[idx + 1], s);
+      P->prof.slot++;
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -113,7 +146,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
           dp.q = dp.p;
           dp.variant = VAR_MULTI;
         }
-        if (!finish_dim(&dp, tb, &why))
+        if (!finish_dim(&dp, P->A, tb, &why))
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
       } else if (!choose_dim(Le, Me, P->A, tb, contiguous, &dp, &why)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
@@ -142,7 +175,13 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       dp.q = g.q;
       dp.D = (opt && opt->D[d] > 0) ? std::min<int64_t>(opt->D[d], g.n) : g.n;
       dp.variant = fv;
-      if (!finish_dim(&dp, tb, &why))
+      if (opt) {
+        dp.E_m = opt->E_m[d];
+        dp.E_p = opt->E_p[d];
+        dp.S = opt->S[d];
+        dp.rows_per_block = opt->rows_per_block[d];
+      }
+      if (!finish_dim(&dp, P->A, tb, &why))
         return set_err(HDCONV_EUNSUPPORTED, "dim %d (m=%lld, p=%lld, q=%lld): %s", d, (long long)dp.m,
                        (long long)dp.p, (long long)dp.q, why.c_str());
     }
@@ -210,10 +249,10 @@ static int alloc_tables(Plan* P) {
   std::vector<Ref> refs;
   for (int d = 0; d < P->dims; ++d) {
     DimPlan& dp = P->dp[d];
-    parts.push_back(stage_twiddles(&dp.fd_m));
+    parts.push_back(fft_table(dp.fd_m));
     refs.push_back({d, 0});
     if (dp.variant == VAR_MULTI) {
-      parts.push_back(stage_twiddles(&dp.fd_p));
+      parts.push_back(fft_table(dp.fd_p));
       refs.push_back({d, 1});
       std::vector<double> zq(2 * dp.q);
       for (int64_t k = 0; k < dp.q; ++k) root(dp.q, k, &zq[2 * k], &zq[2 * k + 1]);
@@ -330,7 +369,7 @@ static RootTable<T> rtab(const Plan* P, int d) {
 
 // rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L
 template <typename T>
-static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s) {
+static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s) {
   const int d = P->dims - 1;
   const DimPlan& dp = P->dp[d];
   const int A = P->A;
@@ -349,6 +388,8 @@ static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t
     a.fd = dp.fd_m;
     a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     a.zqm = rtab<T>(P, d);
+    const double wb = 2.0 * sizeof(T);
+    ProfScope ps(P, s, "fused1d", (double)nrows * (A + 1) * dp.L * wb);
     e = launch_fused1d<T>(a, dp.E_m, (int)dp.p, A, s);
     if (e != hipSuccess) return hip_err(e, "fused1d launch");
     return HDCONV_OK;
@@ -375,7 +416,11 @@ static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t
     k1.fd = dp.fd_p;
     k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k1.zq = (const cpx<T>*)P->dd[d].zq;
-    e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
+    const double wb = 2.0 * sizeof(T);
+    {
+      ProfScope ps(P, s, "cols_fwd", (double)nrows * A * ((double)dp.L + (double)D * dp.p * dp.m) * wb);
+      e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
+    }
     if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
 
     RowConvArgs<T> k2{};
@@ -391,7 +436,10 @@ static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t
     k2.fd = dp.fd_m;
     k2.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     k2.zqm = rtab<T>(P, d);
-    e = launch_rows_conv<T>(k2, dp.E_m, A, s);
+    {
+      ProfScope ps(P, s, "rows_conv", (double)nrows * D * dp.p * dp.m * (A + 1) * wb);
+      e = launch_rows_conv<T>(k2, dp.E_m, A, s);
+    }
     if (e != hipSuccess) return hip_err(e, "rows_conv launch");
 
     ColBwdArgs<T> k3{};
@@ -412,7 +460,13 @@ static int run_rows(const Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t
     k3.fd = dp.fd_p;
     k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k3.zq = (const cpx<T>*)P->dd[d].zq;
-    e = launch_cols_bwd<T>(k3, dp.E_p, s);
+    {
+      const double accb = k3.acc_mode == ACC_WRITE ? (double)dp.L * wb
+                          : (k3.acc_mode == ACC_FIRST ? 16.0 * dp.L
+                                                      : (k3.acc_mode == ACC_ADD ? 32.0 * dp.L : 16.0 * dp.L + dp.L * wb));
+      ProfScope ps(P, s, "cols_bwd", (double)nrows * ((double)D * dp.p * dp.m * wb + accb));
+      e = launch_cols_bwd<T>(k3, dp.E_p, s);
+    }
     if (e != hipSuccess) return hip_err(e, "cols_bwd launch");
   }
   return HDCONV_OK;
@@ -437,7 +491,15 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
         b.N[3 - P->dims + d] = P->npad[d];
       }
       b.pad = 1;
-      e = launch_box_copy<T>(b, s);
+      {
+        double lt = 1, nt = 1;
+        for (int d = 0; d < P->dims; ++d) {
+          lt *= (double)P->L[d];
+          nt *= (double)P->npad[d];
+        }
+        ProfScope ps(P, s, "pad", (lt + nt) * 2.0 * sizeof(T));
+        e = launch_box_copy<T>(b, s);
+      }
       if (e != hipSuccess) return hip_err(e, "pad launch");
       cur[a] = (const cpx<T>*)P->pad_in[a];
     }
@@ -468,7 +530,10 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     o.fd = dp.fd_m;
     o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     o.zqm = rtab<T>(P, d);
-    e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, A, s);
+    {
+      ProfScope ps(P, s, "outer_fwd", (double)nb * A * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+      e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, A, s);
+    }
     if (e != hipSuccess) return hip_err(e, "outer_fwd launch");
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
     nb *= dp.q * dp.m;
@@ -503,7 +568,10 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     o.fd = dp.fd_m;
     o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     o.zqm = rtab<T>(P, d);
-    e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
+    {
+      ProfScope ps(P, s, "outer_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+      e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
+    }
     if (e != hipSuccess) return hip_err(e, "outer_bwd launch");
   }
   if (P->method == HDCONV_METHOD_EXPLICIT) {
@@ -516,7 +584,12 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
       b.N[3 - P->dims + d] = P->npad[d];
     }
     b.pad = 0;
-    e = launch_box_copy<T>(b, s);
+    {
+      double lt = 1;
+      for (int d = 0; d < P->dims; ++d) lt *= (double)P->L[d];
+      ProfScope ps(P, s, "truncate", 2.0 * lt * 2.0 * sizeof(T));
+      e = launch_box_copy<T>(b, s);
+    }
     if (e != hipSuccess) return hip_err(e, "truncate launch");
   }
   return HDCONV_OK;
@@ -700,10 +773,74 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
   (void)hipGetDevice(&cur);
   if (cur != P->device) return set_err(HDCONV_EINVAL, "plan belongs to device %d, current device is %d", P->device, cur);
   hipStream_t s = (hipStream_t)stream;
-  if (P->dtype == HDCONV_C64) return run_plan<float>(P, inputs, outputs[0], s);
-  return run_plan<double>(P, inputs, outputs[0], s);
+  P->prof.slot = 0;
+  int rc = P->dtype == HDCONV_C64 ? run_plan<float>(P, inputs, outputs[0], s)
+                                  : run_plan<double>(P, inputs, outputs[0], s);
+  if (P->prof.on && P->prof.used < P->prof.max_exec) P->prof.used++;
+  return rc;
 }
 
-void hdconv_destroy(void* plan) { free_plan((Plan*)plan); }
+static void prof_release(Plan* P) {
+  for (hipEvent_t e : P->prof.ev) (void)hipEventDestroy(e);
+  P->prof = Plan::Prof{};
+}
+
+int hdconv_profile_begin(void* plan, int max_executes) {
+  clear_err();
+  if (!plan || max_executes < 1) return set_err(HDCONV_EINVAL, "need a plan and max_executes >= 1");
+  Plan* P = (Plan*)plan;
+  if (P->host_only) return set_err(HDCONV_EINVAL, "host-only plan");
+  prof_release(P);
+  Plan::Prof& f = P->prof;
+  f.nslots = P->launches;
+  f.max_exec = max_executes;
+  f.ev.resize((size_t)max_executes * f.nslots * 2);
+  for (auto& e : f.ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      prof_release(P);
+      return hip_err(r, "hipEventCreate");
+    }
+  }
+  f.on = true;
+  return HDCONV_OK;
+}
+
+int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* count) {
+  clear_err();
+  if (!plan) return set_err(HDCONV_EINVAL, "plan is NULL");
+  Plan* P = (Plan*)plan;
+  Plan::Prof& f = P->prof;
+  if (!f.on) return set_err(HDCONV_EINVAL, "profiling was not started");
+  const int ns = (int)f.names.size();
+  std::vector<double> tot(ns, 0.0);
+  std::vector<int64_t> cnt(ns, 0);
+  for (int x = 0; x < f.used; ++x)
+    for (int k = 0; k < ns; ++k) {
+      const int idx = (x * f.nslots + k) * 2;
+      float ms = 0;
+      if (hipEventSynchronize(f.ev[idx + 1]) != hipSuccess) continue;
+      if (hipEventElapsedTime(&ms, f.ev[idx], f.ev[idx + 1]) == hipSuccess) {
+        tot[k] += ms;
+        cnt[k] += 1;
+      }
+    }
+  if (count) *count = ns;
+  for (int k = 0; k < ns && k < cap && out; ++k) {
+    memset(&out[k], 0, sizeof(out[k]));
+    snprintf(out[k].name, sizeof(out[k].name), "%s", f.names[k].c_str());
+    out[k].launches = cnt[k];
+    out[k].total_ms = tot[k];
+    out[k].bytes_per_launch = f.bytes[k];
+  }
+  prof_release(P);
+  return HDCONV_OK;
+}
+
+void hdconv_destroy(void* plan) {
+  if (plan) prof_release((Plan*)plan);
+  free_plan((Plan*)plan);
+}
 
 }  // extern "C"

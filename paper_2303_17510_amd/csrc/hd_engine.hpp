@@ -39,7 +39,7 @@ struct FusedArgs {
   int rows_per_block;
   T scale;  // 1/(q m)
   FftDesc fd;
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   RootTable<T> zqm;  // powers of zeta_{qm}
 };
 
@@ -55,7 +55,7 @@ struct ColFwdArgs {
   int64_t L;
   int m, p, q, v0, D, S;
   FftDesc fd;  // p points
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   const cpx<T>* zq;  // zeta_q^k, k < q
 };
 
@@ -70,7 +70,7 @@ struct RowConvArgs {
   int rows_per_block;
   int64_t qm;
   FftDesc fd;  // m points
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   RootTable<T> zqm;
 };
 
@@ -89,7 +89,7 @@ struct ColBwdArgs {
   int m, p, q, v0, D, S;
   T scale;
   FftDesc fd;  // p points
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   const cpx<T>* zq;
 };
 
@@ -104,7 +104,7 @@ struct OuterFwdArgs {
   int64_t L;
   int m, q, r0, D, S;
   FftDesc fd;
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   RootTable<T> zqm;
 };
 
@@ -119,7 +119,7 @@ struct OuterBwdArgs {
   int m, q, r0, D, S;
   T scale;
   FftDesc fd;
-  const cpx<T>* fft_tw;
+  const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   RootTable<T> zqm;
 };
 
@@ -151,10 +151,10 @@ template <typename T>
 hipError_t launch_box_copy(const BoxCopyArgs<T>& a, hipStream_t s);
 
 // LDS bytes each launcher requests (host-side sizing and validation).
-size_t lds_fused1d(int m, int rows_per_block, int tbytes);
-size_t lds_cols(int p, int S, int tbytes);
-size_t lds_rows(int m, int rows_per_block, int tbytes);
-size_t lds_outer(int m, int S, int tbytes);
+size_t lds_fused1d(int m, int rows_per_block, int A, int ntw, int tbytes);
+size_t lds_cols(int p, int S, int ntw, int tbytes);
+size_t lds_rows(int m, int rows_per_block, int A, int ntw, int tbytes);
+size_t lds_outer(int m, int S, int ntw, int tbytes);
 
 // True when the radix set of d fits the template instance E.
 bool fft_fits(const FftDesc& d, int E);

@@ -107,87 +107,152 @@ struct FftDesc {
   int G;          // lanes per transform; N = G * E
   int nst;        // stages
   int radix[12];  // radix of each stage (each divides E)
-  int twoff[12];  // offset of the stage's twiddle table in the size's table
+  int kb;         // twiddle table split: K = 2^kb
+  int ntw;        // table entries: K + ceil(N / K)
 };
 
-// LDS exchange addressing: point i of a transform lives at
-// base[i * xs + (i >> ps)] -- xs > 1 interleaves the transforms of adjacent
-// columns; ps < 31 pads one slot every 2^ps points to spread LDS banks.
+// Powers of zeta_N = exp(2 pi i/N) from a two-level table held in LDS:
+//   zeta_N^e = lo[e & (K-1)] * hi[e >> kb],  lo[j] = zeta_N^j, hi[h] = zeta_N^{hK}.
+// Each entry is rounded from an FP64 value, so a lookup is within about two
+// ulps of the exact root.
+template <typename T>
+struct TwLds {
+  const cpx<T>* lo;
+  const cpx<T>* hi;
+  int kb;
+  __device__ __forceinline__ cpx<T> get(int e) const {
+    const cpx<T> a = lo[e & ((1 << kb) - 1)];
+    const int h = e >> kb;
+    return h ? cmul(a, hi[h]) : a;
+  }
+};
+
+// Copy a transform's two-level table (lo then hi, ntw entries) from global
+// memory into LDS; all lanes of the workgroup take part.  The caller puts a
+// barrier between this and the first use.
+template <typename T>
+__device__ __forceinline__ TwLds<T> stage_table(const FftDesc& d, const cpx<T>* __restrict__ g,
+                                                cpx<T>* lds) {
+  for (int i = threadIdx.x; i < d.ntw; i += blockDim.x) lds[i] = g[i];
+  TwLds<T> t;
+  t.lo = lds;
+  t.hi = lds + (1 << d.kb);
+  t.kb = d.kb;
+  return t;
+}
+
+// LDS exchange addressing: point i of transform n lives at
+// base[n * ns + i * xs + (i >> ps)] -- xs > 1 interleaves the transforms of
+// adjacent columns; ps < 31 pads one slot every 2^ps points to spread banks.
 template <typename T>
 struct Xchg {
   cpx<T>* base;
   int xs;
   int ps;
-  __device__ __forceinline__ cpx<T>& at(int i) const { return base[i * xs + (i >> ps)]; }
+  int ns;
+  __device__ __forceinline__ cpx<T>& at(int n, int i) const { return base[n * ns + i * xs + (i >> ps)]; }
 };
 
-// One Stockham pass of radix R over span Ns.  Butterfly j = g + G*b reads
-// points j + i*N/R (registers b + i*E/R), multiplies point i by
-// w_{Ns R}^{S k i} (k = j mod Ns, table entries tw[k (R-1) + i - 1]), runs
-// the radix-R DFT and stores output c at (j - k) R + k + c Ns.
-template <typename T, int E, int R, int S>
-__device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], int g, int G, int Ns,
-                                          const cpx<T>* __restrict__ tw, const Xchg<T>& xb,
-                                          bool last) {
+// Twiddles w^i, i = 1 .. R-1, of one butterfly, with w = zeta_N^{e1}: the
+// base-4 digits of i select products of w^{d 4^k} (d = 1..3), so a radix-R
+// butterfly needs ceil(log4 R) table lookups and every twiddle is a product
+// of at most ceil(log4 R) + 2 rounded factors.
+template <typename T, int R>
+__device__ __forceinline__ void butterfly_twiddles(const TwLds<T>& tw, int e1, cpx<T> (&w)[R]) {
+  constexpr int ND = R <= 4 ? 1 : (R <= 16 ? 2 : 3);
+  cpx<T> P[ND][4];
+  int e = e1;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    P[d][0] = mk(T(1), T(0));
+    P[d][1] = tw.get(e);
+    P[d][2] = cmul(P[d][1], P[d][1]);
+    P[d][3] = cmul(P[d][2], P[d][1]);
+    e <<= 2;
+  }
+  w[0] = mk(T(1), T(0));
+#pragma unroll
+  for (int i = 1; i < R; ++i) {
+    cpx<T> t = P[0][i & 3];
+    if (ND > 1 && (i >> 2) > 0) t = (i & 3) ? cmul(t, P[ND > 1 ? 1 : 0][(i >> 2) & 3]) : P[ND > 1 ? 1 : 0][(i >> 2) & 3];
+    if (ND > 2 && (i >> 4) > 0) t = cmul(t, P[ND > 2 ? 2 : 0][(i >> 4) & 3]);
+    w[i] = t;
+  }
+}
+
+// One Stockham pass of radix R over span Ns, applied to NT transforms that
+// share twiddles and barriers.  Butterfly j = g + G*b reads points
+// j + i*N/R (registers b + i*E/R), multiplies point i by w_{Ns R}^{S k i}
+// (k = j mod Ns), runs the radix-R DFT and stores output c at
+// (j - k) R + k + c Ns.  The last pass keeps its outputs in registers: they
+// are already in the strided layout of the natural-order result.
+template <typename T, int E, int R, int S, int NT>
+__device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int N, int Ns,
+                                          const TwLds<T>& tw, const Xchg<T>& xb, bool last) {
   constexpr int NB = E / R;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
     const int k = j % Ns;
-    cpx<T> x[R];
+    cpx<T> w[R];
+    if (Ns > 1) butterfly_twiddles<T, R>(tw, k * (N / (Ns * R)), w);
 #pragma unroll
-    for (int i = 0; i < R; ++i) x[i] = v[b + i * NB];
-    if (Ns > 1) {
-      const cpx<T>* w = tw + k * (R - 1) - 1;
+    for (int n = 0; n < NT; ++n) {
+      cpx<T> x[R];
 #pragma unroll
-      for (int i = 1; i < R; ++i) x[i] = cmul_s<S>(x[i], w[i]);
-    }
-    dftr<R, S>(x);
-    if (last) {
+      for (int i = 0; i < R; ++i) x[i] = v[n][b + i * NB];
+      if (Ns > 1) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) v[b + c * NB] = x[c];
-    } else {
-      const int base = (j - k) * R + k;
+        for (int i = 1; i < R; ++i) x[i] = cmul_s<S>(x[i], w[i]);
+      }
+      dftr<R, S>(x);
+      if (last) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) xb.at(base + c * Ns) = x[c];
+        for (int c = 0; c < R; ++c) v[n][b + c * NB] = x[c];
+      } else {
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int c = 0; c < R; ++c) xb.at(n, base + c * Ns) = x[c];
+      }
     }
   }
   if (!last) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = xb.at(g + G * e);
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[n][e] = xb.at(n, g + G * e);
     __syncthreads();
   }
 }
 
-// Whole transform.  Every lane of the workgroup must call this with the same
-// descriptor (the stage count decides the number of barriers).
-template <typename T, int E, int S>
-__device__ __forceinline__ void gfft(cpx<T> (&v)[E], int g, const FftDesc& d,
-                                     const cpx<T>* __restrict__ tw, const Xchg<T>& xb) {
+// NT transforms of one size at once.  Every lane of the workgroup must call
+// this with the same descriptor (the stage count decides the barriers).
+template <typename T, int E, int S, int NT>
+__device__ __forceinline__ void gfft(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
+                                     const Xchg<T>& xb) {
   int Ns = 1;
   for (int st = 0; st < d.nst; ++st) {
     const int R = d.radix[st];
     const bool last = (st == d.nst - 1);
-    const cpx<T>* t = tw + d.twoff[st];
     switch (R) {
       case 2:
-        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       case 3:
-        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       case 4:
-        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       case 8:
-        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       case 16:
-        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       case 32:
-        if constexpr (E % 32 == 0) fft_stage<T, E, 32, S>(v, g, d.G, Ns, t, xb, last);
+        if constexpr (E % 32 == 0) fft_stage<T, E, 32, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
         break;
       default:
         break;

@@ -69,6 +69,9 @@ bool make_fft_desc(int64_t N, int E, FftDesc* d) {
     rem /= r;
   }
   d->nst = st;
+  d->kb = 0;
+  while ((int64_t(1) << (2 * d->kb)) < N) ++d->kb;
+  d->ntw = (1 << d->kb) + (int)((N + (int64_t(1) << d->kb) - 1) >> d->kb);
   return true;
 }
 
@@ -86,11 +89,8 @@ static bool pick_e_row(int64_t m, bool fused, int tbytes, int* E) {
     *E = 24;
     return m % 24 == 0 && m / 24 <= kMaxThreads;
   }
-  if (fused) {
-    *E = m <= 2048 ? 8 : (m <= 8192 ? 16 : 32);
-  } else {
-    *E = m < 16 ? 8 : (m <= 8192 ? 16 : 32);
-  }
+  (void)fused;
+  *E = m <= 4096 ? 8 : (m <= 8192 ? 16 : 32);
   return m >= *E && m / *E <= kMaxThreads;
 }
 
@@ -103,11 +103,11 @@ static bool pick_e_col(int64_t p, int* E) {
     *E = (int)p;
     return p == 1 || p == 2 || p == 4 || p == 8;
   }
-  *E = (p >= 256) ? 16 : 8;
+  *E = (p > 512) ? 16 : 8;
   return true;
 }
 
-bool finish_dim(DimPlan* dp, int tbytes, std::string* why) {
+bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
   const int cb = 2 * tbytes;  // bytes per complex word
   auto fail = [&](const char* s) {
     if (why) *why = s;
@@ -119,57 +119,67 @@ bool finish_dim(DimPlan* dp, int tbytes, std::string* why) {
   if (!fft_size_ok(dp->m)) return fail("m must be 2^a or 3*2^a (a >= 3)");
   if (dp->D < 1) dp->D = dp->n;
   if (dp->D > dp->n) return fail("D exceeds the number of residues");
+  // Preset shape fields (nonzero on entry) are kept and validated; zero ones
+  // are chosen here.
+  auto in_set = [](int v, std::initializer_list<int> s) {
+    for (int x : s)
+      if (x == v) return true;
+    return false;
+  };
   switch (dp->variant) {
-    case VAR_FUSED: {
-      if (dp->p > 2) return fail("fused variant needs p <= 2");
-      if (dp->m > kMaxFusedM) return fail("fused variant needs m <= 8192");
-      if (dp->D != dp->n) return fail("fused variant processes all residues");
-      if (!pick_e_row(dp->m, true, tbytes, &dp->E_m)) return fail("unsupported m for the fused variant");
-      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
-      int rpb = std::max(1, 256 / dp->fd_m.G);
-      while (rpb > 1 && (size_t)rpb * (dp->m + (dp->m >> 4)) * cb > 65536) rpb /= 2;
-      if ((size_t)rpb * (dp->m + (dp->m >> 4)) * cb > kLdsBudget) return fail("row does not fit in LDS");
-      dp->rows_per_block = rpb;
-      return true;
-    }
+    case VAR_FUSED:
     case VAR_MULTI: {
-      if (dp->q != dp->n * dp->p) return fail("inner form needs q = n p");
-      if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 16384");
-      if (dp->p > kMaxColP || !fft_size_ok(dp->p)) return fail("unsupported p for the column passes");
-      if (!pick_e_row(dp->m, false, tbytes, &dp->E_m)) return fail("unsupported m for the row pass");
-      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
-      int rpb = std::max(1, 256 / dp->fd_m.G);
-      while (rpb > 1 && (size_t)rpb * (dp->m + (dp->m >> 4)) * cb > 65536) rpb /= 2;
-      if ((size_t)rpb * (dp->m + (dp->m >> 4)) * cb > kLdsBudget) return fail("row does not fit in LDS");
-      dp->rows_per_block = rpb;
-      if (!pick_e_col(dp->p, &dp->E_p)) return fail("unsupported p for the column passes");
-      if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p");
-      int S = 64;
-      while (S > 1 && (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || (size_t)dp->p * S * cb > 65536))
-        S /= 2;
-      if (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || (size_t)dp->p * S * cb > kLdsBudget)
+      const bool fused = dp->variant == VAR_FUSED;
+      if (fused) {
+        if (dp->p > 2) return fail("fused variant needs p <= 2");
+        if (dp->m > kMaxFusedM) return fail("fused variant needs m <= 8192");
+        if (dp->D != dp->n) return fail("fused variant processes all residues");
+      } else {
+        if (dp->q != dp->n * dp->p) return fail("inner form needs q = n p");
+        if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 16384");
+        if (dp->p > kMaxColP || !fft_size_ok(dp->p)) return fail("unsupported p for the column passes");
+      }
+      if (dp->E_m == 0 && !pick_e_row(dp->m, fused, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
+      if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("row points per lane must be 8, 16, 24 or 32");
+      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
+      auto need = [&](int r) { return ((size_t)r * A * (dp->m + (dp->m >> 4)) + dp->fd_m.ntw) * cb; };
+      if (dp->rows_per_block == 0) {
+        int rpb = std::max(1, 256 / dp->fd_m.G);
+        while (rpb > 1 && need(rpb) > 65536) rpb /= 2;
+        dp->rows_per_block = rpb;
+      }
+      if (dp->rows_per_block < 1 || dp->rows_per_block * dp->fd_m.G > kMaxThreads)
+        return fail("rows per block exceed the thread limit");
+      if (need(dp->rows_per_block) > kLdsBudget) return fail("row does not fit in LDS");
+      if (fused) return true;
+      if (dp->E_p == 0 && !pick_e_col(dp->p, &dp->E_p)) return fail("unsupported p for the column passes");
+      if (!in_set(dp->E_p, {1, 2, 4, 8, 16, 24})) return fail("column points per lane must be 1, 2, 4, 8, 16 or 24");
+      if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p with these points per lane");
+      auto cneed = [&](int S) { return ((size_t)2 * dp->p * S + dp->fd_p.ntw) * cb; };
+      if (dp->S == 0) {
+        int S = 64;
+        while (S > 1 && (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || cneed(S) > 81920)) S /= 2;
+        dp->S = S;
+      }
+      if (dp->m % dp->S != 0 || dp->S * dp->fd_p.G > kMaxThreads || cneed(dp->S) > kLdsBudget)
         return fail("column tile does not fit");
-      dp->S = S;
       return true;
     }
     case VAR_OUTER: {
       if (dp->p > 2) return fail("outer variant needs p <= 2");
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
       if (dp->D != dp->n) return fail("outer variant processes all residues");
-      if (dp->m % 3 == 0) {
-        dp->E_m = 24;
-        if (dp->m % 24) return fail("unsupported m");
-      } else {
-        dp->E_m = dp->m < 16 ? 8 : (dp->m <= 1024 ? 16 : 32);
-        if (dp->m < 8) return fail("outer variant needs m >= 8");
+      if (dp->m < 8) return fail("outer variant needs m >= 8");
+      if (dp->E_m == 0) dp->E_m = dp->m % 3 == 0 ? 24 : (dp->m < 16 ? 8 : (dp->m <= 1024 ? 16 : 32));
+      if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("outer points per lane must be 8, 16, 24 or 32");
+      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
+      auto oneed = [&](int S) { return ((size_t)dp->m * S + dp->fd_m.ntw) * cb; };
+      if (dp->S == 0) {
+        int S = std::min(pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G)), 64);
+        while (S > 1 && oneed(S) > 128 * 1024) S /= 2;
+        dp->S = S;
       }
-      if (dp->m / dp->E_m > kMaxThreads) return fail("outer column too long");
-      if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m");
-      int S = pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G));
-      S = std::min(S, 64);
-      while (S > 1 && (size_t)dp->m * S * cb > 128 * 1024) S /= 2;
-      if ((size_t)dp->m * S * cb > kLdsBudget) return fail("outer column does not fit in LDS");
-      dp->S = S;
+      if (dp->S * dp->fd_m.G > kMaxThreads || oneed(dp->S) > kLdsBudget) return fail("outer column tile does not fit");
       return true;
     }
     default:
@@ -188,36 +198,35 @@ static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min
   dp->q = g.q;
   dp->D = g.n;
   dp->variant = variant;
+  dp->E_m = dp->E_p = dp->S = dp->rows_per_block = 0;
   return true;
 }
 
 bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPlan* dp, std::string* why) {
-  (void)A;
   std::string w;
   if (contiguous) {
     int64_t m = std::max<int64_t>(8, next_fft_size(L));
-    if (m <= kMaxFusedM && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, tbytes, &w)) return true;
+    if (m <= kMaxFusedM && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, A, tbytes, &w)) return true;
     // large rows: inner form with m near 8192 (c64) / 4096 (c128)
-    int64_t mm = tbytes == 4 ? 8192 : 4096;
+    int64_t mm = 4096;
     while (mm > 16 && mm / 2 >= L) mm /= 2;
     for (; mm <= kMaxRowM; mm *= 2) {
       int64_t p = next_col_size(cdiv(L, mm));
       if (p > kMaxColP) continue;
-      if (set_geom(dp, L, M, mm, p, VAR_MULTI) && finish_dim(dp, tbytes, &w)) return true;
+      if (set_geom(dp, L, M, mm, p, VAR_MULTI) && finish_dim(dp, A, tbytes, &w)) return true;
     }
     if (why) *why = "no supported plan for this length: " + w;
     return false;
   }
   int64_t m = std::max<int64_t>(8, next_fft_size(L));
-  if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, tbytes, &w)) return true;
+  if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
   m = std::max<int64_t>(8, next_fft_size(cdiv(L, 2)));
-  if (set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, tbytes, &w)) return true;
+  if (set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
   if (why) *why = "no supported plan for this outer length: " + w;
   return false;
 }
 
 std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous) {
-  (void)A;
   std::vector<DimPlan> out;
   std::vector<int64_t> sizes;
   for (int64_t s = 8; s <= kMaxRowM; s <<= 1) {
@@ -230,13 +239,13 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
     DimPlan dp;
     std::string w;
     if (contiguous) {
-      if (set_geom(&dp, L, M, m, 0, VAR_FUSED) && finish_dim(&dp, tbytes, &w)) out.push_back(dp);
+      if (set_geom(&dp, L, M, m, 0, VAR_FUSED) && finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
       DimPlan d2;
       int64_t p = next_col_size(cdiv(L, m));
-      if (m >= 16 && p <= kMaxColP && set_geom(&d2, L, M, m, p, VAR_MULTI) && finish_dim(&d2, tbytes, &w))
+      if (m >= 16 && p <= kMaxColP && set_geom(&d2, L, M, m, p, VAR_MULTI) && finish_dim(&d2, A, tbytes, &w))
         out.push_back(d2);
     } else {
-      if (set_geom(&dp, L, M, m, 0, VAR_OUTER) && finish_dim(&dp, tbytes, &w)) out.push_back(dp);
+      if (set_geom(&dp, L, M, m, 0, VAR_OUTER) && finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
     }
   }
   return out;
@@ -256,22 +265,20 @@ void root(int64_t N, int64_t e, double* re, double* im) {
   if (e == 0) { *re = 1.0; *im = 0.0; }
 }
 
-std::vector<double> stage_twiddles(FftDesc* d) {
+std::vector<double> fft_table(const FftDesc& d) {
   std::vector<double> v;
-  int64_t Ns = 1;
-  for (int st = 0; st < d->nst; ++st) {
-    const int R = d->radix[st];
-    d->twoff[st] = (int)(v.size() / 2);
-    if (Ns > 1) {
-      for (int64_t k = 0; k < Ns; ++k)
-        for (int i = 1; i < R; ++i) {
-          double re, im;
-          root(Ns * R, k * i, &re, &im);
-          v.push_back(re);
-          v.push_back(im);
-        }
-    }
-    Ns *= R;
+  const int64_t K = int64_t(1) << d.kb;
+  for (int64_t j = 0; j < K; ++j) {
+    double re, im;
+    root(d.N, j, &re, &im);
+    v.push_back(re);
+    v.push_back(im);
+  }
+  for (int64_t h = 0; h * K < d.N; ++h) {
+    double re, im;
+    root(d.N, h * K, &re, &im);
+    v.push_back(re);
+    v.push_back(im);
   }
   return v;
 }

@@ -57,7 +57,7 @@ bool make_fft_desc(int64_t N, int E, FftDesc* d);
 // Choose template widths, tiles and rows per block for a dimension whose
 // (m, p, n, q, variant) are set.  tbytes = sizeof(real).  On failure returns
 // false with a reason.
-bool finish_dim(DimPlan* dp, int tbytes, std::string* why);
+bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why);
 
 // Default (heuristic) choice for one dimension.  `contiguous` marks the
 // innermost dimension (rows), others are outer dimensions.
@@ -67,9 +67,9 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPla
 // Candidates for the autotuner: every supported (m, variant) of a dimension.
 std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous);
 
-// FP64 stage twiddle tables of a descriptor: fills d->twoff and returns the
-// values (interleaved re, im) of w_{Ns R}^{k i}, k < Ns, 1 <= i < R.
-std::vector<double> stage_twiddles(FftDesc* d);
+// FP64 two-level table of zeta_N for a descriptor (interleaved re, im):
+// lo[j] = zeta_N^j for j < 2^kb, then hi[h] = zeta_N^{h 2^kb} for h < ceil(N / 2^kb).
+std::vector<double> fft_table(const FftDesc& d);
 
 // Roots of unity in FP64 (long double internally), zeta_N^e for e in [0, N).
 void root(int64_t N, int64_t e, double* re, double* im);

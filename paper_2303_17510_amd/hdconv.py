@@ -59,7 +59,7 @@ class Plan:
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
-                 host_only: bool = False):
+                 host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
@@ -79,6 +79,9 @@ class Plan:
             opt.p[d] = v
         for d, v in enumerate(_tup(D, dims)):
             opt.D[d] = v
+        for name, val in (("E_m", E_m), ("E_p", E_p), ("S", S), ("rows_per_block", rows_per_block)):
+            for d, v in enumerate(_tup(val, dims)):
+                getattr(opt, name)[d] = v
         vs = variant if isinstance(variant, (list, tuple)) else [variant] * dims
         for d, v in enumerate(vs):
             opt.variant[d] = _VARIANTS[v]
@@ -130,6 +133,24 @@ class Plan:
         ins = (ctypes.c_void_p * self.A)(*[t.data_ptr() for t in inputs])
         outs = (ctypes.c_void_p * 1)(out.data_ptr())
         _L.check(_L.lib().hdconv_execute(self._h, ins, outs, ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def profile_begin(self, max_executes: int):
+        """Record HIP events around each kernel of the next ``max_executes`` executes."""
+        _L.check(_L.lib().hdconv_profile_begin(self._h, int(max_executes)))
+
+    def profile_end(self) -> list:
+        """Per-launch-slot timing since :meth:`profile_begin` (waits for the events)."""
+        cap = 64
+        arr = (_L.KernelStat * cap)()
+        n = ctypes.c_int(0)
+        _L.check(_L.lib().hdconv_profile_end(self._h, arr, cap, ctypes.byref(n)))
+        out = []
+        for k in range(min(n.value, cap)):
+            r = arr[k]
+            out.append({"slot": k, "name": r.name.decode(), "launches": r.launches, "total_ms": r.total_ms,
+                        "avg_ms": r.total_ms / r.launches if r.launches else float("nan"),
+                        "bytes_per_launch": r.bytes_per_launch})
         return out
 
     def __call__(self, *inputs):
