@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "conv outputs/s + %HBM roofline: hybrid vs explicit pad, FP32 vs FP64 (err≤1e-5)"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["hd_kernels.hip", "hd_fft.hpp", "hd_common.hpp", "hd_engine.hpp"]
+KERNEL_SOURCES = ["hd_k_fused.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_kcommon.hpp", "hd_fft.hpp",
+                  "hd_common.hpp", "hd_engine.hpp"]
 
 
 def kernel_hash() -> str:

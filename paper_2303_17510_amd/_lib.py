@@ -29,13 +29,15 @@ class Options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("flags", ctypes.c_int),
                 ("m", _i64 * 3), ("p", _i64 * 3), ("D", _i64 * 3),
                 ("variant", ctypes.c_int * 3), ("E_m", ctypes.c_int * 3), ("E_p", ctypes.c_int * 3),
-                ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("reserved", ctypes.c_int * 8)]
+                ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("twiddles", ctypes.c_int * 3),
+                ("reserved", ctypes.c_int * 8)]
 
 
 class DimInfo(ctypes.Structure):
     _fields_ = [("L", _i64), ("M", _i64), ("m", _i64), ("p", _i64), ("n", _i64), ("q", _i64),
                 ("D", _i64), ("variant", ctypes.c_int), ("E_m", ctypes.c_int), ("E_p", ctypes.c_int),
-                ("S", ctypes.c_int), ("rows_per_block", ctypes.c_int)]
+                ("S", ctypes.c_int), ("rows_per_block", ctypes.c_int), ("tw_m", ctypes.c_int),
+                ("tw_p", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):

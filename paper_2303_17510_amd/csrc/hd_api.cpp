@@ -180,6 +180,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
         dp.E_p = opt->E_p[d];
         dp.S = opt->S[d];
         dp.rows_per_block = opt->rows_per_block[d];
+        dp.tw_pref = opt->twiddles[d];
       }
       if (!finish_dim(&dp, P->A, tb, &why))
         return set_err(HDCONV_EUNSUPPORTED, "dim %d (m=%lld, p=%lld, q=%lld): %s", d, (long long)dp.m,
@@ -745,6 +746,8 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
     di.E_p = dp.E_p;
     di.S = dp.S;
     di.rows_per_block = dp.rows_per_block;
+    di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
+    di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
   }
   out->workspace_bytes = P->work_bytes;
   out->table_bytes = P->table_bytes;

@@ -151,9 +151,9 @@ template <typename T>
 hipError_t launch_box_copy(const BoxCopyArgs<T>& a, hipStream_t s);
 
 // LDS bytes each launcher requests (host-side sizing and validation).
-size_t lds_fused1d(int m, int rows_per_block, int A, int ntw, int tbytes);
+size_t lds_fused1d(int m, int ps, int rows_per_block, int A, int ntw, int tbytes);
 size_t lds_cols(int p, int S, int ntw, int tbytes);
-size_t lds_rows(int m, int rows_per_block, int A, int ntw, int tbytes);
+size_t lds_rows(int m, int ps, int rows_per_block, int A, int ntw, int tbytes);
 size_t lds_outer(int m, int S, int ntw, int tbytes);
 
 // True when the radix set of d fits the template instance E.

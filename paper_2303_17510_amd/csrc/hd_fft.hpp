@@ -108,18 +108,27 @@ struct FftDesc {
   int nst;        // stages
   int radix[12];  // radix of each stage (each divides E)
   int kb;         // twiddle table split: K = 2^kb
-  int ntw;        // table entries: K + ceil(N / K)
+  int ntw;        // entries of the two-level table: K + ceil(N / K)
+  int twmode;     // 1: per-stage tables staged in LDS; 0: two-level table in LDS
+  int twoff[12];  // per-stage table: offset of each stage (entries k (R-1) + i - 1)
+  int ntw_stage;  // entries of all per-stage tables
+  int ps;         // row exchanges pad one slot every 2^ps points (first-stage writes
+                  // land R apart, so ps = log2 R spreads them over the banks)
 };
 
-// Powers of zeta_N = exp(2 pi i/N) from a two-level table held in LDS:
-//   zeta_N^e = lo[e & (K-1)] * hi[e >> kb],  lo[j] = zeta_N^j, hi[h] = zeta_N^{hK}.
-// Each entry is rounded from an FP64 value, so a lookup is within about two
-// ulps of the exact root.
+// LDS words (complex) a transform's twiddles occupy.
+__host__ __device__ inline int tw_words(const FftDesc& d) { return d.twmode ? d.ntw_stage : d.ntw; }
+
+// Twiddles of a transform, held in LDS.  Mode 0: powers of zeta_N from a
+// two-level table, zeta_N^e = lo[e & (K-1)] * hi[e >> kb] (within about two
+// ulps of the exact root).  Mode 1: for each stage the exact values
+// w_{Ns R}^{k i} (k < Ns, 1 <= i < R), each rounded once from FP64.
 template <typename T>
 struct TwLds {
   const cpx<T>* lo;
   const cpx<T>* hi;
   int kb;
+  int mode;
   __device__ __forceinline__ cpx<T> get(int e) const {
     const cpx<T> a = lo[e & ((1 << kb) - 1)];
     const int h = e >> kb;
@@ -127,17 +136,21 @@ struct TwLds {
   }
 };
 
-// Copy a transform's two-level table (lo then hi, ntw entries) from global
-// memory into LDS; all lanes of the workgroup take part.  The caller puts a
-// barrier between this and the first use.
+// Copy a transform's twiddles (the global table holds the two-level table,
+// ntw entries, followed by the per-stage tables) into LDS; all lanes of the
+// workgroup take part.  The caller puts a barrier between this and the first
+// use.
 template <typename T>
 __device__ __forceinline__ TwLds<T> stage_table(const FftDesc& d, const cpx<T>* __restrict__ g,
                                                 cpx<T>* lds) {
-  for (int i = threadIdx.x; i < d.ntw; i += blockDim.x) lds[i] = g[i];
+  const int n = tw_words(d);
+  const cpx<T>* src = d.twmode ? g + d.ntw : g;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = src[i];
   TwLds<T> t;
   t.lo = lds;
   t.hi = lds + (1 << d.kb);
   t.kb = d.kb;
+  t.mode = d.twmode;
   return t;
 }
 
@@ -187,15 +200,24 @@ __device__ __forceinline__ void butterfly_twiddles(const TwLds<T>& tw, int e1, c
 // (j - k) R + k + c Ns.  The last pass keeps its outputs in registers: they
 // are already in the strided layout of the natural-order result.
 template <typename T, int E, int R, int S, int NT>
-__device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int N, int Ns,
+__device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int N, int Ns, int twoff,
                                           const TwLds<T>& tw, const Xchg<T>& xb, bool last) {
   constexpr int NB = E / R;
+  const bool pow2 = (Ns & (Ns - 1)) == 0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
-    const int k = j % Ns;
+    const int k = pow2 ? (j & (Ns - 1)) : j % Ns;
     cpx<T> w[R];
-    if (Ns > 1) butterfly_twiddles<T, R>(tw, k * (N / (Ns * R)), w);
+    if (Ns > 1) {
+      if (tw.mode) {
+        const cpx<T>* t = tw.lo + twoff + k * (R - 1) - 1;
+#pragma unroll
+        for (int i = 1; i < R; ++i) w[i] = t[i];
+      } else {
+        butterfly_twiddles<T, R>(tw, k * (N / (Ns * R)), w);
+      }
+    }
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
       cpx<T> x[R];
@@ -235,30 +257,89 @@ __device__ __forceinline__ void gfft(cpx<T> (&v)[NT][E], int g, const FftDesc& d
   for (int st = 0; st < d.nst; ++st) {
     const int R = d.radix[st];
     const bool last = (st == d.nst - 1);
+    const int to = d.twoff[st];
     switch (R) {
       case 2:
-        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       case 3:
-        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       case 4:
-        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       case 8:
-        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       case 16:
-        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       case 32:
-        if constexpr (E % 32 == 0) fft_stage<T, E, 32, S, NT>(v, g, d.G, d.N, Ns, tw, xb, last);
+        if constexpr (E % 32 == 0) fft_stage<T, E, 32, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
         break;
       default:
         break;
     }
     Ns *= R;
   }
+}
+
+// Stage radix for `rem` points left, the same rule make_fft_desc applies on
+// the host: factors 3 first, then the largest power of two up to 16 that
+// divides both E and rem.
+__host__ __device__ constexpr int ct_radix(int rem, int E) {
+  if (rem % 3 == 0) return 3;
+  int r = 1;
+  while (r < 16 && E % (2 * r) == 0) r *= 2;
+  while (r > 1 && rem % r != 0) r /= 2;
+  return r;
+}
+
+// The same transform with N and E known at compile time: the stage plan is
+// unrolled and every span, mask and twiddle stride is a constant.
+template <typename T, int N, int E, int S, int NT, int Ns = 1, int ST = 0>
+__device__ __forceinline__ void gfft_ct(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
+                                        const Xchg<T>& xb) {
+  if constexpr (Ns < N) {
+    constexpr int R = ct_radix(N / Ns, E);
+    static_assert(R > 1 && (N / Ns) % R == 0 && E % R == 0, "no stage plan");
+    fft_stage<T, E, R, S, NT>(v, g, N / E, N, Ns, d.twoff[ST], tw, xb, Ns * R == N);
+    gfft_ct<T, N, E, S, NT, Ns * R, ST + 1>(v, g, d, tw, xb);
+  }
+}
+
+// Sizes compiled with a fixed stage plan for each points-per-lane E.
+template <int E, int N>
+__host__ __device__ constexpr bool ct_size() {
+  if (E == 8) return N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096;
+  if (E == 16) return N == 1024 || N == 2048 || N == 4096 || N == 8192;
+  if (E == 32) return N == 2048 || N == 4096 || N == 8192 || N == 16384;
+  return false;
+}
+
+// Sizes each kernel kind specialises (bit k: N = 2^k); the others take the
+// general path.
+constexpr unsigned kCtFused = 0;
+constexpr unsigned kCtRows = (1u << 11) | (1u << 12) | (1u << 13);
+constexpr unsigned kCtCols = (1u << 7) | (1u << 8) | (1u << 9);
+constexpr unsigned kCtOuter = 0;
+
+// Transform with the specialised plan when one exists for (N, E) and the
+// kernel kind's MASK selects N, else the general one.  d.N is the same on
+// every lane, so the branch is uniform.
+template <typename T, int E, int S, int NT, unsigned MASK>
+__device__ __forceinline__ void gfft_any(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
+                                         const Xchg<T>& xb) {
+#define HD_CT(NN)                                              \
+  if constexpr (ct_size<E, NN>() && (MASK & (NN)) != 0) {      \
+    if (d.N == NN) {                                           \
+      gfft_ct<T, NN, E, S, NT>(v, g, d, tw, xb);               \
+      return;                                                  \
+    }                                                          \
+  }
+  HD_CT(128) HD_CT(256) HD_CT(512) HD_CT(1024) HD_CT(2048) HD_CT(4096) HD_CT(8192) HD_CT(16384)
+#undef HD_CT
+  gfft<T, E, S, NT>(v, g, d, tw, xb);
 }
 
 }  // namespace hd

@@ -1,0 +1,135 @@
+// hd_k_fused.hip -- whole 1D convolutions per row, direct form (p <= 2).
+// The convolution is bandwidth-bound, so no kernel uses matrix cores: every
+// kernel streams its operands through registers once, runs its transforms
+// with LDS exchanges (hd_fft.hpp) and writes its result once.  Global loads
+// and stores are coalesced: consecutive lanes touch consecutive complex words.
+#include "hd_kcommon.hpp"
+
+namespace hd {
+
+// ---------------------------------------------------------------------------
+// Whole 1D convolution of one contiguous row per lane group, direct form
+// (Algorithms 1, 3-6): for each residue r < q,
+//   W_s   = sum_{t<P} zeta_{qm}^{r(tm+s)} f_{tm+s}      (zero where tm+s >= L)
+//   F     = fft_m(W) per input;  H = prod_a F_a         (mult, B = 1)
+//   h_j  += zeta_{qm}^{-rj} ifft_m(H)_{j mod m}          (j = tm+s < L)
+// and finally out_j = h_j / (qm).  With P = 2 the backward step is the
+// corrected form of Algorithm 6 (the second half carries zeta_{qm}^{-rj},
+// j = m+s, as eq. invStan requires).  The A forward transforms of a residue
+// run together (shared twiddles and barriers).
+template <typename T, int E, int P, int A>
+__global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
+  const int G = a.fd.G;
+  const int m = a.m;
+  const int slot = threadIdx.x / G;
+  const int g = threadIdx.x - slot * G;
+  const int64_t row = (int64_t)blockIdx.x * a.rows_per_block + slot;
+  const bool valid = row < a.nrows;
+  const int64_t L = a.L;
+  const int64_t qm = (int64_t)a.q * m;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
+  __syncthreads();
+
+  cpx<T> acc[P][E];
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
+
+  for (int r = 0; r < a.q; ++r) {
+    // exponents of zeta_{qm}^{r j} for j = t m + g + G e advance by r G per e
+    const int64_t st = ((int64_t)r * G) % qm;
+    cpx<T> w[A][E];
+#pragma unroll
+    for (int ai = 0; ai < A; ++ai)
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      int64_t ex = ((int64_t)r * (t * m + g)) % qm;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t j = (int64_t)t * m + g + G * e;
+        if (valid && j < L) {
+          const cpx<T> z = a.zqm.get(ex);
+#pragma unroll
+          for (int ai = 0; ai < A; ++ai) w[ai][e] = w[ai][e] + cmul(a.in[ai][row * a.in_stride + j], z);
+        }
+        ex += st;
+        if (ex >= qm) ex -= qm;
+      }
+    }
+    gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
+    cpx<T> prod[1][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      cpx<T> pr = w[0][e];
+#pragma unroll
+      for (int ai = 1; ai < A; ++ai) pr = cmul(pr, w[ai][e]);
+      prod[0][e] = pr;
+    }
+    gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      int64_t ex = ((int64_t)r * (t * m + g)) % qm;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        acc[t][e] = acc[t][e] + cmulc(prod[0][e], a.zqm.get(ex));
+        ex += st;
+        if (ex >= qm) ex -= qm;
+      }
+    }
+  }
+  if (valid) {
+    cpx<T>* dst = a.out + row * a.out_stride;
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t j = (int64_t)t * m + g + G * e;
+        if (j < L) dst[j] = cscale(acc[t][e], a.scale);
+      }
+  }
+}
+
+
+size_t lds_fused1d(int m, int ps, int rows_per_block, int A, int ntw, int tbytes) {
+  return ((size_t)xwords_rows(m, ps, rows_per_block, A) + ntw) * 2 * tbytes;
+}
+size_t lds_rows(int m, int ps, int rows_per_block, int A, int ntw, int tbytes) {
+  return ((size_t)xwords_rows(m, ps, rows_per_block, A) + ntw) * 2 * tbytes;
+}
+size_t lds_cols(int p, int S, int ntw, int tbytes) { return ((size_t)xwords_cols(p, S, 2) + ntw) * 2 * tbytes; }
+size_t lds_outer(int m, int S, int ntw, int tbytes) { return ((size_t)xwords_cols(m, S, 1) + ntw) * 2 * tbytes; }
+
+bool fft_fits(const FftDesc& d, int E) {
+  if ((int64_t)d.G * E != d.N) return false;
+  for (int i = 0; i < d.nst; ++i)
+    if (E % d.radix[i] != 0) return false;
+  return true;
+}
+
+template <typename T>
+hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_t s) {
+  const int nt = a.fd.G * a.rows_per_block;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N) return HD_BAD;
+  dim3 grid((unsigned)((a.nrows + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
+  const size_t lds = lds_fused1d(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
+#define F1(EE, PP, AA) \
+  if (E == EE && P == PP && A == AA) return go(k_fused1d<T, EE, PP, AA>, grid, block, lds, s, a);
+  F1(8, 1, 2) F1(8, 2, 2) F1(8, 1, 3) F1(8, 2, 3)
+  F1(16, 1, 2) F1(16, 2, 2) F1(16, 1, 3) F1(16, 2, 3)
+  F1(24, 1, 2) F1(24, 2, 2) F1(24, 1, 3) F1(24, 2, 3)
+#undef F1
+  return HD_BAD;
+}
+
+#define HD_INST(T) \
+  template hipError_t launch_fused1d<T>(const FusedArgs<T>&, int, int, int, hipStream_t);
+HD_INST(float)
+HD_INST(double)
+#undef HD_INST
+
+}  // namespace hd

@@ -1,0 +1,210 @@
+// hd_k_multi.hip -- the three passes of the inner-loop form (Sec. 6.1).
+#include "hd_kcommon.hpp"
+
+namespace hd {
+
+// ---------------------------------------------------------------------------
+// Inner form, pass 1 (Sec. 6.1, forward): columns s of the p x m view.  For
+// each residue v the column is scaled by zeta_q^{vt} and p-point transformed;
+// residues are taken two at a time (shared twiddles and barriers).
+template <typename T, int E, int NT>
+__device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const cpx<T> (&x)[E], int dv0, int g,
+                                                  int s, int64_t row, int ai, const TwLds<T>& tw,
+                                                  const Xchg<T>& xb) {
+  const int G = a.fd.G, m = a.m, p = a.p, q = a.q;
+  cpx<T> y[NT][E];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int v = a.v0 + dv0 + n;
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[n][e] = cmul(x[e], a.zq[(v * (g + G * e)) % q]);
+  }
+  gfft_any<T, E, +1, NT, kCtCols>(y, g, a.fd, tw, xb);
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    cpx<T>* dst = a.work[ai] + ((row * a.D + dv0 + n) * p) * (int64_t)m + s;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[(int64_t)(g + G * e) * m] = y[n][e];
+  }
+}
+
+template <typename T, int E>
+__global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
+  const int S = a.S, G = a.fd.G, m = a.m;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int s = blockIdx.x * S + c;
+  const int64_t row = blockIdx.y;
+  const int ai = blockIdx.z;
+  const cpx<T>* src = a.in[ai] + row * a.in_stride;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + c, S, 30, a.p * S};
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
+
+  cpx<T> x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t j = (int64_t)(g + G * e) * m + s;
+    x[e] = (j < a.L) ? src[j] : czero<T>();
+  }
+  __syncthreads();
+  int dv = 0;
+  for (; dv + 2 <= a.D; dv += 2) cols_fwd_residues<T, E, 2>(a, x, dv, g, s, row, ai, tw, xb);
+  if (dv < a.D) cols_fwd_residues<T, E, 1>(a, x, dv, g, s, row, ai, tw, xb);
+}
+
+// Inner form, pass 2: m-point convolution rows.  The A rows are loaded
+// together and transformed together.
+template <typename T, int E, int A>
+__global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
+  const int G = a.fd.G, m = a.m, p = a.p;
+  const int slot = threadIdx.x / G;
+  const int g = threadIdx.x - slot * G;
+  const int64_t R2 = (int64_t)blockIdx.x * a.rows_per_block + slot;
+  const bool valid = R2 < a.nrows;
+  const int u = (int)(R2 % p);
+  const int dv = (int)((R2 / p) % a.D);
+  const int64_t r = (int64_t)u * a.n + a.v0 + dv;
+  const int64_t qm = a.qm;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
+
+  cpx<T> x[A][E];
+#pragma unroll
+  for (int ai = 0; ai < A; ++ai) {
+    const cpx<T>* src = a.work[ai] + R2 * m;
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[ai][e] = valid ? src[g + G * e] : czero<T>();
+  }
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
+  cpx<T> z[E];
+  {
+    int64_t ex = (r * g) % qm;
+    const int64_t st = (r * G) % qm;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      z[e] = a.zqm.get(ex);
+      ex += st;
+      if (ex >= qm) ex -= qm;
+    }
+  }
+#pragma unroll
+  for (int ai = 0; ai < A; ++ai)
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[ai][e] = cmul(x[ai][e], z[e]);
+  __syncthreads();
+  gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
+  cpx<T> prod[1][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cpx<T> pr = x[0][e];
+#pragma unroll
+    for (int ai = 1; ai < A; ++ai) pr = cmul(pr, x[ai][e]);
+    prod[0][e] = pr;
+  }
+  gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
+  if (valid) {
+    cpx<T>* dst = a.work[0] + R2 * m;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[g + G * e] = cmulc(prod[0][e], z[e]);
+  }
+}
+
+
+
+// Inner form, pass 3 (eq. invInner): columns back to the p x m view.
+template <typename T, int E, int NT>
+__device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T> (&acc)[E], int dv0, int g, int s,
+                                                  int64_t row, const TwLds<T>& tw, const Xchg<T>& xb) {
+  const int G = a.fd.G, m = a.m, p = a.p, q = a.q;
+  cpx<T> y[NT][E];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const cpx<T>* src = a.work + ((row * a.D + dv0 + n) * p) * (int64_t)m + s;
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[n][e] = src[(int64_t)(g + G * e) * m];
+  }
+  gfft_any<T, E, -1, NT, kCtCols>(y, g, a.fd, tw, xb);
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int v = a.v0 + dv0 + n;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = acc[e] + cmulc(y[n][e], a.zq[(v * (g + G * e)) % q]);
+  }
+}
+
+template <typename T, int E>
+__global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
+  const int S = a.S, G = a.fd.G, m = a.m;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int s = blockIdx.x * S + c;
+  const int64_t row = blockIdx.y;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + c, S, 30, a.p * S};
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
+  __syncthreads();
+
+  cpx<T> acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = czero<T>();
+  int dv = 0;
+  for (; dv + 2 <= a.D; dv += 2) cols_bwd_residues<T, E, 2>(a, acc, dv, g, s, row, tw, xb);
+  if (dv < a.D) cols_bwd_residues<T, E, 1>(a, acc, dv, g, s, row, tw, xb);
+  cpx<T>* dst = a.out + row * a.out_stride;
+  double* acc64 = a.acc ? a.acc + 2 * row * a.out_stride : nullptr;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t j = (int64_t)(g + G * e) * m + s;
+    if (j < a.L) acc_store(dst, acc64, a.acc_mode, j, acc[e], a.scale);
+  }
+}
+
+template <typename T>
+hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s) {
+  const int nt = a.S * a.fd.G;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 || a.nrows > 65535) return HD_BAD;
+  dim3 grid(a.m / a.S, (unsigned)a.nrows, A), block(nt);
+  const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
+#define C1(EE) \
+  if (E == EE) return go(k_cols_fwd<T, EE>, grid, block, lds, s, a);
+  C1(1) C1(2) C1(4) C1(8) C1(16) C1(24)
+#undef C1
+  return HD_BAD;
+}
+
+template <typename T>
+hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s) {
+  const int nt = a.fd.G * a.rows_per_block;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N) return HD_BAD;
+  dim3 grid((unsigned)((a.nrows + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
+  const size_t lds = lds_rows(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
+#define R1(EE, AA) \
+  if (E == EE && A == AA) return go(k_rows_conv<T, EE, AA>, grid, block, lds, s, a);
+  R1(8, 2) R1(8, 3) R1(16, 2) R1(16, 3) R1(24, 2) R1(24, 3) R1(32, 2) R1(32, 3)
+#undef R1
+  return HD_BAD;
+}
+
+template <typename T>
+hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s) {
+  const int nt = a.S * a.fd.G;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 || a.nrows > 65535) return HD_BAD;
+  dim3 grid(a.m / a.S, (unsigned)a.nrows), block(nt);
+  const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
+#define C1(EE) \
+  if (E == EE) return go(k_cols_bwd<T, EE>, grid, block, lds, s, a);
+  C1(1) C1(2) C1(4) C1(8) C1(16) C1(24)
+#undef C1
+  return HD_BAD;
+}
+
+#define HD_INST(T) \
+  template hipError_t launch_cols_fwd<T>(const ColFwdArgs<T>&, int, int, hipStream_t); \
+  template hipError_t launch_rows_conv<T>(const RowConvArgs<T>&, int, int, hipStream_t); \
+  template hipError_t launch_cols_bwd<T>(const ColBwdArgs<T>&, int, hipStream_t);
+HD_INST(float)
+HD_INST(double)
+#undef HD_INST
+
+}  // namespace hd

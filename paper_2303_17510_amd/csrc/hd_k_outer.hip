@@ -1,0 +1,174 @@
+// hd_k_outer.hip -- outer dimensions of 2D/3D convolutions (Sec. 5) and the
+// explicit method's padding copies.
+#include "hd_kcommon.hpp"
+
+namespace hd {
+
+// ---------------------------------------------------------------------------
+// Outer dimension, direct form, forward: S adjacent columns per workgroup.
+template <typename T, int E, int P>
+__global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
+  const int S = a.S, G = a.fd.G, m = a.m;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int64_t col = (int64_t)blockIdx.x * S + c;
+  const bool valid = col < a.R;
+  const int64_t b = blockIdx.y;
+  const int ai = blockIdx.z;
+  const int64_t R = a.R;
+  const int64_t qm = (int64_t)a.q * m;
+  const cpx<T>* src = a.in[ai] + b * a.in_bstride + col;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + c, S, 30, m * S};
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
+
+  cpx<T> x[P][E];
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t j = (int64_t)t * m + g + G * e;
+      x[t][e] = (valid && j < a.L) ? src[j * R] : czero<T>();
+    }
+  __syncthreads();
+  for (int dr = 0; dr < a.D; ++dr) {
+    const int64_t r = a.r0 + dr;
+    cpx<T> w[1][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      int64_t ex = (r * (t * m + g)) % qm;
+      const int64_t st = (r * G) % qm;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        w[0][e] = w[0][e] + cmul(x[t][e], a.zqm.get(ex));
+        ex += st;
+        if (ex >= qm) ex -= qm;
+      }
+    }
+    gfft_any<T, E, +1, 1, kCtOuter>(w, g, a.fd, tw, xb);
+    if (valid) {
+      cpx<T>* dst = a.out[ai] + ((b * a.D + dr) * m) * R + col;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[(int64_t)(g + G * e) * R] = w[0][e];
+    }
+  }
+}
+
+// Outer dimension, direct form, backward and accumulation over residues.
+template <typename T, int E, int P>
+__global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
+  const int S = a.S, G = a.fd.G, m = a.m;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int64_t col = (int64_t)blockIdx.x * S + c;
+  const bool valid = col < a.R;
+  const int64_t b = blockIdx.y;
+  const int64_t R = a.R;
+  const int64_t qm = (int64_t)a.q * m;
+  cpx<T>* lds = smem_as<T>();
+  Xchg<T> xb{lds + c, S, 30, m * S};
+  const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
+  __syncthreads();
+
+  cpx<T> acc[P][E];
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
+  for (int dr = 0; dr < a.D; ++dr) {
+    const int64_t r = a.r0 + dr;
+    const cpx<T>* src = a.y + ((b * a.D + dr) * m) * R + col;
+    cpx<T> y[1][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[0][e] = valid ? src[(int64_t)(g + G * e) * R] : czero<T>();
+    gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      int64_t ex = (r * (t * m + g)) % qm;
+      const int64_t st = (r * G) % qm;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        acc[t][e] = acc[t][e] + cmulc(y[0][e], a.zqm.get(ex));
+        ex += st;
+        if (ex >= qm) ex -= qm;
+      }
+    }
+  }
+  if (!valid) return;
+  cpx<T>* dst = a.out + b * a.out_bstride + col;
+  double* acc64 = a.acc ? a.acc + 2 * (b * a.out_bstride + col) : nullptr;
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t j = (int64_t)t * m + g + G * e;
+      if (j < a.L) acc_store(dst, acc64, a.acc_mode, j * R, acc[t][e], a.scale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
+  // one destination row (i0, i1) per blockIdx.y step; lanes run along i2
+  const int64_t* D = a.pad ? a.N : a.L;
+  const int64_t* Sx = a.pad ? a.L : a.N;
+  const int64_t rows = D[0] * D[1];
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int64_t i1 = row % D[1], i0 = row / D[1];
+    const bool in_src = i0 < Sx[0] && i1 < Sx[1];
+    const cpx<T>* src = a.src + (i0 * Sx[1] + i1) * Sx[2];
+    cpx<T>* dst = a.dst + row * D[2];
+    for (int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i2 < D[2];
+         i2 += (int64_t)gridDim.x * blockDim.x)
+      dst[i2] = (in_src && i2 < Sx[2]) ? src[i2] : czero<T>();
+  }
+}
+
+template <typename T>
+hipError_t launch_outer_fwd(const OuterFwdArgs<T>& a, int E, int P, int A, hipStream_t s) {
+  const int nt = a.S * a.fd.G;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb > 65535) return HD_BAD;
+  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)a.nb, A), block(nt);
+  const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
+#define O1(EE, PP) \
+  if (E == EE && P == PP) return go(k_outer_fwd<T, EE, PP>, grid, block, lds, s, a);
+  O1(8, 1) O1(8, 2) O1(16, 1) O1(16, 2) O1(24, 1) O1(24, 2) O1(32, 1) O1(32, 2)
+#undef O1
+  return HD_BAD;
+}
+
+template <typename T>
+hipError_t launch_outer_bwd(const OuterBwdArgs<T>& a, int E, int P, hipStream_t s) {
+  const int nt = a.S * a.fd.G;
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb > 65535) return HD_BAD;
+  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)a.nb), block(nt);
+  const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
+#define O1(EE, PP) \
+  if (E == EE && P == PP) return go(k_outer_bwd<T, EE, PP>, grid, block, lds, s, a);
+  O1(8, 1) O1(8, 2) O1(16, 1) O1(16, 2) O1(24, 1) O1(24, 2) O1(32, 1) O1(32, 2)
+#undef O1
+  return HD_BAD;
+}
+
+template <typename T>
+hipError_t launch_box_copy(const BoxCopyArgs<T>& a, hipStream_t s) {
+  const int64_t* D = a.pad ? a.N : a.L;
+  const int64_t rows = D[0] * D[1];
+  int64_t bx = (D[2] + 255) / 256;
+  if (bx > 4096) bx = 4096;
+  int64_t by = rows < 65535 ? rows : 65535;
+  hipLaunchKernelGGL(k_box_copy<T>, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+#define HD_INST(T) \
+  template hipError_t launch_outer_fwd<T>(const OuterFwdArgs<T>&, int, int, int, hipStream_t); \
+  template hipError_t launch_outer_bwd<T>(const OuterBwdArgs<T>&, int, int, hipStream_t); \
+  template hipError_t launch_box_copy<T>(const BoxCopyArgs<T>&, hipStream_t);
+HD_INST(float)
+HD_INST(double)
+#undef HD_INST
+
+}  // namespace hd

@@ -1,0 +1,57 @@
+// hd_kcommon.hpp -- helpers shared by the kernel translation units.
+#pragma once
+#include "hd_engine.hpp"
+
+namespace hd {
+
+extern __shared__ __align__(16) char hd_smem[];
+
+template <typename T>
+__device__ __forceinline__ cpx<T>* smem_as() {
+  return reinterpret_cast<cpx<T>*>(hd_smem);
+}
+
+// Row exchange area: one pad slot every 2^ps points.
+__host__ __device__ constexpr int row_pad(int m, int ps) { return m + (m >> ps); }
+
+// LDS words (complex) of each kernel's exchange area; the transform's twiddle
+// table follows it.
+__host__ __device__ constexpr int xwords_rows(int m, int ps, int rows_per_block, int nt) {
+  return rows_per_block * nt * row_pad(m, ps);
+}
+__host__ __device__ constexpr int xwords_cols(int p, int S, int nt) { return nt * p * S; }
+
+template <typename T>
+__device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, int64_t i, cpx<T> v, T scale) {
+  if (mode == ACC_WRITE) {
+    out[i] = cscale(v, scale);
+  } else if (mode == ACC_FIRST) {
+    acc[2 * i] = (double)v.x;
+    acc[2 * i + 1] = (double)v.y;
+  } else if (mode == ACC_ADD) {
+    acc[2 * i] += (double)v.x;
+    acc[2 * i + 1] += (double)v.y;
+  } else {
+    const double sx = acc[2 * i] + (double)v.x, sy = acc[2 * i + 1] + (double)v.y;
+    out[i] = mk(T(sx * (double)scale), T(sy * (double)scale));
+  }
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename K, typename Args>
+static hipError_t go(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, const Args& a) {
+  hipError_t e = allow_lds(kernel, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+#define HD_BAD hipErrorInvalidConfiguration
+
+}  // namespace hd

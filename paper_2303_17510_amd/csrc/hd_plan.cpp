@@ -72,6 +72,17 @@ bool make_fft_desc(int64_t N, int E, FftDesc* d) {
   d->kb = 0;
   while ((int64_t(1) << (2 * d->kb)) < N) ++d->kb;
   d->ntw = (1 << d->kb) + (int)((N + (int64_t(1) << d->kb) - 1) >> d->kb);
+  int64_t Ns = 1, off = 0;
+  for (int s = 0; s < st; ++s) {
+    d->twoff[s] = (int)off;
+    if (Ns > 1) off += Ns * (d->radix[s] - 1);
+    Ns *= d->radix[s];
+  }
+  d->ntw_stage = (int)std::max<int64_t>(off, 1);
+  d->twmode = 0;
+  d->ps = 3;
+  if (st > 0 && d->radix[0] == 16) d->ps = 4;
+  if (st > 0 && d->radix[0] == 32) d->ps = 5;
   return true;
 }
 
@@ -142,7 +153,11 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->E_m == 0 && !pick_e_row(dp->m, fused, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
       if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("row points per lane must be 8, 16, 24 or 32");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
-      auto need = [&](int r) { return ((size_t)r * A * (dp->m + (dp->m >> 4)) + dp->fd_m.ntw) * cb; };
+      auto need = [&](int r) {
+        return ((size_t)r * A * (dp->m + (dp->m >> dp->fd_m.ps)) + tw_words(dp->fd_m)) * cb;
+      };
+      dp->fd_m.twmode = dp->tw_pref == 2;
+      if (dp->tw_pref == 0 && need(1) > 81920) dp->fd_m.twmode = 0;
       if (dp->rows_per_block == 0) {
         int rpb = std::max(1, 256 / dp->fd_m.G);
         while (rpb > 1 && need(rpb) > 65536) rpb /= 2;
@@ -155,7 +170,9 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->E_p == 0 && !pick_e_col(dp->p, &dp->E_p)) return fail("unsupported p for the column passes");
       if (!in_set(dp->E_p, {1, 2, 4, 8, 16, 24})) return fail("column points per lane must be 1, 2, 4, 8, 16 or 24");
       if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p with these points per lane");
-      auto cneed = [&](int S) { return ((size_t)2 * dp->p * S + dp->fd_p.ntw) * cb; };
+      auto cneed = [&](int S) { return ((size_t)2 * dp->p * S + tw_words(dp->fd_p)) * cb; };
+      dp->fd_p.twmode = dp->tw_pref == 2;
+      if (dp->tw_pref == 0 && cneed(std::min(16, (int)dp->m)) > 81920) dp->fd_p.twmode = 0;
       if (dp->S == 0) {
         int S = 64;
         while (S > 1 && (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || cneed(S) > 81920)) S /= 2;
@@ -173,7 +190,9 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->E_m == 0) dp->E_m = dp->m % 3 == 0 ? 24 : (dp->m < 16 ? 8 : (dp->m <= 1024 ? 16 : 32));
       if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("outer points per lane must be 8, 16, 24 or 32");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
-      auto oneed = [&](int S) { return ((size_t)dp->m * S + dp->fd_m.ntw) * cb; };
+      auto oneed = [&](int S) { return ((size_t)dp->m * S + tw_words(dp->fd_m)) * cb; };
+      dp->fd_m.twmode = dp->tw_pref == 2;
+      if (dp->tw_pref == 0 && oneed(8) > 128 * 1024) dp->fd_m.twmode = 0;
       if (dp->S == 0) {
         int S = std::min(pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G)), 64);
         while (S > 1 && oneed(S) > 128 * 1024) S /= 2;
@@ -279,6 +298,25 @@ std::vector<double> fft_table(const FftDesc& d) {
     root(d.N, h * K, &re, &im);
     v.push_back(re);
     v.push_back(im);
+  }
+  // per-stage tables: w_{Ns R}^{k i}, k < Ns, 1 <= i < R
+  int64_t Ns = 1;
+  size_t base = v.size();
+  for (int s = 0; s < d.nst; ++s) {
+    const int R = d.radix[s];
+    if (Ns > 1)
+      for (int64_t k = 0; k < Ns; ++k)
+        for (int i = 1; i < R; ++i) {
+          double re, im;
+          root(Ns * R, (k * i) % (Ns * R), &re, &im);
+          v.push_back(re);
+          v.push_back(im);
+        }
+    Ns *= R;
+  }
+  if (v.size() == base) {  // no twiddled stage: one placeholder entry
+    v.push_back(1.0);
+    v.push_back(0.0);
   }
   return v;
 }

@@ -34,6 +34,7 @@ struct DimPlan {
   int E_p = 0;
   int S = 0;                  // columns per workgroup (column / outer kernels)
   int rows_per_block = 0;     // rows per workgroup (fused / row kernels)
+  int tw_pref = 0;            // twiddles: 0 choose, 1 two-level table, 2 per-stage tables
 };
 
 // Paper's geometry rules for a given m (Algorithm 1, Sec. 2.1, Sec. 6.1):

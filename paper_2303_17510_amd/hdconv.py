@@ -59,7 +59,8 @@ class Plan:
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
-                 host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None):
+                 host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
+                 twiddles=None):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
@@ -79,7 +80,8 @@ class Plan:
             opt.p[d] = v
         for d, v in enumerate(_tup(D, dims)):
             opt.D[d] = v
-        for name, val in (("E_m", E_m), ("E_p", E_p), ("S", S), ("rows_per_block", rows_per_block)):
+        for name, val in (("E_m", E_m), ("E_p", E_p), ("S", S), ("rows_per_block", rows_per_block),
+                          ("twiddles", twiddles)):
             for d, v in enumerate(_tup(val, dims)):
                 getattr(opt, name)[d] = v
         vs = variant if isinstance(variant, (list, tuple)) else [variant] * dims
@@ -103,7 +105,7 @@ class Plan:
             di = out.dim[d]
             dims.append({"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
                          "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p,
-                         "S": di.S, "rows_per_block": di.rows_per_block})
+                         "S": di.S, "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p})
         return {"dims": dims, "A": out.A, "B": out.B, "dtype": "c64" if out.dtype == 0 else "c128",
                 "method": {1: "hybrid", 2: "explicit"}.get(out.method, "auto"),
                 "npad": list(out.npad)[: out.dims], "workspace_bytes": out.workspace_bytes,
