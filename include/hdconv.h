@@ -74,6 +74,7 @@ typedef struct hdconv_options {
   int E_p[3];        /* points per lane of the p-point transform (0: choose)    */
   int S[3];          /* columns per workgroup of column/outer kernels (0: choose) */
   int rows_per_block[3]; /* rows per workgroup of row kernels (0: choose)       */
+  int twiddles[3];   /* FFT twiddles: 0 choose, 1 two-level root table, 2 exact per-stage tables */
   int reserved[8];   /* zero                                                    */
 } hdconv_options;
 
@@ -85,6 +86,7 @@ typedef struct hdconv_dim_info {
   int E_m, E_p;      /* points per lane of the m- and p-point transforms        */
   int S;             /* columns per workgroup (column / outer kernels)          */
   int rows_per_block;/* rows per workgroup (row kernels)                        */
+  int tw_m, tw_p;    /* twiddle mode of the m- and p-point transforms (1 two-level, 2 per-stage) */
 } hdconv_dim_info_t;
 
 typedef struct hdconv_plan_info {
