@@ -147,6 +147,39 @@ def leg(wl, dtype, method, steps, warmup):
     return r, xs, out
 
 
+def batched_leg(steps, warmup, dtype="c64", count=4096):
+    """4096 independent convolutions, L log-uniform in [64, 65536], M = 2L, one graph launch."""
+    import numpy as np
+    import torch
+    from paper_2303_17510_amd import BatchPlan, synth
+    Ls = [int(v) for v in synth.batched_lengths(count=count)]
+    tot = sum(Ls)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    big = [torch.from_numpy(synth.unit_disk((tot,), synth.seed_for(2, a)).astype(npdt)).cuda() for a in range(2)]
+    out_big = torch.empty_like(big[0])
+    offs = np.concatenate([[0], np.cumsum(Ls)])
+    ins = [[big[a][offs[i]:offs[i + 1]] for a in range(2)] for i in range(count)]
+    outs = [out_big[offs[i]:offs[i + 1]] for i in range(count)]
+    with BatchPlan(Ls, dtype=dtype) as bp:
+        groups = bp.groups()
+        for _ in range(max(2, warmup)):   # the second execute captures the graph
+            bp.execute(ins, outs)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            bp.execute(ins, outs)
+        t1.record()
+        torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    w = 8 if dtype == "c64" else 16
+    return {"dtype": dtype, "method": "hybrid, batched graph", "convolutions": count, "outputs": tot,
+            "ms": ms, "outputs_per_s": tot / (ms * 1e-3),
+            "compulsory_frac": 3 * w * tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "groups": [(g["variant"], g["m"], g["p"], g["q"], g["count"]) for g in groups]}
+
+
 def cpu_baseline(wl, xs_by_dtype, outs_by_dtype, budget_s):
     """Time the FP64 oracle (explicit FFT convolution) on the workload; errors of the GPU results."""
     import oracle
@@ -236,9 +269,11 @@ def main():
             compare["L1500000_hybrid_c64"] = r
             r, _, _ = leg(workload("c2_1p5m"), "c64", "explicit", max(10, args.steps // 4), 5)
             compare["L1500000_explicit_c64"] = r
+            compare["batched_4096_c64"] = batched_leg(max(10, args.steps // 10), 3)
         for k, v in compare.items():
+            dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
-                                                                     v["dominant"]["kernel"], v["dominant"]["frac"]))
+                                                                     dom["kernel"], dom["frac"]))
     cpu = None
     errs = {}
     if not args.no_cpu:

@@ -60,7 +60,8 @@ enum {
 
 /* plan flags */
 enum {
-  HDCONV_PLAN_HOST_ONLY = 1 /* plan geometry only: no device memory, cannot execute */
+  HDCONV_PLAN_HOST_ONLY = 1, /* plan geometry only: no device memory, cannot execute */
+  HDCONV_BATCH_NO_GRAPH = 2  /* batched plans: launch eagerly on every execute      */
 };
 
 typedef struct hdconv_options {
@@ -135,6 +136,31 @@ void hdconv_destroy(void* plan);
  * MULTIPASS for the inner form). */
 int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner,
                     hdconv_dim_info_t* out);
+
+/* Batched plans: `count` independent one-dimensional convolutions of uneven
+ * length (dims = 1), L[i] and M[i] each as in hdconv_plan, all with the same
+ * A, B and dtype.  Convolutions whose planned shape (variant, m, p, q and
+ * kernel widths) coincides form one group; each group runs as one set of
+ * launches over a device table of per-row pointers and lengths, groups run
+ * on parallel branches (four side streams forked from and joined to the
+ * execute stream), and from the second execute on the whole batch is one
+ * hipGraph launch.  Allocates per-group tables, workspace, a device task
+ * table and a pinned staging copy of it.  NULL on error. */
+void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
+                          const hdconv_options* opt);
+
+/* inputs: count*A device pointers (convolution i uses inputs[i*A + a]);
+ * outputs: count*B device pointers; each of L[i] words.  Uploads the task
+ * table (asynchronously, on `stream`) and launches; the pinned staging
+ * buffer is reused, so an execute waits for the previous execute's upload. */
+int hdconv_execute_batched(void* batch, const void* const* inputs, void* const* outputs, void* stream);
+
+/* Groups of a batched plan: shapes into groups[0..cap), member counts into
+ * counts[0..cap), and the number of groups into *ngroups. */
+int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups);
+
+/* Release a batched plan (synchronises the device first).  NULL is ignored. */
+void hdconv_batch_destroy(void* batch);
 
 /* Per-launch timing.  hdconv_profile_begin(plan, n) creates HIP events for
  * the next n executes of `plan`; each of those executes records an event

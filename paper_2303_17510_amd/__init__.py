@@ -5,6 +5,6 @@ Murasko & Bowman, "Hybrid Dealiasing of Complex Convolutions" (arXiv
 include/hdconv.h) with a thin Python front end.  Importing this package does
 not load the library; the first plan does, and raises if it is not built.
 """
-from .hdconv import Plan, convolve, geometry, dtype_code  # noqa: F401
+from .hdconv import BatchPlan, Plan, convolve, dtype_code, geometry  # noqa: F401
 
-__all__ = ["Plan", "convolve", "geometry", "dtype_code"]
+__all__ = ["Plan", "BatchPlan", "convolve", "geometry", "dtype_code"]

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENODEV = 0, -1, -2, -3, -4, -5
 METHOD_AUTO, METHOD_HYBRID, METHOD_EXPLICIT = 0, 1, 2
 VARIANT_AUTO, VARIANT_FUSED, VARIANT_MULTIPASS, VARIANT_OUTER = 0, 1, 2, 3
 PLAN_HOST_ONLY = 1
+BATCH_NO_GRAPH = 2
 
 VARIANT_NAMES = {0: "auto", 1: "fused", 2: "multipass", 3: "outer"}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENODEV"}
@@ -65,6 +66,13 @@ SIGNATURES = {
     "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hdconv_destroy": (None, [ctypes.c_void_p]),
     "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),
+    "hdconv_plan_batched": (ctypes.c_void_p, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i64, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]),
+    "hdconv_execute_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "hdconv_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DimInfo), ctypes.POINTER(_i64),
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "hdconv_batch_destroy": (None, [ctypes.c_void_p]),
     "hdconv_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hdconv_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]),

@@ -6,8 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hdconv.h"
@@ -69,6 +71,7 @@ struct Plan {
   void* lvl[2][kMaxA] = {{nullptr}};                  // outer-level buffers W_d
   void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
   double* acc64 = nullptr;                            // multi-block accumulator
+  int64_t batch_rows = 1;                             // rows of a batched group
   int launches = 0;
   // per-launch event timing (hdconv_profile_begin / hdconv_profile_end)
   struct Prof {
@@ -317,7 +320,7 @@ static int alloc_workspace(Plan* P) {
     for (int d = 0; d < P->dims; ++d) n *= (size_t)P->npad[d];
     for (int a = 0; a < P->A; ++a) want.push_back({&P->pad_in[a], n * w});
   }
-  size_t nb = 1;
+  size_t nb = (size_t)P->batch_rows;  // independent rows (batched groups), else 1
   for (int d = 0; d + 1 < P->dims; ++d) {
     size_t rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)Le[e];
@@ -368,16 +371,19 @@ static RootTable<T> rtab(const Plan* P, int d) {
   return r;
 }
 
-// rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L
+// rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L,
+// or (tasks != NULL) nrows independent rows described by a device task table
 template <typename T>
-static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s) {
+static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s,
+                    const RowTask<T>* tasks = nullptr) {
   const int d = P->dims - 1;
   const DimPlan& dp = P->dp[d];
   const int A = P->A;
   hipError_t e;
   if (dp.variant == VAR_FUSED) {
     FusedArgs<T> a{};
-    for (int i = 0; i < A; ++i) a.in[i] = in[i];
+    a.tasks = tasks;
+    for (int i = 0; i < A; ++i) a.in[i] = in ? in[i] : nullptr;
     a.out = out;
     a.in_stride = a.out_stride = dp.L;
     a.nrows = nrows;
@@ -401,8 +407,9 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     const int v0 = (int)(blk * dp.D);
     const int D = (int)std::min<int64_t>(dp.D, dp.n - v0);
     ColFwdArgs<T> k1{};
+    k1.tasks = tasks;
     for (int i = 0; i < A; ++i) {
-      k1.in[i] = in[i];
+      k1.in[i] = in ? in[i] : nullptr;
       k1.work[i] = (cpx<T>*)P->rowwork[i];
     }
     k1.in_stride = dp.L;
@@ -444,6 +451,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     if (e != hipSuccess) return hip_err(e, "rows_conv launch");
 
     ColBwdArgs<T> k3{};
+    k3.tasks = tasks;
     k3.work = (const cpx<T>*)P->rowwork[0];
     k3.out = out;
     k3.acc = P->acc64;
@@ -845,5 +853,323 @@ void hdconv_destroy(void* plan) {
   if (plan) prof_release((Plan*)plan);
   free_plan((Plan*)plan);
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched plans: many independent 1D convolutions of uneven length
+
+namespace {
+constexpr int kSideStreams = 4;
+
+struct GroupKey {
+  int variant;
+  int64_t m, p, n, q;
+  int E_m, E_p, S, rpb;
+  bool operator<(const GroupKey& o) const {
+    return std::tie(variant, m, p, n, q, E_m, E_p, S, rpb) <
+           std::tie(o.variant, o.m, o.p, o.n, o.q, o.E_m, o.E_p, o.S, o.rpb);
+  }
+};
+}  // namespace
+
+struct Batch {
+  int A = 0, B = 0, dtype = 0, flags = 0, device = -1;
+  int64_t count = 0;
+  std::vector<int64_t> L, M;
+  std::vector<Plan*> groups;                  // one plan per shape, rows = its members
+  std::vector<std::vector<int64_t>> members;  // convolution indices per group
+  std::vector<size_t> task_off;               // byte offset of each group's task table
+  char* task_dev = nullptr;
+  char* task_host = nullptr;  // pinned staging of the task tables
+  size_t task_bytes = 0;
+  hipEvent_t copied = nullptr;
+  bool copy_pending = false;
+  hipStream_t side[kSideStreams] = {};
+  hipStream_t capture = nullptr;  // stream the graph is captured on
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  hipGraphExec_t exec = nullptr;
+  int executes = 0;
+};
+
+// A one-dimensional plan for `rows` independent rows sharing the shape dp.
+static Plan* make_group_plan(int A, int B, int dtype, const DimPlan& dp, int64_t rows, int device) {
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) {
+    set_err(HDCONV_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  P->dims = 1;
+  P->A = A;
+  P->B = B;
+  P->dtype = dtype;
+  P->method = HDCONV_METHOD_HYBRID;
+  P->L[0] = dp.L;
+  P->M[0] = dp.M;
+  P->dp[0] = dp;
+  P->batch_rows = rows;
+  P->device = device;
+  if (alloc_tables(P) != HDCONV_OK || alloc_workspace(P) != HDCONV_OK) {
+    free_plan(P);
+    return nullptr;
+  }
+  plan_traffic(P, &P->launches);
+  return P;
+}
+
+static void free_batch(Batch* Bt) {
+  if (!Bt) return;
+  (void)hipDeviceSynchronize();
+  for (Plan* P : Bt->groups) free_plan(P);
+  if (Bt->exec) (void)hipGraphExecDestroy(Bt->exec);
+  for (hipEvent_t e : Bt->joins) (void)hipEventDestroy(e);
+  if (Bt->fork) (void)hipEventDestroy(Bt->fork);
+  if (Bt->copied) (void)hipEventDestroy(Bt->copied);
+  for (hipStream_t s : Bt->side)
+    if (s) (void)hipStreamDestroy(s);
+  if (Bt->capture) (void)hipStreamDestroy(Bt->capture);
+  if (Bt->task_dev) (void)hipFree(Bt->task_dev);
+  if (Bt->task_host) (void)hipHostFree(Bt->task_host);
+  delete Bt;
+}
+
+// Launch every group: fork from `s` onto the side streams, join back.
+template <typename T>
+static int issue_batch(Batch* Bt, hipStream_t s) {
+  hipError_t e = hipEventRecord(Bt->fork, s);
+  if (e != hipSuccess) return hip_err(e, "hipEventRecord(fork)");
+  for (size_t g = 0; g < Bt->groups.size(); ++g) {
+    hipStream_t hs = Bt->side[g % kSideStreams];
+    if ((e = hipStreamWaitEvent(hs, Bt->fork, 0)) != hipSuccess) return hip_err(e, "hipStreamWaitEvent");
+    const RowTask<T>* tasks = (const RowTask<T>*)(Bt->task_dev + Bt->task_off[g]);
+    int rc = run_rows<T>(Bt->groups[g], nullptr, nullptr, (int64_t)Bt->members[g].size(), hs, tasks);
+    if (rc != HDCONV_OK) return rc;
+    if ((e = hipEventRecord(Bt->joins[g], hs)) != hipSuccess) return hip_err(e, "hipEventRecord(join)");
+  }
+  for (size_t g = 0; g < Bt->groups.size(); ++g)
+    if ((e = hipStreamWaitEvent(s, Bt->joins[g], 0)) != hipSuccess) return hip_err(e, "hipStreamWaitEvent");
+  return HDCONV_OK;
+}
+
+template <typename T>
+static void fill_tasks(Batch* Bt, const void* const* inputs, void* const* outputs) {
+  for (size_t g = 0; g < Bt->groups.size(); ++g) {
+    RowTask<T>* t = (RowTask<T>*)(Bt->task_host + Bt->task_off[g]);
+    for (size_t k = 0; k < Bt->members[g].size(); ++k) {
+      const int64_t i = Bt->members[g][k];
+      RowTask<T> r{};
+      for (int a = 0; a < Bt->A; ++a) r.in[a] = (const cpx<T>*)inputs[i * Bt->A + a];
+      r.out = (cpx<T>*)outputs[i * Bt->B];
+      r.L = Bt->L[i];
+      t[k] = r;
+    }
+  }
+}
+
+template <typename T>
+static int run_batched(Batch* Bt, const void* const* inputs, void* const* outputs, hipStream_t s) {
+  hipError_t e;
+  if (Bt->copy_pending) {  // the staging buffer is reused: wait for the previous upload
+    if ((e = hipEventSynchronize(Bt->copied)) != hipSuccess) return hip_err(e, "hipEventSynchronize");
+    Bt->copy_pending = false;
+  }
+  fill_tasks<T>(Bt, inputs, outputs);
+  if ((e = hipMemcpyAsync(Bt->task_dev, Bt->task_host, Bt->task_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_err(e, "hipMemcpyAsync(tasks)");
+  if ((e = hipEventRecord(Bt->copied, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+  Bt->copy_pending = true;
+  const bool graph = !(Bt->flags & HDCONV_BATCH_NO_GRAPH);
+  // the first execute runs eagerly (kernels loaded, LDS limits granted);
+  // the second captures the launches into a graph that later executes replay
+  if (!graph || Bt->executes == 0) {
+    Bt->executes++;
+    return issue_batch<T>(Bt, s);
+  }
+  if (!Bt->exec) {
+    // capture on the plan's own stream (the caller's may be the legacy null
+    // stream, which cannot be captured); the graph then runs on the caller's
+    hipGraph_t g = nullptr;
+    hipStream_t cs = Bt->capture;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return hip_err(e, "hipStreamBeginCapture");
+    int rc = issue_batch<T>(Bt, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (rc != HDCONV_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e2 != hipSuccess) return hip_err(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&Bt->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      Bt->exec = nullptr;
+      return hip_err(e, "hipGraphInstantiate");
+    }
+  }
+  Bt->executes++;
+  if ((e = hipGraphLaunch(Bt->exec, s)) != hipSuccess) return hip_err(e, "hipGraphLaunch");
+  return HDCONV_OK;
+}
+
+extern "C" {
+
+void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
+                          const hdconv_options* opt) {
+  clear_err();
+  if (!L || !M || count < 1) {
+    set_err(HDCONV_EINVAL, "need L, M and count >= 1");
+    return nullptr;
+  }
+  if (dims != 1) {
+    set_err(HDCONV_EUNSUPPORTED, "batched plans are one-dimensional (got dims = %d)", dims);
+    return nullptr;
+  }
+  if (A < 2 || A > 3 || B != 1) {
+    set_err(HDCONV_EUNSUPPORTED, "batched plans need A in {2,3} and B = 1");
+    return nullptr;
+  }
+  if (dtype != HDCONV_C64 && dtype != HDCONV_C128) {
+    set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128");
+    return nullptr;
+  }
+  for (int64_t i = 0; i < count; ++i)
+    if (L[i] < 1 || M[i] < (int64_t)A * (L[i] - 1) + 1) {
+      set_err(HDCONV_EINVAL, "convolution %lld: need L >= 1 and M >= A(L-1)+1 (L=%lld, M=%lld)", (long long)i,
+              (long long)L[i], (long long)M[i]);
+      return nullptr;
+    }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    set_err(HDCONV_ENODEV, "no HIP device available");
+    return nullptr;
+  }
+  Batch* Bt = new (std::nothrow) Batch();
+  if (!Bt) {
+    set_err(HDCONV_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  (void)hipGetDevice(&Bt->device);
+  Bt->A = A;
+  Bt->B = B;
+  Bt->dtype = dtype;
+  Bt->flags = opt ? opt->flags : 0;
+  Bt->count = count;
+  Bt->L.assign(L, L + count);
+  Bt->M.assign(M, M + count);
+  const int tb = tbytes_of(dtype);
+  std::map<GroupKey, std::vector<int64_t>> byk;
+  std::map<GroupKey, DimPlan> shape;
+  for (int64_t i = 0; i < count; ++i) {
+    DimPlan dp;
+    std::string why;
+    if (!choose_dim(L[i], M[i], A, tb, true, &dp, &why)) {
+      set_err(HDCONV_EUNSUPPORTED, "convolution %lld (L=%lld): %s", (long long)i, (long long)L[i], why.c_str());
+      free_batch(Bt);
+      return nullptr;
+    }
+    GroupKey k{dp.variant, dp.m, dp.p, dp.n, dp.q, dp.E_m, dp.E_p, dp.S, dp.rows_per_block};
+    auto it = shape.find(k);
+    if (it == shape.end()) shape[k] = dp;
+    else {
+      it->second.L = std::max(it->second.L, dp.L);
+      it->second.M = std::max(it->second.M, dp.M);
+    }
+    byk[k].push_back(i);
+  }
+  // largest rows first, so long groups start early on their side stream
+  std::vector<GroupKey> order;
+  for (auto& kv : byk) order.push_back(kv.first);
+  std::sort(order.begin(), order.end(), [&](const GroupKey& a, const GroupKey& b) {
+    return shape[a].m * shape[a].p * (int64_t)byk[a].size() > shape[b].m * shape[b].p * (int64_t)byk[b].size();
+  });
+  size_t off = 0;
+  for (const GroupKey& k : order) {
+    Plan* P = make_group_plan(A, B, dtype, shape[k], (int64_t)byk[k].size(), Bt->device);
+    if (!P) {
+      free_batch(Bt);
+      return nullptr;
+    }
+    Bt->groups.push_back(P);
+    Bt->members.push_back(byk[k]);
+    Bt->task_off.push_back(off);
+    off += align256(byk[k].size() * (tb == 4 ? sizeof(RowTask<float>) : sizeof(RowTask<double>)));
+  }
+  Bt->task_bytes = off;
+  if ((e = hipMalloc((void**)&Bt->task_dev, off)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&Bt->task_host, off, hipHostMallocDefault)) != hipSuccess) {
+    set_err(HDCONV_ENOMEM, "task tables: %s", hipGetErrorString(e));
+    free_batch(Bt);
+    return nullptr;
+  }
+  for (int i = 0; i <= kSideStreams; ++i) {
+    hipStream_t* ps = i < kSideStreams ? &Bt->side[i] : &Bt->capture;
+    if ((e = hipStreamCreateWithFlags(ps, hipStreamNonBlocking)) != hipSuccess) {
+      hip_err(e, "hipStreamCreateWithFlags");
+      free_batch(Bt);
+      return nullptr;
+    }
+  }
+  Bt->joins.resize(Bt->groups.size(), nullptr);
+  bool ok = hipEventCreateWithFlags(&Bt->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&Bt->copied, hipEventDisableTiming) == hipSuccess;
+  for (auto& j : Bt->joins) ok = ok && hipEventCreateWithFlags(&j, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    set_err(HDCONV_EDEVICE, "event creation failed");
+    free_batch(Bt);
+    return nullptr;
+  }
+  return Bt;
+}
+
+int hdconv_execute_batched(void* batch, const void* const* inputs, void* const* outputs, void* stream) {
+  clear_err();
+  if (!batch || !inputs || !outputs) return set_err(HDCONV_EINVAL, "batch, inputs and outputs must not be NULL");
+  Batch* Bt = (Batch*)batch;
+  for (int64_t i = 0; i < Bt->count; ++i) {
+    for (int a = 0; a < Bt->A; ++a)
+      if (!inputs[i * Bt->A + a]) return set_err(HDCONV_EINVAL, "inputs[%lld] is NULL", (long long)(i * Bt->A + a));
+    if (!outputs[i * Bt->B]) return set_err(HDCONV_EINVAL, "outputs[%lld] is NULL", (long long)(i * Bt->B));
+  }
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != Bt->device) return set_err(HDCONV_EINVAL, "batch belongs to device %d, current is %d", Bt->device, cur);
+  hipStream_t s = (hipStream_t)stream;
+  return Bt->dtype == HDCONV_C64 ? run_batched<float>(Bt, inputs, outputs, s)
+                                 : run_batched<double>(Bt, inputs, outputs, s);
+}
+
+int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups) {
+  clear_err();
+  if (!batch) return set_err(HDCONV_EINVAL, "batch is NULL");
+  const Batch* Bt = (const Batch*)batch;
+  if (ngroups) *ngroups = (int)Bt->groups.size();
+  for (int g = 0; g < (int)Bt->groups.size() && g < cap; ++g) {
+    const DimPlan& dp = Bt->groups[g]->dp[0];
+    if (groups) {
+      hdconv_dim_info_t& di = groups[g];
+      memset(&di, 0, sizeof(di));
+      di.L = dp.L;
+      di.M = dp.M;
+      di.m = dp.m;
+      di.p = dp.p;
+      di.n = dp.n;
+      di.q = dp.q;
+      di.D = dp.D;
+      di.variant = dp.variant;
+      di.E_m = dp.E_m;
+      di.E_p = dp.E_p;
+      di.S = dp.S;
+      di.rows_per_block = dp.rows_per_block;
+      di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
+      di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
+    }
+    if (counts) counts[g] = (int64_t)Bt->members[g].size();
+  }
+  return HDCONV_OK;
+}
+
+void hdconv_batch_destroy(void* batch) { free_batch((Batch*)batch); }
 
 }  // extern "C"

@@ -26,10 +26,22 @@ constexpr int kMaxA = 3;
 // acc is an FP64 buffer laid out like out.
 enum AccMode { ACC_WRITE = 0, ACC_FIRST = 1, ACC_ADD = 2, ACC_LAST = 3 };
 
+// One independent 1D convolution of a batched plan: its own inputs, output
+// and length (all rows of a launch share m, p, q).
+template <typename T>
+struct RowTask {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out;
+  int64_t L;
+};
+
 // Whole 1D convolutions along contiguous rows, direct form with p <= 2.
-// One group of G lanes per row; rows_per_block rows per workgroup.
+// One group of G lanes per row; rows_per_block rows per workgroup.  When
+// `tasks` is set, row i takes its pointers and length from tasks[i] instead
+// of in/out/L and the strides.
 template <typename T>
 struct FusedArgs {
+  const RowTask<T>* tasks;
   const cpx<T>* in[kMaxA];
   cpx<T>* out;
   int64_t in_stride, out_stride;  // elements between consecutive rows
@@ -48,6 +60,7 @@ struct FusedArgs {
 // for residues v0 .. v0+D-1.  Output work[a][(row D + dv) p + u][s].
 template <typename T>
 struct ColFwdArgs {
+  const RowTask<T>* tasks;  // batched plans: per-row inputs and length
   const cpx<T>* in[kMaxA];
   cpx<T>* work[kMaxA];
   int64_t in_stride;
@@ -79,6 +92,7 @@ struct RowConvArgs {
 // truncated to L.
 template <typename T>
 struct ColBwdArgs {
+  const RowTask<T>* tasks;  // batched plans: per-row output and length
   const cpx<T>* work;
   cpx<T>* out;
   double* acc;  // FP64 accumulator (interleaved), for multi-block plans

@@ -25,11 +25,27 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   const int g = threadIdx.x - slot * G;
   const int64_t row = (int64_t)blockIdx.x * a.rows_per_block + slot;
   const bool valid = row < a.nrows;
-  const int64_t L = a.L;
+  // per-row pointers and length: from the task table (batched plans) or strided rows
+  const RowTask<T>* tk = (a.tasks && valid) ? a.tasks + row : nullptr;
+  const int64_t L = valid ? (tk ? tk->L : a.L) : 0;
   const int64_t qm = (int64_t)a.q * m;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
+
+  // the row's inputs, read once (zero beyond L)
+  cpx<T> x[A][P][E];
+#pragma unroll
+  for (int ai = 0; ai < A; ++ai) {
+    const cpx<T>* src = tk ? tk->in[ai] : a.in[ai] + row * a.in_stride;
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t j = (int64_t)t * m + g + G * e;
+        x[ai][t][e] = j < L ? src[j] : czero<T>();
+      }
+  }
   __syncthreads();
 
   cpx<T> acc[P][E];
@@ -51,12 +67,9 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       int64_t ex = ((int64_t)r * (t * m + g)) % qm;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int64_t j = (int64_t)t * m + g + G * e;
-        if (valid && j < L) {
-          const cpx<T> z = a.zqm.get(ex);
+        const cpx<T> z = a.zqm.get(ex);
 #pragma unroll
-          for (int ai = 0; ai < A; ++ai) w[ai][e] = w[ai][e] + cmul(a.in[ai][row * a.in_stride + j], z);
-        }
+        for (int ai = 0; ai < A; ++ai) w[ai][e] = w[ai][e] + cmul(x[ai][t][e], z);
         ex += st;
         if (ex >= qm) ex -= qm;
       }
@@ -83,7 +96,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     }
   }
   if (valid) {
-    cpx<T>* dst = a.out + row * a.out_stride;
+    cpx<T>* dst = tk ? tk->out : a.out + row * a.out_stride;
 #pragma unroll
     for (int t = 0; t < P; ++t)
 #pragma unroll

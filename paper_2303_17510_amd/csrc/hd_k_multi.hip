@@ -36,7 +36,8 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
   const int s = blockIdx.x * S + c;
   const int64_t row = blockIdx.y;
   const int ai = blockIdx.z;
-  const cpx<T>* src = a.in[ai] + row * a.in_stride;
+  const cpx<T>* src = a.tasks ? a.tasks[row].in[ai] : a.in[ai] + row * a.in_stride;
+  const int64_t L = a.tasks ? a.tasks[row].L : a.L;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, a.p * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
@@ -45,7 +46,7 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int64_t j = (int64_t)(g + G * e) * m + s;
-    x[e] = (j < a.L) ? src[j] : czero<T>();
+    x[e] = (j < L) ? src[j] : czero<T>();
   }
   __syncthreads();
   int dv = 0;
@@ -151,12 +152,13 @@ __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
   int dv = 0;
   for (; dv + 2 <= a.D; dv += 2) cols_bwd_residues<T, E, 2>(a, acc, dv, g, s, row, tw, xb);
   if (dv < a.D) cols_bwd_residues<T, E, 1>(a, acc, dv, g, s, row, tw, xb);
-  cpx<T>* dst = a.out + row * a.out_stride;
+  cpx<T>* dst = a.tasks ? a.tasks[row].out : a.out + row * a.out_stride;
+  const int64_t L = a.tasks ? a.tasks[row].L : a.L;
   double* acc64 = a.acc ? a.acc + 2 * row * a.out_stride : nullptr;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int64_t j = (int64_t)(g + G * e) * m + s;
-    if (j < a.L) acc_store(dst, acc64, a.acc_mode, j, acc[e], a.scale);
+    if (j < L) acc_store(dst, acc64, a.acc_mode, j, acc[e], a.scale);
   }
 }
 

@@ -1,8 +1,22 @@
 // hd_kcommon.hpp -- helpers shared by the kernel translation units.
 #pragma once
+#include <mutex>
+#include <unordered_map>
+
 #include "hd_engine.hpp"
 
 namespace hd {
+
+// Largest dynamic LDS size already granted to each kernel on this device, so
+// the attribute call happens once per kernel (not inside captured graphs).
+inline std::unordered_map<const void*, size_t>& lds_granted() {
+  static std::unordered_map<const void*, size_t> m;
+  return m;
+}
+inline std::mutex& lds_mutex() {
+  static std::mutex mu;
+  return mu;
+}
 
 extern __shared__ __align__(16) char hd_smem[];
 
@@ -40,8 +54,13 @@ __device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, in
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t lds) {
   if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lk(lds_mutex());
+  auto it = lds_granted().find(key);
+  if (it != lds_granted().end() && it->second >= lds) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) lds_granted()[key] = lds;
+  return e;
 }
 
 template <typename K, typename Args>

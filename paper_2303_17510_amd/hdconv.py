@@ -178,6 +178,81 @@ class Plan:
         self.close()
 
 
+class BatchPlan:
+    """Many independent 1D convolutions of uneven length ``Ls`` (each padded to ``Ms``).
+
+    Convolutions with the same planned shape form a group; each execute is one
+    hipGraph launch (from the second execute on, unless ``graph=False``).
+    """
+
+    def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True):
+        Ls = [int(v) for v in Ls]
+        Ms = [A * v for v in Ls] if Ms is None else [int(v) for v in Ms]
+        if len(Ms) != len(Ls):
+            raise ValueError("Ls and Ms differ in length")
+        self.Ls, self.Ms, self.A, self.B = Ls, Ms, A, B
+        self.dtype_code = dtype_code(dtype)
+        opt = _L.Options()
+        _L.lib().hdconv_options_init(ctypes.byref(opt))
+        opt.flags = 0 if graph else _L.BATCH_NO_GRAPH
+        n = len(Ls)
+        h = _L.lib().hdconv_plan_batched((ctypes.c_int64 * n)(*Ls), (ctypes.c_int64 * n)(*Ms), n, A, B, 1,
+                                         self.dtype_code, ctypes.byref(opt))
+        if not h:
+            code, msg = _L.last_error()
+            raise _L.HdconvError(code, msg)
+        self._h = h
+
+    def groups(self) -> list:
+        cap = 256
+        arr = (_L.DimInfo * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        ng = ctypes.c_int(0)
+        _L.check(_L.lib().hdconv_batch_info(self._h, arr, cnt, cap, ctypes.byref(ng)))
+        return [{"variant": _L.VARIANT_NAMES[arr[g].variant], "m": arr[g].m, "p": arr[g].p, "n": arr[g].n,
+                 "q": arr[g].q, "count": cnt[g], "Lmax": arr[g].L} for g in range(min(ng.value, cap))]
+
+    def execute(self, inputs, outputs, stream=None):
+        """inputs: list (per convolution) of A tensors; outputs: list of tensors."""
+        torch = _torch()
+        n = len(self.Ls)
+        if len(inputs) != n or len(outputs) != n:
+            raise ValueError("expected %d convolutions" % n)
+        want = torch.complex64 if self.dtype_code == _L.C64 else torch.complex128
+        ptrs = []
+        for i, ins in enumerate(inputs):
+            if len(ins) != self.A:
+                raise ValueError("convolution %d needs %d inputs" % (i, self.A))
+            for t in list(ins) + [outputs[i]]:
+                if not t.is_cuda or t.dtype != want or t.numel() != self.Ls[i] or not t.is_contiguous():
+                    raise ValueError("convolution %d: tensors must be contiguous %s CUDA vectors of length %d"
+                                     % (i, want, self.Ls[i]))
+            ptrs.extend(t.data_ptr() for t in ins)
+        ins_c = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        outs_c = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outputs])
+        if stream is None:
+            stream = torch.cuda.current_stream(outputs[0].device)
+        _L.check(_L.lib().hdconv_execute_batched(self._h, ins_c, outs_c, ctypes.c_void_p(stream.cuda_stream)))
+        return outputs
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _L.lib().hdconv_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def convolve(*inputs, M=None, **kw):
     """One-shot convolution of equal-shape complex CUDA tensors (first L outputs)."""
     L = tuple(inputs[0].shape)
