@@ -76,8 +76,18 @@ typedef struct hdconv_options {
   int S[3];          /* columns per workgroup of column/outer kernels (0: choose) */
   int rows_per_block[3]; /* rows per workgroup of row kernels (0: choose)       */
   int twiddles[3];   /* FFT twiddles: 0 choose, 1 two-level root table, 2 exact per-stage tables */
+  int tuner;         /* HDCONV_TUNER_*: how shapes left to the planner are chosen */
+  int tune_reps;     /* timed executes per candidate (0: 5)                     */
+  double margin;     /* model tuner: time the top candidates when the predicted
+                        log-time gap between the best two is below this (0: 0.05) */
+  void* model;       /* model tuner: a cost model from hdconv_model_create      */
+  const char* db_path; /* timed tuners: append every timing to this CSV (NULL: none) */
   int reserved[8];   /* zero                                                    */
 } hdconv_options;
+
+/* tuners (Sec. 7: the paper's optimizer times candidate (m, D, ...) per
+ * dimension; the model tuner predicts those times and times only close calls) */
+enum { HDCONV_TUNER_HEURISTIC = 0, HDCONV_TUNER_EXHAUSTIVE = 1, HDCONV_TUNER_MODEL = 2 };
 
 typedef struct hdconv_dim_info {
   int64_t L, M;      /* lengths the engine works on in this dimension           */
@@ -100,7 +110,30 @@ typedef struct hdconv_plan_info {
   double compulsory_bytes;       /* (A+B) prod(L) word bytes: read inputs, write output once */
   double traffic_bytes;          /* bytes the plan's kernels read + write by design */
   int launches;                  /* kernel launches per execute                  */
+  int tuner;                     /* tuner that chose the shapes                  */
+  int tuned_candidates;          /* candidates considered                        */
+  int timed_candidates;          /* candidates timed on the device               */
+  double tuned_ms;               /* time of the chosen shapes when it was measured, else 0 */
 } hdconv_plan_info_t;
+
+/* Autotuning interface.  hdconv_candidates lists the planner's search space
+ * for a problem the way the paper's optimizer decouples it (Sec. 7): the
+ * default plan, and that plan with one dimension's shape replaced by each of
+ * its candidates.  Candidate k is out[k*dims .. k*dims+dims); varied[k] is the
+ * dimension it changes (-1 for the default plan).  Host only. */
+int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                      hdconv_dim_info_t* out, int* varied, int cap, int* count);
+
+/* Median time in ms of `reps` executes (after one warm-up) of the plan whose
+ * per-dimension shapes are shape[0..dims), on zeroed device buffers. */
+int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                      const hdconv_dim_info_t* shape, int reps, double* ms);
+
+/* Cost-model features of a candidate: HDCONV_NFEATURES floats describing the
+ * problem and the shape (logs of lengths, sizes, traffic, work). */
+enum { HDCONV_NFEATURES = 44 };
+int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                    const hdconv_dim_info_t* shape, float* out);
 
 /* Fill *opt with defaults (AUTO everywhere, nothing forced). */
 void hdconv_options_init(hdconv_options* opt);
@@ -136,6 +169,26 @@ void hdconv_destroy(void* plan);
  * MULTIPASS for the inner form). */
 int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner,
                     hdconv_dim_info_t* out);
+
+/* Learned cost model (the planner's model tuner).  A multilayer perceptron:
+ * HDCONV_NFEATURES inputs (normalised by the training set's mean and
+ * standard deviation), three hidden layers of `hidden` SiLU units, one linear
+ * output = predicted log run time in ms.  Training (forward, backward, Adam on
+ * the mean squared error of normalised targets) and inference run in FP32 HIP
+ * kernels of this library.  The parameter vector is W1[NF][H], b1[H],
+ * W2[H][H], b2[H], W3[H][H], b3[H], W4[H], b4 (the network), then xmean[NF],
+ * xstd[NF], ymean, ystd.  X arrays are row-major n x HDCONV_NFEATURES host
+ * floats; y holds log run times.  All calls synchronise. */
+void* hdconv_model_create(int hidden, uint64_t seed);      /* Glorot-uniform init; NULL on error */
+int hdconv_model_params(void* model, float* params, int cap, int* n);
+int hdconv_model_load(void* model, const float* params, int n);
+int hdconv_model_train(void* model, const float* X, const float* y, int64_t n, int epochs, int batch, float lr,
+                       uint64_t seed, float* final_loss);
+int hdconv_model_predict(void* model, const float* X, int64_t n, float* out);
+/* Gradient of the loss over all n rows with respect to the network
+ * parameters (with the model's current normalisation) and the loss. */
+int hdconv_model_grad(void* model, const float* X, const float* y, int64_t n, float* grad, float* loss);
+void hdconv_model_destroy(void* model);
 
 /* Batched plans: `count` independent one-dimensional convolutions of uneven
  * length (dims = 1), L[i] and M[i] each as in hdconv_plan, all with the same

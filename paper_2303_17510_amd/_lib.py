@@ -19,6 +19,8 @@ METHOD_AUTO, METHOD_HYBRID, METHOD_EXPLICIT = 0, 1, 2
 VARIANT_AUTO, VARIANT_FUSED, VARIANT_MULTIPASS, VARIANT_OUTER = 0, 1, 2, 3
 PLAN_HOST_ONLY = 1
 BATCH_NO_GRAPH = 2
+TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
+NFEATURES = 44
 
 VARIANT_NAMES = {0: "auto", 1: "fused", 2: "multipass", 3: "outer"}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENODEV"}
@@ -31,7 +33,8 @@ class Options(ctypes.Structure):
                 ("m", _i64 * 3), ("p", _i64 * 3), ("D", _i64 * 3),
                 ("variant", ctypes.c_int * 3), ("E_m", ctypes.c_int * 3), ("E_p", ctypes.c_int * 3),
                 ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("twiddles", ctypes.c_int * 3),
-                ("reserved", ctypes.c_int * 8)]
+                ("tuner", ctypes.c_int), ("tune_reps", ctypes.c_int), ("margin", ctypes.c_double),
+                ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("reserved", ctypes.c_int * 8)]
 
 
 class DimInfo(ctypes.Structure):
@@ -46,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("method", ctypes.c_int), ("L", _i64 * 3), ("M", _i64 * 3), ("dim", DimInfo * 3),
                 ("npad", _i64 * 3), ("workspace_bytes", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
                 ("compulsory_bytes", ctypes.c_double), ("traffic_bytes", ctypes.c_double),
-                ("launches", ctypes.c_int)]
+                ("launches", ctypes.c_int), ("tuner", ctypes.c_int), ("tuned_candidates", ctypes.c_int),
+                ("timed_candidates", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -66,6 +70,28 @@ SIGNATURES = {
     "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hdconv_destroy": (None, [ctypes.c_void_p]),
     "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),
+    "hdconv_candidates": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "hdconv_time_shape": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "hdconv_features": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo),
+                                       ctypes.POINTER(ctypes.c_float)]),
+    "hdconv_model_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_uint64]),
+    "hdconv_model_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int)]),
+    "hdconv_model_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
+    "hdconv_model_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float), _i64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)]),
+    "hdconv_model_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), _i64,
+                                            ctypes.POINTER(ctypes.c_float)]),
+    "hdconv_model_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_float), _i64, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_float)]),
+    "hdconv_model_destroy": (None, [ctypes.c_void_p]),
     "hdconv_plan_batched": (ctypes.c_void_p, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i64, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]),
     "hdconv_execute_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),

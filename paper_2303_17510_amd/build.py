@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libhdconv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("HDCONV_ARCH", "gfx950")
 
-SOURCES = ["hd_k_fused.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_api.cpp", "hd_plan.cpp"]
+SOURCES = ["hd_k_fused.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_mlp.hip", "hd_api.cpp", "hd_plan.cpp"]
 
 
 def hipcc() -> str:

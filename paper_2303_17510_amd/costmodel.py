@@ -1,0 +1,150 @@
+"""Learned parameter picker: data from the autotuner, training, regret.
+
+Workflow (all GPU work runs in libhdconv's kernels):
+
+1. ``collect``: for seeded geometries (``tune.geometries``), enumerate the
+   planner's candidates (the default plan and every single-dimension
+   variation, Sec. 7's decoupled search), time each on the device and store
+   (features, log ms) rows.  The timings are the exhaustive search's.
+2. ``train``: fit the library's MLP (HIP forward/backward/Adam) to predict
+   log ms from features.
+3. ``evaluate``: on held-out geometries, the model's pick (argmin predicted
+   time over a geometry's candidates) against the exhaustive pick (argmin
+   timed): regret = t(model pick) / t(best) - 1, and the gain over the
+   planner's default (untuned) plan = t(default) / t(model pick).
+
+CLI: ``python -m paper_2303_17510_amd.costmodel collect --seed S --start i
+--count n --out file.npz`` (chunks of the geometry list), ``train`` and
+``evaluate`` (see --help).
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import tune
+
+SEED_TRAIN = 17510500
+SEED_HELDOUT = 17510501
+
+
+def collect(geoms, reps=3, dtype="c64", log=None, time_budget_s=None, ids=None):
+    """Rows of every candidate of every geometry: dict of numpy arrays."""
+    X, y, gid, var, dims_l = [], [], [], [], []
+    t0 = time.time()
+    for i, g in enumerate(geoms):
+        if time_budget_s and time.time() - t0 > time_budget_s:
+            break
+        gi = ids[i] if ids is not None else i
+        try:
+            cands = tune.candidates(g["L"], g["M"], A=g["A"], dtype=dtype)
+        except Exception as e:  # no plan for this geometry
+            if log:
+                log("geometry %d %s: no candidates (%s)" % (gi, g, e))
+            continue
+        n_ok = 0
+        for v, shape in cands:
+            try:
+                ms = tune.time_shape(g["L"], g["M"], shape, A=g["A"], dtype=dtype, reps=reps)
+            except Exception:
+                continue
+            if not (ms > 0):
+                continue
+            X.append(tune.features(g["L"], g["M"], shape, A=g["A"], dtype=dtype))
+            y.append(math.log(ms))
+            gid.append(gi)
+            var.append(v)
+            dims_l.append(len(g["L"]))
+            n_ok += 1
+        if log and (i % 20 == 0):
+            log("geometry %d/%d L=%s A=%d: %d candidates timed, %.0f s" % (i, len(geoms), g["L"], g["A"], n_ok,
+                                                                          time.time() - t0))
+    return {"X": np.array(X, dtype=np.float32).reshape(-1, tune.NF), "y": np.array(y, dtype=np.float32),
+            "gid": np.array(gid, dtype=np.int64), "varied": np.array(var, dtype=np.int64),
+            "dims": np.array(dims_l, dtype=np.int64)}
+
+
+def save(data, path):
+    np.savez(path, **data)
+
+
+def load(paths):
+    parts = [np.load(p, allow_pickle=False) for p in paths]
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0].files}
+
+
+def train(data, hidden=64, epochs=300, batch=256, lr=2e-3, seed=0):
+    m = tune.CostModel(hidden=hidden, seed=seed)
+    loss = m.train(data["X"], data["y"], epochs=epochs, batch=batch, lr=lr, seed=seed)
+    return m, loss
+
+
+def evaluate(model, data):
+    """Per held-out geometry: regret of the model's pick and gain over the default plan."""
+    pred = model.predict(data["X"])
+    regrets, gains, rows = [], [], []
+    for g in np.unique(data["gid"]):
+        idx = np.nonzero(data["gid"] == g)[0]
+        t = np.exp(data["y"][idx].astype(np.float64))
+        best = t.min()
+        pick = t[np.argmin(pred[idx])]
+        dflt = idx[data["varied"][idx] == -1]
+        t_def = math.exp(float(data["y"][dflt[0]])) if len(dflt) else float("nan")
+        regrets.append(pick / best - 1.0)
+        gains.append(t_def / pick)
+        rows.append((int(g), int(data["dims"][idx[0]]), float(best), float(pick), float(t_def)))
+    r = np.array(regrets)
+    gm = float(np.exp(np.mean(np.log1p(r))) - 1.0)
+    return {"geometries": len(r), "regret_geomean": gm, "regret_median": float(np.median(r)),
+            "regret_p90": float(np.percentile(r, 90)), "regret_max": float(r.max()),
+            "gain_over_default_geomean": float(np.exp(np.mean(np.log(np.array(gains))))),
+            "exhaustive_gain_over_default_geomean": float(np.exp(np.mean(
+                [math.log(x[4] / x[2]) for x in rows if x[4] == x[4]]))),
+            "rows": rows}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--seed", type=int, default=SEED_TRAIN)
+    c.add_argument("--total", type=int, default=2000, help="geometries in the seeded list")
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--count", type=int, default=2000)
+    c.add_argument("--reps", type=int, default=3)
+    c.add_argument("--budget", type=float, default=0, help="stop after this many seconds (0: none)")
+    c.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", nargs="+", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--epochs", type=int, default=300)
+    t.add_argument("--seed", type=int, default=0)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--model", required=True)
+    e.add_argument("--data", nargs="+", required=True)
+    a = ap.parse_args(argv)
+    log = lambda *s: print(*s, file=sys.stderr, flush=True)  # noqa: E731
+    if a.cmd == "collect":
+        geoms = tune.geometries(a.total, a.seed)
+        sel = list(range(a.start, min(a.total, a.start + a.count)))
+        d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None, ids=sel)
+        save(d, a.out)
+        log("saved %d rows from %d geometries to %s" % (len(d["y"]), len(np.unique(d["gid"])), a.out))
+    elif a.cmd == "train":
+        d = load(a.data)
+        m, loss = train(d, epochs=a.epochs, seed=a.seed)
+        m.save(a.out)
+        log("trained on %d rows, final normalised MSE %.4f, saved %s" % (len(d["y"]), loss, a.out))
+    else:
+        m = tune.CostModel.load_file(a.model)
+        r = evaluate(m, load(a.data))
+        r.pop("rows")
+        print(r)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,8 @@ struct Plan {
   void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
   double* acc64 = nullptr;                            // multi-block accumulator
   int64_t batch_rows = 1;                             // rows of a batched group
+  int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
+  double tuned_ms = 0;
   int launches = 0;
   // per-launch event timing (hdconv_profile_begin / hdconv_profile_end)
   struct Prof {
@@ -112,6 +114,10 @@ struct ProfScope {
 // planning
 
 static int tbytes_of(int dtype) { return dtype == HDCONV_C64 ? 4 : 8; }
+
+static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                       const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms);
+static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims);
 
 static int build_dims(Plan* P, const hdconv_options* opt) {
   const int tb = tbytes_of(P->dtype);
@@ -674,6 +680,24 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
       return nullptr;
     }
   }
+  if (opt && opt->tuner != HDCONV_TUNER_HEURISTIC && opt->method != HDCONV_METHOD_EXPLICIT &&
+      !(opt->flags & HDCONV_PLAN_HOST_ONLY)) {
+    // tuned plan: choose every dimension's shape, then build it like a forced plan
+    hdconv_dim_info_t shp[3];
+    int nc = 0, nt = 0;
+    double ms = 0;
+    if (tune_shapes(L, M, A, B, dims, dtype, opt, shp, &nc, &nt, &ms) != HDCONV_OK) return nullptr;
+    hdconv_options o = opts_from_shape(shp, dims);
+    o.flags = opt->flags;
+    Plan* T = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
+    if (T) {
+      T->tuner = opt->tuner;
+      T->tuned_candidates = nc;
+      T->timed_candidates = nt;
+      T->tuned_ms = ms;
+    }
+    return T;
+  }
   Plan* P = new (std::nothrow) Plan();
   if (!P) {
     set_err(HDCONV_ENOMEM, "host allocation failed");
@@ -761,6 +785,10 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
   out->table_bytes = P->table_bytes;
   out->compulsory_bytes = (double)(P->A + P->B) * ltot * 2.0 * tbytes_of(P->dtype);
   out->traffic_bytes = plan_traffic(P, &out->launches);
+  out->tuner = P->tuner;
+  out->tuned_candidates = P->tuned_candidates;
+  out->timed_candidates = P->timed_candidates;
+  out->tuned_ms = P->tuned_ms;
   return HDCONV_OK;
 }
 
@@ -852,6 +880,312 @@ int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* coun
 void hdconv_destroy(void* plan) {
   if (plan) prof_release((Plan*)plan);
   free_plan((Plan*)plan);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuning: candidates, timing, cost-model features
+
+static void fill_dim_info(const DimPlan& dp, hdconv_dim_info_t* di) {
+  memset(di, 0, sizeof(*di));
+  di->L = dp.L;
+  di->M = dp.M;
+  di->m = dp.m;
+  di->p = dp.p;
+  di->n = dp.n;
+  di->q = dp.q;
+  di->D = dp.D;
+  di->variant = dp.variant;
+  di->E_m = dp.E_m;
+  di->E_p = dp.E_p;
+  di->S = dp.S;
+  di->rows_per_block = dp.rows_per_block;
+  di->tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
+  di->tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
+}
+
+// options that reproduce the per-dimension shapes exactly
+static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims) {
+  hdconv_options o;
+  memset(&o, 0, sizeof(o));
+  o.method = HDCONV_METHOD_HYBRID;
+  for (int d = 0; d < dims; ++d) {
+    o.m[d] = shp[d].m;
+    o.p[d] = shp[d].p;
+    o.D[d] = shp[d].D;
+    o.variant[d] = shp[d].variant;
+    o.E_m[d] = shp[d].E_m;
+    o.E_p[d] = shp[d].E_p;
+    o.S[d] = shp[d].S;
+    o.rows_per_block[d] = shp[d].rows_per_block;
+    o.twiddles[d] = shp[d].tw_m == 2 ? 2 : 0;
+  }
+  return o;
+}
+
+// default plan plus, per dimension, that plan with the dimension replaced by
+// each of its candidates (Sec. 7: dimensions are tuned independently)
+static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, int dtype,
+                           std::vector<hdconv_dim_info_t>* out, std::vector<int>* varied) {
+  const int tb = tbytes_of(dtype);
+  std::vector<DimPlan> base(dims);
+  for (int d = 0; d < dims; ++d) {
+    std::string why;
+    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, &base[d], &why))
+      return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
+  }
+  auto push = [&](const std::vector<DimPlan>& s, int v) {
+    for (int d = 0; d < dims; ++d) {
+      hdconv_dim_info_t di;
+      fill_dim_info(s[d], &di);
+      out->push_back(di);
+    }
+    varied->push_back(v);
+  };
+  push(base, -1);
+  for (int d = 0; d < dims; ++d) {
+    for (const DimPlan& c : dim_candidates(L[d], M[d], A, tb, d == dims - 1)) {
+      const DimPlan& b = base[d];
+      if (c.variant == b.variant && c.m == b.m && c.p == b.p && c.E_m == b.E_m && c.E_p == b.E_p && c.S == b.S &&
+          c.rows_per_block == b.rows_per_block)
+        continue;
+      std::vector<DimPlan> s = base;
+      s[d] = c;
+      push(s, d);
+    }
+  }
+  return HDCONV_OK;
+}
+
+static int time_plan_ms(void* plan, int A, size_t bytes, int reps, double* ms) {
+  void* buf[kMaxA + 1] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = HDCONV_OK;
+  std::vector<float> t;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  for (int a = 0; a <= A && e == hipSuccess; ++a) {
+    e = hipMalloc(&buf[a], bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(buf[a], 0, bytes, s);
+  }
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    rc = set_err(HDCONV_ENOMEM, "tuning buffers: %s", hipGetErrorString(e));
+  } else {
+    const void* ins[kMaxA] = {buf[0], buf[1], buf[2]};
+    void* outs[1] = {buf[A]};
+    rc = hdconv_execute(plan, ins, outs, s);  // warm-up
+    for (int r = 0; r < reps && rc == HDCONV_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      rc = hdconv_execute(plan, ins, outs, s);
+      (void)hipEventRecord(e1, s);
+      float x = 0;
+      if (rc == HDCONV_OK && (e = hipEventSynchronize(e1)) == hipSuccess &&
+          (e = hipEventElapsedTime(&x, e0, e1)) == hipSuccess)
+        t.push_back(x);
+      else if (rc == HDCONV_OK)
+        rc = hip_err(e, "tuning timing");
+    }
+  }
+  if (s) (void)hipStreamSynchronize(s);
+  for (void* b : buf)
+    if (b) (void)hipFree(b);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (rc == HDCONV_OK) {
+    std::sort(t.begin(), t.end());
+    *ms = t.empty() ? 0.0 : t[t.size() / 2];
+  }
+  return rc;
+}
+
+extern "C" int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                                 const hdconv_dim_info_t* shape, int reps, double* ms);
+
+static void db_append(const char* path, const int64_t* L, const int64_t* M, int A, int dims, int dtype,
+                      const hdconv_dim_info_t* shp, int varied, double ms) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%d,%d,%d", dims, A, dtype);
+  for (int d = 0; d < 3; ++d) fprintf(f, ",%lld,%lld", (long long)(d < dims ? L[d] : 0), (long long)(d < dims ? M[d] : 0));
+  fprintf(f, ",%d", varied);
+  for (int d = 0; d < 3; ++d) {
+    if (d < dims)
+      fprintf(f, ",%d,%lld,%lld,%lld,%d,%d,%d,%d", shp[d].variant, (long long)shp[d].m, (long long)shp[d].p,
+              (long long)shp[d].q, shp[d].E_m, shp[d].E_p, shp[d].S, shp[d].rows_per_block);
+    else
+      fprintf(f, ",0,0,0,0,0,0,0,0");
+  }
+  fprintf(f, ",%.6f\n", ms);
+  fclose(f);
+}
+
+namespace hd {
+int mlp_predict_host(void* model, const float* X, int64_t n, float* out);
+}
+
+// Choose shapes with the requested tuner; fills shp[0..dims).
+static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                       const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms) {
+  std::vector<hdconv_dim_info_t> cand;
+  std::vector<int> varied;
+  int rc = list_candidates(L, M, A, dims, dtype, &cand, &varied);
+  if (rc != HDCONV_OK) return rc;
+  const int nc = (int)varied.size();
+  *ncand = nc;
+  *ntimed = 0;
+  const int reps = opt->tune_reps > 0 ? opt->tune_reps : 5;
+  std::vector<double> score(nc, 1e300);  // measured ms or predicted log-ms
+  std::vector<char> timed(nc, 0);
+  auto time_one = [&](int k) -> int {
+    double ms = 0;
+    int r = hdconv_time_shape(L, M, A, B, dims, dtype, &cand[(size_t)k * dims], reps, &ms);
+    if (r != HDCONV_OK) return r;
+    score[k] = ms;
+    timed[k] = 1;
+    (*ntimed)++;
+    if (opt->db_path) db_append(opt->db_path, L, M, A, dims, dtype, &cand[(size_t)k * dims], varied[k], ms);
+    return HDCONV_OK;
+  };
+  if (opt->tuner == HDCONV_TUNER_EXHAUSTIVE) {
+    for (int k = 0; k < nc; ++k) {
+      int r = time_one(k);
+      if (r != HDCONV_OK) score[k] = 1e300;  // a candidate that cannot run is skipped
+    }
+  } else {
+    if (!opt->model) return set_err(HDCONV_EINVAL, "the model tuner needs options.model");
+    std::vector<float> X((size_t)nc * HDCONV_NFEATURES), pred(nc);
+    for (int k = 0; k < nc; ++k)
+      if ((rc = hdconv_features(L, M, A, B, dims, dtype, &cand[(size_t)k * dims], &X[(size_t)k * HDCONV_NFEATURES])) != HDCONV_OK)
+        return rc;
+    if ((rc = hd::mlp_predict_host(opt->model, X.data(), nc, pred.data())) != HDCONV_OK) return rc;
+    for (int k = 0; k < nc; ++k) score[k] = pred[k];
+  }
+  // per dimension, the best candidate varying that dimension (or the default)
+  const double margin = opt->margin > 0 ? opt->margin : 0.05;
+  for (int d = 0; d < dims; ++d) {
+    std::vector<int> ks;
+    for (int k = 0; k < nc; ++k)
+      if (varied[k] == -1 || varied[k] == d) ks.push_back(k);
+    std::sort(ks.begin(), ks.end(), [&](int a, int b) { return score[a] < score[b]; });
+    int best = ks[0];
+    if (opt->tuner == HDCONV_TUNER_MODEL && ks.size() > 1 && score[ks[1]] - score[ks[0]] < margin) {
+      // close call: time the predicted top three and keep the fastest
+      double bm = 1e300;
+      for (size_t i = 0; i < ks.size() && i < 3; ++i) {
+        const int k = ks[i];
+        if (!timed[k]) {
+          const double pred = score[k];
+          if (time_one(k) != HDCONV_OK) {
+            score[k] = pred;
+            continue;
+          }
+        }
+        if (score[k] < bm) {
+          bm = score[k];
+          best = k;
+        }
+      }
+    }
+    shp[d] = cand[(size_t)best * dims + d];
+  }
+  *best_ms = 0;
+  for (int k = 0; k < nc; ++k) {
+    bool same = true;
+    for (int d = 0; d < dims; ++d) {
+      const hdconv_dim_info_t &a = cand[(size_t)k * dims + d], &b = shp[d];
+      same = same && a.variant == b.variant && a.m == b.m && a.p == b.p && a.E_m == b.E_m && a.E_p == b.E_p &&
+             a.S == b.S && a.rows_per_block == b.rows_per_block;
+    }
+    if (same && timed[k]) *best_ms = score[k];
+  }
+  return HDCONV_OK;
+}
+
+extern "C" {
+
+int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                      hdconv_dim_info_t* out, int* varied, int cap, int* count) {
+  clear_err();
+  if (!L || !M || dims < 1 || dims > 3 || A < 2 || A > 3 || B != 1 || (dtype != HDCONV_C64 && dtype != HDCONV_C128))
+    return set_err(HDCONV_EINVAL, "invalid problem");
+  std::vector<hdconv_dim_info_t> cand;
+  std::vector<int> var;
+  int rc = list_candidates(L, M, A, dims, dtype, &cand, &var);
+  if (rc != HDCONV_OK) return rc;
+  if (count) *count = (int)var.size();
+  for (int k = 0; k < (int)var.size() && k < cap; ++k) {
+    if (out)
+      for (int d = 0; d < dims; ++d) out[(size_t)k * dims + d] = cand[(size_t)k * dims + d];
+    if (varied) varied[k] = var[k];
+  }
+  return HDCONV_OK;
+}
+
+int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                      const hdconv_dim_info_t* shape, int reps, double* ms) {
+  clear_err();
+  if (!shape || !ms || reps < 1) return set_err(HDCONV_EINVAL, "need a shape, ms and reps >= 1");
+  hdconv_options o = opts_from_shape(shape, dims);
+  void* plan = hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
+  if (!plan) return g_err_code;
+  size_t bytes = 2 * (size_t)tbytes_of(dtype);
+  for (int d = 0; d < dims; ++d) bytes *= (size_t)L[d];
+  int rc = time_plan_ms(plan, A, bytes, reps, ms);
+  hdconv_destroy(plan);
+  return rc;
+}
+
+int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+                    const hdconv_dim_info_t* shape, float* out) {
+  clear_err();
+  if (!shape || !out) return set_err(HDCONV_EINVAL, "need a shape and out");
+  hdconv_options o = opts_from_shape(shape, dims);
+  o.flags = HDCONV_PLAN_HOST_ONLY;
+  Plan* P = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
+  if (!P) return g_err_code;
+  auto lg = [](double x) { return (float)std::log2(std::max(x, 1.0)); };
+  for (int i = 0; i < HDCONV_NFEATURES; ++i) out[i] = 0.f;
+  int launches = 0;
+  const double traffic = plan_traffic(P, &launches);
+  double tot = 1, work = 0, nb = 1;
+  for (int d = 0; d < dims; ++d) tot *= (double)L[d];
+  for (int d = 0; d < dims; ++d) {
+    const DimPlan& dp = P->dp[d];
+    double rest = 1;
+    for (int e = d + 1; e < dims; ++e) rest *= (double)L[e];
+    // transform work of this level: (A+B) transforms of q m points per line
+    work += (A + B) * nb * rest * (double)(dp.q * dp.m) * std::log2(std::max<double>(2.0, (double)(dp.m * dp.p)));
+    nb *= (double)(dp.q * dp.m);
+    float* f = out + 13 + 10 * d;
+    f[0] = lg((double)dp.m);
+    f[1] = lg((double)dp.p);
+    f[2] = lg((double)dp.q);
+    f[3] = dp.variant == VAR_FUSED;
+    f[4] = dp.variant == VAR_MULTI;
+    f[5] = dp.variant == VAR_OUTER;
+    f[6] = lg((double)dp.E_m);
+    f[7] = lg((double)dp.E_p);
+    f[8] = lg((double)dp.S);
+    f[9] = lg((double)dp.rows_per_block);
+  }
+  out[0] = (float)dims;
+  out[1] = (float)A;
+  out[2] = (float)dtype;
+  for (int d = 0; d < dims; ++d) {
+    out[3 + d] = lg((double)L[d]);
+    out[6 + d] = lg((double)M[d]);
+  }
+  out[9] = lg(tot);
+  out[10] = lg(traffic);
+  out[11] = lg((double)launches);
+  out[12] = lg(work);
+  out[43] = lg((double)P->work_bytes + 1.0);
+  hdconv_destroy(P);
+  return HDCONV_OK;
 }
 
 }  // extern "C"

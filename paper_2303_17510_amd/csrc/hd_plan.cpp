@@ -253,21 +253,46 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
     if (s >= 8 && 3 * s <= kMaxRowM) sizes.push_back(3 * s);
   }
   std::sort(sizes.begin(), sizes.end());
-  for (int64_t m : sizes) {
-    if (m > next_fft_size(M) && m > 8) break;
+  auto add = [&](int64_t m, int64_t pmin, int variant, int E_m) {
     DimPlan dp;
     std::string w;
+    if (!set_geom(&dp, L, M, m, pmin, variant)) return;
+    dp.E_m = E_m;
+    if (finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
+  };
+  for (int64_t m : sizes) {
+    if (m > next_fft_size(M) && m > 8) break;
     if (contiguous) {
-      if (set_geom(&dp, L, M, m, 0, VAR_FUSED) && finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
-      DimPlan d2;
-      int64_t p = next_col_size(cdiv(L, m));
-      if (m >= 16 && p <= kMaxColP && set_geom(&d2, L, M, m, p, VAR_MULTI) && finish_dim(&d2, A, tbytes, &w))
-        out.push_back(d2);
+      // whole rows in one workgroup (p <= 2), two widths of the m-point transform
+      if (cdiv(L, m) <= 2)
+        for (int E : {8, 16}) add(m, 0, VAR_FUSED, E);
+      // inner form: p rounded up to a supported size, and to a power of two
+      if (m >= 16 && m >= L / kMaxColP) {
+        const int64_t p0 = cdiv(L, m);
+        int64_t p2 = 1;
+        while (p2 < p0) p2 <<= 1;
+        std::vector<int64_t> ps = {next_col_size(p0)};
+        if (p2 != ps[0]) ps.push_back(p2);
+        for (int64_t p : ps) {
+          if (p > kMaxColP) continue;
+          for (int E : {8, 16}) add(m, p, VAR_MULTI, E);
+        }
+      }
     } else {
-      if (set_geom(&dp, L, M, m, 0, VAR_OUTER) && finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
+      if (cdiv(L, m) <= 2)
+        for (int E : {16, 32}) add(m, 0, VAR_OUTER, E);
     }
   }
-  return out;
+  // drop exact duplicates (same shape reached twice)
+  std::vector<DimPlan> uniq;
+  for (const DimPlan& d : out) {
+    bool dup = false;
+    for (const DimPlan& u : uniq)
+      dup = dup || (u.variant == d.variant && u.m == d.m && u.p == d.p && u.q == d.q && u.E_m == d.E_m &&
+                    u.E_p == d.E_p && u.S == d.S && u.rows_per_block == d.rows_per_block);
+    if (!dup) uniq.push_back(d);
+  }
+  return uniq;
 }
 
 void root(int64_t N, int64_t e, double* re, double* im) {

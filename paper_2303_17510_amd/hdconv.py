@@ -60,7 +60,8 @@ class Plan:
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
-                 twiddles=None):
+                 twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
+                 db_path: str | None = None):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
@@ -80,6 +81,13 @@ class Plan:
             opt.p[d] = v
         for d, v in enumerate(_tup(D, dims)):
             opt.D[d] = v
+        opt.tuner = {"heuristic": _L.TUNER_HEURISTIC, "exhaustive": _L.TUNER_EXHAUSTIVE,
+                     "model": _L.TUNER_MODEL}[tuner]
+        opt.tune_reps = int(tune_reps)
+        opt.margin = float(margin)
+        opt.model = ctypes.c_void_p(model.handle if model is not None else None)
+        self._db = db_path.encode() if db_path else None
+        opt.db_path = self._db
         for name, val in (("E_m", E_m), ("E_p", E_p), ("S", S), ("rows_per_block", rows_per_block),
                           ("twiddles", twiddles)):
             for d, v in enumerate(_tup(val, dims)):
@@ -110,7 +118,10 @@ class Plan:
                 "method": {1: "hybrid", 2: "explicit"}.get(out.method, "auto"),
                 "npad": list(out.npad)[: out.dims], "workspace_bytes": out.workspace_bytes,
                 "table_bytes": out.table_bytes, "compulsory_bytes": out.compulsory_bytes,
-                "traffic_bytes": out.traffic_bytes, "launches": out.launches}
+                "traffic_bytes": out.traffic_bytes, "launches": out.launches,
+                "tuner": {0: "heuristic", 1: "exhaustive", 2: "model"}.get(out.tuner, "?"),
+                "tuned_candidates": out.tuned_candidates, "timed_candidates": out.timed_candidates,
+                "tuned_ms": out.tuned_ms}
 
     # -- execution --------------------------------------------------------
     def _check_tensor(self, t, name):

@@ -1,0 +1,176 @@
+"""Autotuning and the learned cost model, from Python.
+
+Thin wrappers over the C ABI (include/hdconv.h): candidate enumeration
+(``candidates``), device timing of one candidate (``time_shape``), the
+cost-model feature vector (``features``), and ``CostModel`` around the
+library's MLP (trained and evaluated by its HIP kernels).  Also the seeded
+geometry generator of the cost-model workload and the regret measure.
+
+The paper's optimizer (Sec. 7) picks the subtransform size and the residue
+block count empirically, tuning each dimension independently; the
+candidates here follow that decoupling: the default plan and the plan with
+one dimension's shape replaced.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+
+from . import _lib as _L
+from .hdconv import dtype_code
+
+NF = _L.NFEATURES
+SHAPE_KEYS = ("variant", "m", "p", "q", "E_m", "E_p", "S", "rows_per_block")
+
+
+def _arrs(L, M):
+    L = [int(v) for v in L]
+    M = [int(v) for v in M]
+    return (ctypes.c_int64 * 3)(*(L + [1] * (3 - len(L)))), (ctypes.c_int64 * 3)(*(M + [1] * (3 - len(M)))), len(L)
+
+
+def _shape_to_struct(shape):
+    arr = (_L.DimInfo * len(shape))()
+    for d, s in enumerate(shape):
+        for k, v in s.items():
+            if k == "variant":
+                v = {"fused": 1, "multipass": 2, "outer": 3}.get(v, v)
+            if hasattr(arr[d], k):
+                setattr(arr[d], k, int(v))
+    return arr
+
+
+def _struct_to_shape(di):
+    return {"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
+            "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p, "S": di.S,
+            "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p}
+
+
+def candidates(L, M, A=2, dtype="c64"):
+    """[(varied_dim, [per-dimension shape dicts])]; varied_dim -1 is the default plan."""
+    Ls, Ms, dims = _arrs(L, M)
+    cnt = ctypes.c_int(0)
+    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), None, None, 0, ctypes.byref(cnt)))
+    n = cnt.value
+    out = (_L.DimInfo * (n * dims))()
+    var = (ctypes.c_int * n)()
+    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), out, var, n, ctypes.byref(cnt)))
+    return [(var[k], [_struct_to_shape(out[k * dims + d]) for d in range(dims)]) for k in range(n)]
+
+
+def time_shape(L, M, shape, A=2, dtype="c64", reps=5) -> float:
+    """Median ms of `reps` executes of the plan with these per-dimension shapes."""
+    Ls, Ms, dims = _arrs(L, M)
+    ms = ctypes.c_double(0)
+    _L.check(_L.lib().hdconv_time_shape(Ls, Ms, A, 1, dims, dtype_code(dtype), _shape_to_struct(shape), reps,
+                                        ctypes.byref(ms)))
+    return ms.value
+
+
+def features(L, M, shape, A=2, dtype="c64") -> np.ndarray:
+    Ls, Ms, dims = _arrs(L, M)
+    out = (ctypes.c_float * NF)()
+    _L.check(_L.lib().hdconv_features(Ls, Ms, A, 1, dims, dtype_code(dtype), _shape_to_struct(shape), out))
+    return np.frombuffer(out, dtype=np.float32).copy()
+
+
+def _fp(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class CostModel:
+    """The library's MLP cost model (features -> predicted log ms)."""
+
+    def __init__(self, hidden: int = 64, seed: int = 0):
+        self.hidden = hidden
+        self.handle = _L.lib().hdconv_model_create(hidden, seed)
+        if not self.handle:
+            raise _L.HdconvError(_L.EDEVICE, "hdconv_model_create failed")
+
+    def params(self) -> np.ndarray:
+        n = ctypes.c_int(0)
+        _L.check(_L.lib().hdconv_model_params(self.handle, None, 0, ctypes.byref(n)))
+        buf, ptr = _fp(np.zeros(n.value))
+        _L.check(_L.lib().hdconv_model_params(self.handle, ptr, n.value, ctypes.byref(n)))
+        return buf
+
+    def load(self, params):
+        buf, ptr = _fp(params)
+        _L.check(_L.lib().hdconv_model_load(self.handle, ptr, buf.size))
+
+    def train(self, X, y, epochs=200, batch=512, lr=1e-3, seed=0) -> float:
+        X, xp = _fp(X)
+        y, yp = _fp(y)
+        loss = ctypes.c_float(0)
+        _L.check(_L.lib().hdconv_model_train(self.handle, xp, yp, len(y), int(epochs), int(batch), float(lr),
+                                             int(seed), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def predict(self, X) -> np.ndarray:
+        X, xp = _fp(X)
+        n = X.shape[0]
+        out, op = _fp(np.zeros(n))
+        _L.check(_L.lib().hdconv_model_predict(self.handle, xp, n, op))
+        return out
+
+    def grad(self, X, y):
+        X, xp = _fp(X)
+        y, yp = _fp(y)
+        n_net = self.params().size - (2 * NF + 2)
+        g, gp = _fp(np.zeros(n_net))
+        loss = ctypes.c_float(0)
+        _L.check(_L.lib().hdconv_model_grad(self.handle, xp, yp, len(y), gp, ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def save(self, path: str):
+        """Parameters as little-endian float32 (path) plus a JSON header (path + '.json')."""
+        p = self.params()
+        p.astype("<f4").tofile(path)
+        with open(path + ".json", "w") as fh:
+            json.dump({"hidden": self.hidden, "nfeatures": NF, "nparams": int(p.size),
+                       "layout": "W1,b1,W2,b2,W3,b3,W4,b4,xmean,xstd,ymean,ystd"}, fh)
+
+    @classmethod
+    def load_file(cls, path: str) -> "CostModel":
+        with open(path + ".json") as fh:
+            hdr = json.load(fh)
+        m = cls(hidden=int(hdr["hidden"]))
+        m.load(np.fromfile(path, dtype="<f4"))
+        return m
+
+    def close(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            _L.lib().hdconv_model_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def geometries(count: int, seed: int, A_choices=(2, 3), mix=(0.60, 0.25, 0.15), l1=(256, 1 << 22),
+               l2=(16, 4096), l3=(8, 384)):
+    """Seeded geometries of the cost-model workload: 1D L log-uniform in l1,
+    2D square L x L with L log-uniform in l2, 3D cubes with L log-uniform in
+    l3 (fractions `mix`); A drawn from A_choices; M = A L per dimension."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        u = rng.random()
+        dims = 1 if u < mix[0] else (2 if u < mix[0] + mix[1] else 3)
+        lo, hi = {1: l1, 2: l2, 3: l3}[dims]
+        L = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        A = int(A_choices[rng.integers(len(A_choices))])
+        out.append({"L": [L] * dims, "M": [A * L] * dims, "A": A})
+    return out
+
+
+def regret(t_pick: float, t_best: float) -> float:
+    return t_pick / t_best - 1.0
