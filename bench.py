@@ -125,17 +125,22 @@ def read_traffic(kernel: str, wlname: str, khash: str):
         return None
 
 
-def leg(wl, dtype, method, steps, warmup):
+def leg(wl, dtype, method, steps, warmup, tuner="heuristic"):
+    import math
     from paper_2303_17510_amd import Plan
     xs, dev = make_inputs(wl, dtype)
-    with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method) as p:
+    t0 = time.perf_counter()
+    with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method, tuner=tuner) as p:
+        plan_s = time.perf_counter() - t0
         info = p.info()
         ms, stats, out = time_plan(p, dev, steps, warmup)
     name, avg_ms, bpl, agg = dominant(stats)
     n_out = 1
     for l in wl["L"]:
         n_out *= l
-    r = {"dtype": dtype, "method": method, "ms": ms, "outputs_per_s": n_out / (ms * 1e-3),
+    r = {"dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s, "ms": ms,
+         "outputs_per_s": n_out / (ms * 1e-3),
+         "ns_per_NlogN": ms * 1e6 / (n_out * math.log2(max(2, n_out))),
          "plan": [(d["variant"], d["m"], d["p"], d["n"], d["q"]) for d in info["dims"]],
          "traffic_by_design_GBps": info["traffic_bytes"] / (ms * 1e-3) / 1e9,
          "compulsory_frac": info["compulsory_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -147,35 +152,42 @@ def leg(wl, dtype, method, steps, warmup):
     return r, xs, out
 
 
-def batched_leg(steps, warmup, dtype="c64", count=4096):
-    """4096 independent convolutions, L log-uniform in [64, 65536], M = 2L, one graph launch."""
+def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=None, config_id=2):
+    """Independent convolutions in one graph launch: by default 4096 with L
+    log-uniform in [64, 65536] and M = 2L."""
     import numpy as np
     import torch
     from paper_2303_17510_amd import BatchPlan, synth
-    Ls = [int(v) for v in synth.batched_lengths(count=count)]
+    if Ls is None:
+        Ls = [int(v) for v in synth.batched_lengths(count=count)]
+    count = len(Ls)
     tot = sum(Ls)
     npdt = np.complex64 if dtype == "c64" else np.complex128
-    big = [torch.from_numpy(synth.unit_disk((tot,), synth.seed_for(2, a)).astype(npdt)).cuda() for a in range(2)]
+    big = [torch.from_numpy(synth.unit_disk((tot,), synth.seed_for(config_id, a)).astype(npdt)).cuda()
+           for a in range(2)]
     out_big = torch.empty_like(big[0])
     offs = np.concatenate([[0], np.cumsum(Ls)])
     ins = [[big[a][offs[i]:offs[i + 1]] for a in range(2)] for i in range(count)]
     outs = [out_big[offs[i]:offs[i + 1]] for i in range(count)]
-    with BatchPlan(Ls, dtype=dtype) as bp:
+    t0 = time.perf_counter()
+    with BatchPlan(Ls, dtype=dtype, tuner=tuner) as bp:
+        plan_s = time.perf_counter() - t0
         groups = bp.groups()
+        bound = bp.bind(ins, outs)   # pointer tables built once, outside the timed region
         for _ in range(max(2, warmup)):   # the second execute captures the graph
-            bp.execute(ins, outs)
+            bound.execute()
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
         for _ in range(steps):
-            bp.execute(ins, outs)
+            bound.execute()
         t1.record()
         torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     w = 8 if dtype == "c64" else 16
-    return {"dtype": dtype, "method": "hybrid, batched graph", "convolutions": count, "outputs": tot,
-            "ms": ms, "outputs_per_s": tot / (ms * 1e-3),
+    return {"dtype": dtype, "method": "hybrid, batched graph", "tuner": tuner, "plan_s": plan_s,
+            "convolutions": count, "outputs": tot, "ms": ms, "outputs_per_s": tot / (ms * 1e-3),
             "compulsory_frac": 3 * w * tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "groups": [(g["variant"], g["m"], g["p"], g["q"], g["count"]) for g in groups]}
 
@@ -264,12 +276,23 @@ def main():
         r, _, o = leg(wl, "c128", "explicit", max(10, args.steps // 4), 5)
         compare["explicit_c128"] = r
         outs["c128"]["explicit_c128"] = o
+        r, _, _ = leg(wl, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
+        compare["hybrid_c64_tuned"] = r
+        r, _, _ = leg(wl, "c128", "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
+        compare["hybrid_c128_tuned"] = r
         if args.workload == "c2":
-            r, _, _ = leg(workload("c2_1p5m"), "c64", "hybrid", max(10, args.steps // 4), 5)
-            compare["L1500000_hybrid_c64"] = r
-            r, _, _ = leg(workload("c2_1p5m"), "c64", "explicit", max(10, args.steps // 4), 5)
-            compare["L1500000_explicit_c64"] = r
+            w15 = workload("c2_1p5m")
+            for dt in ("c64", "c128"):
+                r, _, _ = leg(w15, dt, "hybrid", max(10, args.steps // 4), 5)
+                compare["L1500000_hybrid_%s" % dt] = r
+                r, _, _ = leg(w15, dt, "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
+                compare["L1500000_hybrid_%s_tuned" % dt] = r
+                r, _, _ = leg(w15, dt, "explicit", max(10, args.steps // 4), 5)
+                compare["L1500000_explicit_%s" % dt] = r
             compare["batched_4096_c64"] = batched_leg(max(10, args.steps // 10), 3)
+            compare["batched_4096_c64_tuned"] = batched_leg(max(10, args.steps // 10), 3, tuner="exhaustive")
+            compare["C1_8192_copies_c128"] = batched_leg(max(10, args.steps // 10), 3, dtype="c128",
+                                                          Ls=[1024] * 8192, config_id=0)
         for k, v in compare.items():
             dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],

@@ -198,7 +198,14 @@ void hdconv_model_destroy(void* model);
  * on parallel branches (four side streams forked from and joined to the
  * execute stream), and from the second execute on the whole batch is one
  * hipGraph launch.  Allocates per-group tables, workspace, a device task
- * table and a pinned staging copy of it.  NULL on error. */
+ * table and a pinned staging copy of it.  NULL on error.
+ * With opt->tuner EXHAUSTIVE or MODEL, each group of the heuristic plan (a
+ * size bucket) is tuned: the candidates are the one-dimensional candidates
+ * of its longest member plus row-packing variants of the whole-row kernel,
+ * timed as the batch runs them (all rows of the group, their own lengths,
+ * zeroed scratch buffers); EXHAUSTIVE times all, MODEL ranks them with
+ * opt->model and times the top three when the best two predictions are
+ * within opt->margin.  Groups whose tuned shapes coincide are merged. */
 void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
                           const hdconv_options* opt);
 

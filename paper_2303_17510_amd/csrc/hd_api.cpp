@@ -146,7 +146,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
           for (int pass = 0; pass < 2 && m == 0; ++pass) {
             const int64_t mmax = pass == 0 ? (tb == 4 ? 8192 : 4096) : kMaxRowM;
             for (int64_t c = mmax; c >= 8 && m == 0; --c)
-              if (fft_size_ok(c) && Le % c == 0 && fft_size_ok(Le / c) && Le / c <= kMaxColP) m = c;
+              if (fft_size_ok(c) && Le % c == 0 && col_size_ok(Le / c) && Le / c <= kMaxColP) m = c;
           }
           if (m == 0) return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d: no split of N'=%lld", d, (long long)Le);
           dp.m = m;
@@ -172,7 +172,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       if (g.inner && fv != VAR_MULTI)
         return set_err(HDCONV_EINVAL, "dim %d: m=%lld gives p=%lld > 2, which needs the multipass variant", d,
                        (long long)m, (long long)g.p);
-      if (fv == VAR_MULTI && !fft_size_ok(g.p)) {
+      if (fv == VAR_MULTI && !col_size_ok(g.p)) {
         g = geometry(Le, Me, m, next_col_size(g.p), true);
       }
       dp = DimPlan{};
@@ -1038,31 +1038,30 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
   *ncand = nc;
   *ntimed = 0;
   const int reps = opt->tune_reps > 0 ? opt->tune_reps : 5;
-  std::vector<double> score(nc, 1e300);  // measured ms or predicted log-ms
+  // measured ms (timed candidates) and, for the model tuner, predicted log ms
+  std::vector<double> meas(nc, 1e300), pred(nc, 0.0);
   std::vector<char> timed(nc, 0);
   auto time_one = [&](int k) -> int {
     double ms = 0;
     int r = hdconv_time_shape(L, M, A, B, dims, dtype, &cand[(size_t)k * dims], reps, &ms);
+    timed[k] = 1;  // a candidate that cannot run keeps meas = 1e300
     if (r != HDCONV_OK) return r;
-    score[k] = ms;
-    timed[k] = 1;
+    meas[k] = ms;
     (*ntimed)++;
     if (opt->db_path) db_append(opt->db_path, L, M, A, dims, dtype, &cand[(size_t)k * dims], varied[k], ms);
     return HDCONV_OK;
   };
-  if (opt->tuner == HDCONV_TUNER_EXHAUSTIVE) {
-    for (int k = 0; k < nc; ++k) {
-      int r = time_one(k);
-      if (r != HDCONV_OK) score[k] = 1e300;  // a candidate that cannot run is skipped
-    }
+  const bool model = opt->tuner == HDCONV_TUNER_MODEL;
+  if (!model) {
+    for (int k = 0; k < nc; ++k) (void)time_one(k);
   } else {
     if (!opt->model) return set_err(HDCONV_EINVAL, "the model tuner needs options.model");
-    std::vector<float> X((size_t)nc * HDCONV_NFEATURES), pred(nc);
+    std::vector<float> X((size_t)nc * HDCONV_NFEATURES), pf(nc);
     for (int k = 0; k < nc; ++k)
       if ((rc = hdconv_features(L, M, A, B, dims, dtype, &cand[(size_t)k * dims], &X[(size_t)k * HDCONV_NFEATURES])) != HDCONV_OK)
         return rc;
-    if ((rc = hd::mlp_predict_host(opt->model, X.data(), nc, pred.data())) != HDCONV_OK) return rc;
-    for (int k = 0; k < nc; ++k) score[k] = pred[k];
+    if ((rc = hd::mlp_predict_host(opt->model, X.data(), nc, pf.data())) != HDCONV_OK) return rc;
+    for (int k = 0; k < nc; ++k) pred[k] = pf[k];
   }
   // per dimension, the best candidate varying that dimension (or the default)
   const double margin = opt->margin > 0 ? opt->margin : 0.05;
@@ -1070,22 +1069,17 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
     std::vector<int> ks;
     for (int k = 0; k < nc; ++k)
       if (varied[k] == -1 || varied[k] == d) ks.push_back(k);
-    std::sort(ks.begin(), ks.end(), [&](int a, int b) { return score[a] < score[b]; });
+    const std::vector<double>& key = model ? pred : meas;
+    std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return key[a] < key[b]; });
     int best = ks[0];
-    if (opt->tuner == HDCONV_TUNER_MODEL && ks.size() > 1 && score[ks[1]] - score[ks[0]] < margin) {
-      // close call: time the predicted top three and keep the fastest
+    if (model && ks.size() > 1 && pred[ks[1]] - pred[ks[0]] < margin) {
+      // close call: time the predicted top three and keep the fastest that runs
       double bm = 1e300;
       for (size_t i = 0; i < ks.size() && i < 3; ++i) {
         const int k = ks[i];
-        if (!timed[k]) {
-          const double pred = score[k];
-          if (time_one(k) != HDCONV_OK) {
-            score[k] = pred;
-            continue;
-          }
-        }
-        if (score[k] < bm) {
-          bm = score[k];
+        if (!timed[k]) (void)time_one(k);
+        if (meas[k] < bm) {
+          bm = meas[k];
           best = k;
         }
       }
@@ -1100,7 +1094,7 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
       same = same && a.variant == b.variant && a.m == b.m && a.p == b.p && a.E_m == b.E_m && a.E_p == b.E_p &&
              a.S == b.S && a.rows_per_block == b.rows_per_block;
     }
-    if (same && timed[k]) *best_ms = score[k];
+    if (same && timed[k] && meas[k] < 1e300) *best_ms = meas[k];
   }
   return HDCONV_OK;
 }
@@ -1225,6 +1219,7 @@ struct Batch {
   std::vector<hipEvent_t> joins;
   hipGraphExec_t exec = nullptr;
   int executes = 0;
+  int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
 };
 
 // A one-dimensional plan for `rows` independent rows sharing the shape dp.
@@ -1346,6 +1341,175 @@ static int run_batched(Batch* Bt, const void* const* inputs, void* const* output
   return HDCONV_OK;
 }
 
+// Median ms of one group's launches with shape dp over rows of the given
+// lengths (each row in its own zeroed slot of Lmax words), as the batch runs
+// them.  Returns a non-OK code if the shape cannot be planned or launched.
+template <typename T>
+static int time_group_ms(int A, int B, int dtype, const DimPlan& dp, const std::vector<int64_t>& Ls, int device,
+                         int reps, double* ms) {
+  const int64_t rows = (int64_t)Ls.size();
+  int64_t Lmax = 1;
+  for (int64_t v : Ls) Lmax = std::max(Lmax, v);
+  Plan* P = make_group_plan(A, B, dtype, dp, rows, device);
+  if (!P) return g_err_code;
+  const size_t bytes = (size_t)rows * (size_t)Lmax * sizeof(cpx<T>);
+  cpx<T>* buf[kMaxA + 1] = {nullptr, nullptr, nullptr, nullptr};
+  RowTask<T>* tdev = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<float> t;
+  int rc = HDCONV_OK;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  for (int a = 0; a <= A && e == hipSuccess; ++a) {
+    e = hipMalloc((void**)&buf[a], bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(buf[a], 0, bytes, s);
+  }
+  std::vector<RowTask<T>> th((size_t)rows);
+  for (int64_t i = 0; i < rows; ++i) {
+    RowTask<T> r{};
+    for (int a = 0; a < A; ++a) r.in[a] = buf[a] ? buf[a] + i * Lmax : nullptr;
+    r.out = buf[A] ? buf[A] + i * Lmax : nullptr;
+    r.L = Ls[(size_t)i];
+    th[(size_t)i] = r;
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&tdev, th.size() * sizeof(RowTask<T>));
+  if (e == hipSuccess) e = hipMemcpyAsync(tdev, th.data(), th.size() * sizeof(RowTask<T>), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    rc = set_err(HDCONV_ENOMEM, "batch tuning buffers: %s", hipGetErrorString(e));
+  } else {
+    rc = run_rows<T>(P, nullptr, nullptr, rows, s, tdev);  // warm-up
+    for (int r = 0; r < reps && rc == HDCONV_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      rc = run_rows<T>(P, nullptr, nullptr, rows, s, tdev);
+      (void)hipEventRecord(e1, s);
+      float x = 0;
+      if (rc == HDCONV_OK && (e = hipEventSynchronize(e1)) == hipSuccess &&
+          (e = hipEventElapsedTime(&x, e0, e1)) == hipSuccess)
+        t.push_back(x);
+      else if (rc == HDCONV_OK)
+        rc = hip_err(e, "batch tuning timing");
+    }
+  }
+  if (s) (void)hipStreamSynchronize(s);
+  for (cpx<T>* b : buf)
+    if (b) (void)hipFree(b);
+  if (tdev) (void)hipFree(tdev);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  free_plan(P);
+  if (rc == HDCONV_OK) {
+    std::sort(t.begin(), t.end());
+    *ms = t.empty() ? 0.0 : t[t.size() / 2];
+  }
+  return rc;
+}
+
+// Per-group tuning of a batched plan (the size buckets are the heuristic
+// groups).  Candidates are the one-dimensional candidates of the group's
+// longest member (so every member fits every candidate), plus row-packing
+// variants of the whole-row kernel; the exhaustive tuner times all of them
+// over the group's own lengths, the model tuner ranks them by predicted time
+// and times the top three when the best two are within the margin.  Groups
+// whose tuned shapes coincide are merged.  Returns candidates and timings
+// counted into *ncand / *ntimed.
+static int tune_batch_groups(int A, int B, int dtype, int device, const hdconv_options* opt,
+                             const std::vector<int64_t>& Lall, std::map<GroupKey, std::vector<int64_t>>* byk,
+                             std::map<GroupKey, DimPlan>* shape, int* ncand, int* ntimed) {
+  const int tb = tbytes_of(dtype);
+  const int reps = opt->tune_reps > 0 ? opt->tune_reps : 5;
+  const double margin = opt->margin > 0 ? opt->margin : 0.05;
+  const bool model = opt->tuner == HDCONV_TUNER_MODEL;
+  if (model && !opt->model) return set_err(HDCONV_EINVAL, "the model tuner needs options.model");
+  std::map<GroupKey, std::vector<int64_t>> nbyk;
+  std::map<GroupKey, DimPlan> nshape;
+  for (auto& kv : *byk) {
+    const DimPlan& base = (*shape)[kv.first];
+    std::vector<int64_t> Ls;
+    for (int64_t i : kv.second) Ls.push_back(Lall[(size_t)i]);
+    std::vector<DimPlan> cands = {base};
+    auto same = [](const DimPlan& a, const DimPlan& b) {
+      return a.variant == b.variant && a.m == b.m && a.p == b.p && a.q == b.q && a.E_m == b.E_m &&
+             a.E_p == b.E_p && a.S == b.S && a.rows_per_block == b.rows_per_block;
+    };
+    auto add = [&](const DimPlan& c) {
+      for (const DimPlan& u : cands)
+        if (same(u, c)) return;
+      cands.push_back(c);
+    };
+    for (const DimPlan& c : dim_candidates(base.L, base.M, A, tb, true)) {
+      add(c);
+      if (c.variant == VAR_FUSED)
+        for (int f : {2, 4}) {
+          for (int dir = 0; dir < 2; ++dir) {
+            DimPlan v = c;
+            v.rows_per_block = dir ? c.rows_per_block * f : c.rows_per_block / f;
+            std::string w;
+            if (v.rows_per_block >= 1 && finish_dim(&v, A, tb, &w)) add(v);
+          }
+        }
+    }
+    const int nc = (int)cands.size();
+    *ncand += nc;
+    std::vector<double> meas(nc, 1e300), pred(nc, 0.0);
+    auto time_one = [&](int k) {
+      double ms = 0;
+      const int r = tb == 4 ? time_group_ms<float>(A, B, dtype, cands[k], Ls, device, reps, &ms)
+                            : time_group_ms<double>(A, B, dtype, cands[k], Ls, device, reps, &ms);
+      if (r == HDCONV_OK && ms > 0) {
+        meas[k] = ms;
+        (*ntimed)++;
+      }
+    };
+    int best = 0;
+    if (!model) {
+      for (int k = 0; k < nc; ++k) time_one(k);
+      for (int k = 1; k < nc; ++k)
+        if (meas[k] < meas[best]) best = k;
+    } else {
+      std::vector<float> X((size_t)nc * HDCONV_NFEATURES), pf(nc);
+      for (int k = 0; k < nc; ++k) {
+        hdconv_dim_info_t di;
+        fill_dim_info(cands[k], &di);
+        const int r = hdconv_features(&base.L, &base.M, A, B, 1, dtype, &di, &X[(size_t)k * HDCONV_NFEATURES]);
+        if (r != HDCONV_OK) return r;
+      }
+      int r = hd::mlp_predict_host(opt->model, X.data(), nc, pf.data());
+      if (r != HDCONV_OK) return r;
+      std::vector<int> ks(nc);
+      for (int k = 0; k < nc; ++k) ks[k] = k;
+      std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return pf[a] < pf[b]; });
+      best = ks[0];
+      if (nc > 1 && pf[ks[1]] - pf[ks[0]] < margin) {
+        double bm = 1e300;
+        for (int i = 0; i < nc && i < 3; ++i) {
+          time_one(ks[i]);
+          if (meas[ks[i]] < bm) {
+            bm = meas[ks[i]];
+            best = ks[i];
+          }
+        }
+      }
+    }
+    DimPlan dp = cands[best];
+    GroupKey k{dp.variant, dp.m, dp.p, dp.n, dp.q, dp.E_m, dp.E_p, dp.S, dp.rows_per_block};
+    auto it = nshape.find(k);
+    if (it == nshape.end()) nshape[k] = dp;
+    else {
+      it->second.L = std::max(it->second.L, dp.L);
+      it->second.M = std::max(it->second.M, dp.M);
+    }
+    auto& mem = nbyk[k];
+    mem.insert(mem.end(), kv.second.begin(), kv.second.end());
+  }
+  for (auto& kv : nbyk) std::sort(kv.second.begin(), kv.second.end());
+  *byk = std::move(nbyk);
+  *shape = std::move(nshape);
+  return HDCONV_OK;
+}
+
 extern "C" {
 
 void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
@@ -1411,6 +1575,16 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
       it->second.M = std::max(it->second.M, dp.M);
     }
     byk[k].push_back(i);
+  }
+  if (opt && opt->tuner != HDCONV_TUNER_HEURISTIC) {
+    int nc = 0, nt = 0;
+    if (tune_batch_groups(A, B, dtype, Bt->device, opt, Bt->L, &byk, &shape, &nc, &nt) != HDCONV_OK) {
+      free_batch(Bt);
+      return nullptr;
+    }
+    Bt->tuner = opt->tuner;
+    Bt->tuned_candidates = nc;
+    Bt->timed_candidates = nt;
   }
   // largest rows first, so long groups start early on their side stream
   std::vector<GroupKey> order;

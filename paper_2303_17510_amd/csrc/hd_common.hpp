@@ -59,16 +59,29 @@ __device__ __forceinline__ cpx<T> czero() {
 //   zeta_N^e = lo[e & (K-1)] * hi[e >> kbits],  0 <= e < N,  K = 2^kbits.
 // Both halves are rounded from FP64 values, so an entry is within about two
 // ulps of the exact root.
+// Loads and stores at a 32-bit byte offset from a base pointer: with a
+// wave-uniform base the address is one scalar pair plus one vector register,
+// instead of a 64-bit vector address per access.
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_at(const cpx<T>* base, uint32_t idx) {
+  return *(const cpx<T>*)((const char*)base + idx * (uint32_t)sizeof(cpx<T>));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(cpx<T>* base, uint32_t idx, cpx<T> v) {
+  *(cpx<T>*)((char*)base + idx * (uint32_t)sizeof(cpx<T>)) = v;
+}
+
+// The planner keeps every transform length N below 2^27, so element offsets
+// within one row or one column block times the word size stay below 2^32.
 template <typename T>
 struct RootTable {
   const cpx<T>* lo;
   const cpx<T>* hi;
   int64_t N;
   int kbits;
-  __device__ __forceinline__ cpx<T> get(int64_t e) const {
-    cpx<T> a = lo[e & ((int64_t(1) << kbits) - 1)];
-    int64_t h = e >> kbits;
-    return h == 0 ? a : cmul(a, hi[h]);
+  __device__ __forceinline__ cpx<T> get(int64_t e64) const {
+    const uint32_t e = (uint32_t)e64;
+    return cmul(ld_at(lo, e & ((1u << kbits) - 1)), ld_at(hi, e >> kbits));
   }
   // zeta_N^{(a*b) mod N} for non-negative a, b with a*b < 2^63
   __device__ __forceinline__ cpx<T> pow_prod(int64_t a, int64_t b) const {

@@ -248,42 +248,6 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int 
   }
 }
 
-// NT transforms of one size at once.  Every lane of the workgroup must call
-// this with the same descriptor (the stage count decides the barriers).
-template <typename T, int E, int S, int NT>
-__device__ __forceinline__ void gfft(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
-                                     const Xchg<T>& xb) {
-  int Ns = 1;
-  for (int st = 0; st < d.nst; ++st) {
-    const int R = d.radix[st];
-    const bool last = (st == d.nst - 1);
-    const int to = d.twoff[st];
-    switch (R) {
-      case 2:
-        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      case 3:
-        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      case 4:
-        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      case 8:
-        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      case 16:
-        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      case 32:
-        if constexpr (E % 32 == 0) fft_stage<T, E, 32, S, NT>(v, g, d.G, d.N, Ns, to, tw, xb, last);
-        break;
-      default:
-        break;
-    }
-    Ns *= R;
-  }
-}
-
 // Stage radix for `rem` points left, the same rule make_fft_desc applies on
 // the host: factors 3 first, then the largest power of two up to 16 that
 // divides both E and rem.
@@ -293,6 +257,46 @@ __host__ __device__ constexpr int ct_radix(int rem, int E) {
   while (r < 16 && E % (2 * r) == 0) r *= 2;
   while (r > 1 && rem % r != 0) r /= 2;
   return r;
+}
+
+// NT transforms of one size at once.  Every lane of the workgroup must call
+// this with the same descriptor (the stage count decides the barriers).  The
+// stage radices are recomputed from (N, E) by the planner's rule rather than
+// read from d.radix[], and the per-stage table offsets accumulate as in
+// make_fft_desc: indexing the descriptor's arrays with a run-time stage
+// number would make the compiler copy the whole kernel argument block to
+// scratch memory.
+template <typename T, int E, int S, int NT>
+__device__ __forceinline__ void gfft(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
+                                     const Xchg<T>& xb) {
+  const int N = d.N, G = d.G;
+  int Ns = 1, rem = N, to = 0;
+  while (rem > 1) {
+    const int R = ct_radix(rem, E);
+    const bool last = (R == rem);
+    switch (R) {
+      case 2:
+        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        break;
+      case 3:
+        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        break;
+      case 4:
+        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        break;
+      case 8:
+        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        break;
+      case 16:
+        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        break;
+      default:
+        return;  // no such plan (the host never builds one)
+    }
+    if (Ns > 1) to += Ns * (R - 1);
+    Ns *= R;
+    rem /= R;
+  }
 }
 
 // The same transform with N and E known at compile time: the stage plan is
@@ -313,7 +317,6 @@ template <int E, int N>
 __host__ __device__ constexpr bool ct_size() {
   if (E == 8) return N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096;
   if (E == 16) return N == 1024 || N == 2048 || N == 4096 || N == 8192;
-  if (E == 32) return N == 2048 || N == 4096 || N == 8192 || N == 16384;
   return false;
 }
 
@@ -321,15 +324,21 @@ __host__ __device__ constexpr bool ct_size() {
 // general path.
 constexpr unsigned kCtFused = 0;
 constexpr unsigned kCtRows = (1u << 11) | (1u << 12) | (1u << 13);
-constexpr unsigned kCtCols = (1u << 7) | (1u << 8) | (1u << 9);
+constexpr unsigned kCtCols = 0;
 constexpr unsigned kCtOuter = 0;
 
 // Transform with the specialised plan when one exists for (N, E) and the
 // kernel kind's MASK selects N, else the general one.  d.N is the same on
 // every lane, so the branch is uniform.
 template <typename T, int E, int S, int NT, unsigned MASK>
-__device__ __forceinline__ void gfft_any(cpx<T> (&v)[NT][E], int g, const FftDesc& d, const TwLds<T>& tw,
+__device__ __forceinline__ void gfft_any(cpx<T> (&v)[NT][E], int g_in, const FftDesc& d, const TwLds<T>& tw,
                                          const Xchg<T>& xb) {
+  // The butterfly twiddles depend only on the lane, so a caller that
+  // transforms in a loop (residues) would have them hoisted out of the loop
+  // and kept live across it, which costs more registers than recomputing
+  // them; an opaque copy of the lane index keeps them inside.
+  int g = g_in;
+  asm volatile("" : "+v"(g));
 #define HD_CT(NN)                                              \
   if constexpr (ct_size<E, NN>() && (MASK & (NN)) != 0) {      \
     if (d.N == NN) {                                           \

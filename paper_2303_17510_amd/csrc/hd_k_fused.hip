@@ -19,6 +19,9 @@ namespace hd {
 // run together (shared twiddles and barriers).
 template <typename T, int E, int P, int A>
 __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
+  // Inputs small enough stay in registers across the residues; larger ones
+  // are read again for each residue (from cache) to keep registers free.
+  constexpr bool kKeep = P * A * E <= 16;
   const int G = a.fd.G;
   const int m = a.m;
   const int slot = threadIdx.x / G;
@@ -27,24 +30,28 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   const bool valid = row < a.nrows;
   // per-row pointers and length: from the task table (batched plans) or strided rows
   const RowTask<T>* tk = (a.tasks && valid) ? a.tasks + row : nullptr;
-  const int64_t L = valid ? (tk ? tk->L : a.L) : 0;
-  const int64_t qm = (int64_t)a.q * m;
+  const uint32_t L = valid ? (uint32_t)(tk ? tk->L : a.L) : 0u;
+  const uint32_t qm = (uint32_t)a.q * (uint32_t)m;
+  const cpx<T>* src[A];
+#pragma unroll
+  for (int ai = 0; ai < A; ++ai) src[ai] = tk ? tk->in[ai] : a.in[ai] + row * a.in_stride;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
 
-  // the row's inputs, read once (zero beyond L)
-  cpx<T> x[A][P][E];
+  // the row's inputs (zero beyond L)
+  auto load = [&](int ai, int t, int e) -> cpx<T> {
+    const uint32_t j = (uint32_t)(t * m + g + G * e);
+    return j < L ? ld_at(src[ai], j) : czero<T>();
+  };
+  cpx<T> x[kKeep ? A : 1][kKeep ? P : 1][kKeep ? E : 1];
+  if constexpr (kKeep) {
 #pragma unroll
-  for (int ai = 0; ai < A; ++ai) {
-    const cpx<T>* src = tk ? tk->in[ai] : a.in[ai] + row * a.in_stride;
+    for (int ai = 0; ai < A; ++ai)
 #pragma unroll
-    for (int t = 0; t < P; ++t)
+      for (int t = 0; t < P; ++t)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int64_t j = (int64_t)t * m + g + G * e;
-        x[ai][t][e] = j < L ? src[j] : czero<T>();
-      }
+        for (int e = 0; e < E; ++e) x[ai][t][e] = load(ai, t, e);
   }
   __syncthreads();
 
@@ -56,7 +63,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
 
   for (int r = 0; r < a.q; ++r) {
     // exponents of zeta_{qm}^{r j} for j = t m + g + G e advance by r G per e
-    const int64_t st = ((int64_t)r * G) % qm;
+    const uint32_t st = (uint32_t)(((uint64_t)r * G) % qm);
     cpx<T> w[A][E];
 #pragma unroll
     for (int ai = 0; ai < A; ++ai)
@@ -64,12 +71,17 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      int64_t ex = ((int64_t)r * (t * m + g)) % qm;
+      uint32_t ex = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const cpx<T> z = a.zqm.get(ex);
 #pragma unroll
-        for (int ai = 0; ai < A; ++ai) w[ai][e] = w[ai][e] + cmul(x[ai][t][e], z);
+        for (int ai = 0; ai < A; ++ai) {
+          cpx<T> xv;
+          if constexpr (kKeep) xv = x[ai][t][e];
+          else xv = load(ai, t, e);
+          w[ai][e] = w[ai][e] + cmul(xv, z);
+        }
         ex += st;
         if (ex >= qm) ex -= qm;
       }
@@ -86,7 +98,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      int64_t ex = ((int64_t)r * (t * m + g)) % qm;
+      uint32_t ex = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         acc[t][e] = acc[t][e] + cmulc(prod[0][e], a.zqm.get(ex));
@@ -101,8 +113,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     for (int t = 0; t < P; ++t)
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int64_t j = (int64_t)t * m + g + G * e;
-        if (j < L) dst[j] = cscale(acc[t][e], a.scale);
+        const uint32_t j = (uint32_t)(t * m + g + G * e);
+        if (j < L) st_at(dst, j, cscale(acc[t][e], a.scale));
       }
   }
 }
@@ -132,9 +144,10 @@ hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_
   const size_t lds = lds_fused1d(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
 #define F1(EE, PP, AA) \
   if (E == EE && P == PP && A == AA) return go(k_fused1d<T, EE, PP, AA>, grid, block, lds, s, a);
+  F1(4, 1, 2) F1(4, 2, 2) F1(4, 1, 3) F1(4, 2, 3)
   F1(8, 1, 2) F1(8, 2, 2) F1(8, 1, 3) F1(8, 2, 3)
+  F1(12, 1, 2) F1(12, 2, 2) F1(12, 1, 3) F1(12, 2, 3)
   F1(16, 1, 2) F1(16, 2, 2) F1(16, 1, 3) F1(16, 2, 3)
-  F1(24, 1, 2) F1(24, 2, 2) F1(24, 1, 3) F1(24, 2, 3)
 #undef F1
   return HD_BAD;
 }

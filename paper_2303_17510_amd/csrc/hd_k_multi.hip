@@ -55,7 +55,9 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
 }
 
 // Inner form, pass 2: m-point convolution rows.  The A rows are loaded
-// together and transformed together.
+// together and transformed together.  The twiddles zeta_{qm}^{r s} are looked
+// up again for the post-multiplication rather than kept in registers across
+// the transforms.
 template <typename T, int E, int A>
 __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   const int G = a.fd.G, m = a.m, p = a.p;
@@ -65,8 +67,11 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   const bool valid = R2 < a.nrows;
   const int u = (int)(R2 % p);
   const int dv = (int)((R2 / p) % a.D);
-  const int64_t r = (int64_t)u * a.n + a.v0 + dv;
-  const int64_t qm = a.qm;
+  const uint32_t qm = (uint32_t)a.qm;
+  // twiddle exponent r s mod qm for s = g + G e: start and step
+  const uint64_t r = (uint64_t)u * a.n + a.v0 + dv;
+  const uint32_t ex0 = (uint32_t)((r * (uint32_t)g) % qm);
+  const uint32_t st = (uint32_t)((r * (uint32_t)G) % qm);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
 
@@ -75,24 +80,20 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   for (int ai = 0; ai < A; ++ai) {
     const cpx<T>* src = a.work[ai] + R2 * m;
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[ai][e] = valid ? src[g + G * e] : czero<T>();
+    for (int e = 0; e < E; ++e) x[ai][e] = valid ? ld_at(src, (uint32_t)(g + G * e)) : czero<T>();
   }
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
-  cpx<T> z[E];
   {
-    int64_t ex = (r * g) % qm;
-    const int64_t st = (r * G) % qm;
+    uint32_t ex = ex0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      z[e] = a.zqm.get(ex);
+      const cpx<T> z = a.zqm.get(ex);
+#pragma unroll
+      for (int ai = 0; ai < A; ++ai) x[ai][e] = cmul(x[ai][e], z);
       ex += st;
       if (ex >= qm) ex -= qm;
     }
   }
-#pragma unroll
-  for (int ai = 0; ai < A; ++ai)
-#pragma unroll
-    for (int e = 0; e < E; ++e) x[ai][e] = cmul(x[ai][e], z[e]);
   __syncthreads();
   gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
   cpx<T> prod[1][E];
@@ -106,8 +107,13 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
   if (valid) {
     cpx<T>* dst = a.work[0] + R2 * m;
+    uint32_t ex = ex0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[g + G * e] = cmulc(prod[0][e], z[e]);
+    for (int e = 0; e < E; ++e) {
+      st_at(dst, (uint32_t)(g + G * e), cmulc(prod[0][e], a.zqm.get(ex)));
+      ex += st;
+      if (ex >= qm) ex -= qm;
+    }
   }
 }
 
@@ -170,7 +176,7 @@ hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s) 
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
 #define C1(EE) \
   if (E == EE) return go(k_cols_fwd<T, EE>, grid, block, lds, s, a);
-  C1(1) C1(2) C1(4) C1(8) C1(16) C1(24)
+  C1(1) C1(2) C1(4) C1(8) C1(12) C1(16)
 #undef C1
   return HD_BAD;
 }
@@ -183,7 +189,7 @@ hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s
   const size_t lds = lds_rows(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
 #define R1(EE, AA) \
   if (E == EE && A == AA) return go(k_rows_conv<T, EE, AA>, grid, block, lds, s, a);
-  R1(8, 2) R1(8, 3) R1(16, 2) R1(16, 3) R1(24, 2) R1(24, 3) R1(32, 2) R1(32, 3)
+  R1(4, 2) R1(4, 3) R1(8, 2) R1(8, 3) R1(12, 2) R1(12, 3) R1(16, 2) R1(16, 3)
 #undef R1
   return HD_BAD;
 }
@@ -196,7 +202,7 @@ hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s) {
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
 #define C1(EE) \
   if (E == EE) return go(k_cols_bwd<T, EE>, grid, block, lds, s, a);
-  C1(1) C1(2) C1(4) C1(8) C1(16) C1(24)
+  C1(1) C1(2) C1(4) C1(8) C1(12) C1(16)
 #undef C1
   return HD_BAD;
 }

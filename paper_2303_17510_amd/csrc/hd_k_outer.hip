@@ -134,7 +134,7 @@ hipError_t launch_outer_fwd(const OuterFwdArgs<T>& a, int E, int P, int A, hipSt
   const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
 #define O1(EE, PP) \
   if (E == EE && P == PP) return go(k_outer_fwd<T, EE, PP>, grid, block, lds, s, a);
-  O1(8, 1) O1(8, 2) O1(16, 1) O1(16, 2) O1(24, 1) O1(24, 2) O1(32, 1) O1(32, 2)
+  O1(4, 1) O1(4, 2) O1(8, 1) O1(8, 2) O1(12, 1) O1(12, 2) O1(16, 1) O1(16, 2)
 #undef O1
   return HD_BAD;
 }
@@ -147,7 +147,7 @@ hipError_t launch_outer_bwd(const OuterBwdArgs<T>& a, int E, int P, hipStream_t 
   const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
 #define O1(EE, PP) \
   if (E == EE && P == PP) return go(k_outer_bwd<T, EE, PP>, grid, block, lds, s, a);
-  O1(8, 1) O1(8, 2) O1(16, 1) O1(16, 2) O1(24, 1) O1(24, 2) O1(32, 1) O1(32, 2)
+  O1(4, 1) O1(4, 2) O1(8, 1) O1(8, 2) O1(12, 1) O1(12, 2) O1(16, 1) O1(16, 2)
 #undef O1
   return HD_BAD;
 }

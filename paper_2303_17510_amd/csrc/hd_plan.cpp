@@ -44,7 +44,22 @@ int64_t next_fft_size(int64_t n) {
   return best;
 }
 
-int64_t next_col_size(int64_t n) { return next_fft_size(n); }
+// Column transform sizes: powers of two and 3 * 2^a with a >= 2 (12, 24, ...).
+bool col_size_ok(int64_t p) {
+  if (p < 1) return false;
+  if ((p & (p - 1)) == 0) return true;
+  if (p % 3 != 0) return false;
+  const int64_t t = p / 3;
+  return (t & (t - 1)) == 0 && t >= 4;
+}
+
+int64_t next_col_size(int64_t n) {
+  int64_t best = 1;
+  while (best < n) best <<= 1;
+  for (int64_t t = 4; 3 * t < best; t <<= 1)
+    if (3 * t >= n) return 3 * t;
+  return best;
+}
 
 bool make_fft_desc(int64_t N, int E, FftDesc* d) {
   *d = FftDesc{};
@@ -92,30 +107,51 @@ static int pow2_floor(int64_t x) {
   return r;
 }
 
-// Points per lane of a row transform: enough that a row of m points needs at
-// most kMaxThreads lanes, few enough to stay in registers.
+// Points per lane of a row transform (fused and row kernels): enough that m
+// points need at most kMaxThreads lanes, few enough that the kernel keeps
+// its values in registers.  Sizes with a factor 3 take 12 (radices 3 and 4).
+// Powers of two: measured on gfx950, the row pass is fastest with fewer,
+// wider passes (16 points per lane in FP32 from m = 2048, 8 in FP64), the
+// whole-row kernel with 8 (FP32, m >= 1024) or 4 points per lane.
 static bool pick_e_row(int64_t m, bool fused, int tbytes, int* E) {
-  (void)tbytes;
   if (m % 3 == 0) {
-    *E = 24;
-    return m % 24 == 0 && m / 24 <= kMaxThreads;
+    *E = 12;
+    return m % 12 == 0 && m / 12 <= kMaxThreads;
   }
-  (void)fused;
-  *E = m <= 4096 ? 8 : (m <= 8192 ? 16 : 32);
-  return m >= *E && m / *E <= kMaxThreads;
+  int e;
+  if (tbytes == 4) e = fused ? (m >= 1024 ? 8 : 4) : (m >= 2048 ? 16 : 8);
+  else e = m >= 2048 ? 8 : 4;
+  while (m / e > kMaxThreads && e < 16) e *= 2;
+  if (m < e) e = (int)m;
+  *E = e;
+  return m % e == 0 && m / e <= kMaxThreads;
 }
 
-static bool pick_e_col(int64_t p, int* E) {
+// Points per lane of a column transform (p points per column).
+static bool pick_e_col(int64_t p, int tbytes, int* E) {
   if (p % 3 == 0) {
-    *E = 24;
-    return p % 24 == 0;
+    *E = 12;
+    return p % 12 == 0 && p / 12 <= kMaxThreads;
   }
   if (p <= 8) {
     *E = (int)p;
     return p == 1 || p == 2 || p == 4 || p == 8;
   }
-  *E = (p > 512) ? 16 : 8;
-  return true;
+  const int e0 = tbytes == 4 ? 8 : 4;
+  *E = p / e0 <= kMaxThreads ? e0 : (p / 8 <= kMaxThreads ? 8 : 16);
+  return p / *E <= kMaxThreads;
+}
+
+// Points per lane of an outer-dimension transform: the workgroup holds S
+// adjacent columns, so fewer lanes per column give wider coalesced rows.
+static bool pick_e_outer(int64_t m, int tbytes, int* E) {
+  if (m % 3 == 0) {
+    *E = 12;
+    return m % 12 == 0 && m / 12 <= kMaxThreads;
+  }
+  *E = m < 16 ? 8 : (tbytes == 4 ? 16 : 8);
+  if (m / *E > kMaxThreads) *E = 16;
+  return m % *E == 0 && m / *E <= kMaxThreads;
 }
 
 bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
@@ -147,11 +183,11 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
         if (dp->D != dp->n) return fail("fused variant processes all residues");
       } else {
         if (dp->q != dp->n * dp->p) return fail("inner form needs q = n p");
-        if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 16384");
-        if (dp->p > kMaxColP || !fft_size_ok(dp->p)) return fail("unsupported p for the column passes");
+        if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 8192");
+        if (dp->p > kMaxColP || !col_size_ok(dp->p)) return fail("unsupported p for the column passes");
       }
       if (dp->E_m == 0 && !pick_e_row(dp->m, fused, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
-      if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("row points per lane must be 8, 16, 24 or 32");
+      if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("row points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto need = [&](int r) {
         return ((size_t)r * A * (dp->m + (dp->m >> dp->fd_m.ps)) + tw_words(dp->fd_m)) * cb;
@@ -167,8 +203,8 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
         return fail("rows per block exceed the thread limit");
       if (need(dp->rows_per_block) > kLdsBudget) return fail("row does not fit in LDS");
       if (fused) return true;
-      if (dp->E_p == 0 && !pick_e_col(dp->p, &dp->E_p)) return fail("unsupported p for the column passes");
-      if (!in_set(dp->E_p, {1, 2, 4, 8, 16, 24})) return fail("column points per lane must be 1, 2, 4, 8, 16 or 24");
+      if (dp->E_p == 0 && !pick_e_col(dp->p, tbytes, &dp->E_p)) return fail("unsupported p for the column passes");
+      if (!in_set(dp->E_p, {1, 2, 4, 8, 12, 16})) return fail("column points per lane must be 1, 2, 4, 8, 12 or 16");
       if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p with these points per lane");
       auto cneed = [&](int S) { return ((size_t)2 * dp->p * S + tw_words(dp->fd_p)) * cb; };
       dp->fd_p.twmode = dp->tw_pref == 2;
@@ -187,8 +223,8 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
       if (dp->D != dp->n) return fail("outer variant processes all residues");
       if (dp->m < 8) return fail("outer variant needs m >= 8");
-      if (dp->E_m == 0) dp->E_m = dp->m % 3 == 0 ? 24 : (dp->m < 16 ? 8 : (dp->m <= 1024 ? 16 : 32));
-      if (!in_set(dp->E_m, {8, 16, 24, 32})) return fail("outer points per lane must be 8, 16, 24 or 32");
+      if (dp->E_m == 0 && !pick_e_outer(dp->m, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
+      if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("outer points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto oneed = [&](int S) { return ((size_t)dp->m * S + tw_words(dp->fd_m)) * cb; };
       dp->fd_m.twmode = dp->tw_pref == 2;
@@ -226,19 +262,37 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPla
   if (contiguous) {
     int64_t m = std::max<int64_t>(8, next_fft_size(L));
     if (m <= kMaxFusedM && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, A, tbytes, &w)) return true;
-    // large rows: inner form with m near 8192 (c64) / 4096 (c128)
-    int64_t mm = 4096;
-    while (mm > 16 && mm / 2 >= L) mm /= 2;
-    for (; mm <= kMaxRowM; mm *= 2) {
+    // large rows: inner form with a power-of-two m near 4096 and the least
+    // padding q m (ties keep the earlier m of the list)
+    DimPlan best;
+    bool found = false;
+    int64_t m0 = 4096;
+    while (m0 > 16 && m0 / 2 >= L) m0 /= 2;
+    for (int64_t mm : {m0, m0 / 2, m0 * 2, m0 / 4}) {
+      if (mm < 8 || mm > kMaxRowM) continue;
+      // FP64 column passes with a factor 3 spill registers: powers of two there
       int64_t p = next_col_size(cdiv(L, mm));
+      if (tbytes == 8)
+        for (p = 1; p < cdiv(L, mm);) p <<= 1;
       if (p > kMaxColP) continue;
-      if (set_geom(dp, L, M, mm, p, VAR_MULTI) && finish_dim(dp, A, tbytes, &w)) return true;
+      DimPlan c;
+      if (!set_geom(&c, L, M, mm, p, VAR_MULTI) || !finish_dim(&c, A, tbytes, &w)) continue;
+      if (!found || c.q * c.m < best.q * best.m) {
+        best = c;
+        found = true;
+      }
+    }
+    if (found) {
+      *dp = best;
+      return true;
     }
     if (why) *why = "no supported plan for this length: " + w;
     return false;
   }
+  // outer dimensions: p = 1 up to m = 1024, then p = 2 (half the transform
+  // length, so twice the columns fit a workgroup: wider coalesced rows)
   int64_t m = std::max<int64_t>(8, next_fft_size(L));
-  if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
+  if (m <= 1024 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
   m = std::max<int64_t>(8, next_fft_size(cdiv(L, 2)));
   if (set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
   if (why) *why = "no supported plan for this outer length: " + w;
@@ -262,10 +316,15 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
   };
   for (int64_t m : sizes) {
     if (m > next_fft_size(M) && m > 8) break;
+    // widths of the m-point transform: 12 for sizes with a factor 3, else
+    // 4, 8 and 16 points per lane
+    std::vector<int> Es;
+    if (m % 3 == 0) Es = {12};
+    else Es = {4, 8, 16};
     if (contiguous) {
-      // whole rows in one workgroup (p <= 2), two widths of the m-point transform
+      // whole rows in one workgroup (p <= 2)
       if (cdiv(L, m) <= 2)
-        for (int E : {8, 16}) add(m, 0, VAR_FUSED, E);
+        for (int E : Es) add(m, 0, VAR_FUSED, E);
       // inner form: p rounded up to a supported size, and to a power of two
       if (m >= 16 && m >= L / kMaxColP) {
         const int64_t p0 = cdiv(L, m);
@@ -275,12 +334,12 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
         if (p2 != ps[0]) ps.push_back(p2);
         for (int64_t p : ps) {
           if (p > kMaxColP) continue;
-          for (int E : {8, 16}) add(m, p, VAR_MULTI, E);
+          for (int E : Es) add(m, p, VAR_MULTI, E);
         }
       }
     } else {
       if (cdiv(L, m) <= 2)
-        for (int E : {16, 32}) add(m, 0, VAR_OUTER, E);
+        for (int E : Es) add(m, 0, VAR_OUTER, E);
     }
   }
   // drop exact duplicates (same shape reached twice)

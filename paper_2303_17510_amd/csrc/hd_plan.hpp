@@ -20,7 +20,7 @@ enum Variant {
 // Limits of the kernels (see hd_kernels.hip).
 constexpr int kMaxThreads = 512;
 constexpr int64_t kMaxFusedM = 8192;   // m of the fused and outer kernels
-constexpr int64_t kMaxRowM = 16384;    // m of the row-convolution pass
+constexpr int64_t kMaxRowM = 8192;     // m of the row-convolution pass
 constexpr int64_t kMaxColP = 4096;     // p of the column passes
 constexpr size_t kLdsBudget = 160 * 1024;
 
@@ -49,6 +49,7 @@ Geometry geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inn
 
 bool fft_size_ok(int64_t N);            // 2^a, or 3 * 2^a with a >= 3
 int64_t next_fft_size(int64_t n);       // smallest size >= n accepted by fft_size_ok
+bool col_size_ok(int64_t p);            // 2^a, or 3 * 2^a with a >= 2
 int64_t next_col_size(int64_t n);       // smallest p >= n the column passes accept
 
 // Factor N into stage radices that divide E (largest first; a factor 3 first).

@@ -196,7 +196,8 @@ class BatchPlan:
     hipGraph launch (from the second execute on, unless ``graph=False``).
     """
 
-    def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True):
+    def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True,
+                 tuner: str = "heuristic", model=None, tune_reps: int = 5, margin: float = 0.05):
         Ls = [int(v) for v in Ls]
         Ms = [A * v for v in Ls] if Ms is None else [int(v) for v in Ms]
         if len(Ms) != len(Ls):
@@ -206,6 +207,11 @@ class BatchPlan:
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.flags = 0 if graph else _L.BATCH_NO_GRAPH
+        opt.tuner = {"heuristic": _L.TUNER_HEURISTIC, "exhaustive": _L.TUNER_EXHAUSTIVE,
+                     "model": _L.TUNER_MODEL}[tuner]
+        opt.tune_reps = int(tune_reps)
+        opt.margin = float(margin)
+        opt.model = ctypes.c_void_p(model.handle if model is not None else None)
         n = len(Ls)
         h = _L.lib().hdconv_plan_batched((ctypes.c_int64 * n)(*Ls), (ctypes.c_int64 * n)(*Ms), n, A, B, 1,
                                          self.dtype_code, ctypes.byref(opt))
@@ -221,10 +227,14 @@ class BatchPlan:
         ng = ctypes.c_int(0)
         _L.check(_L.lib().hdconv_batch_info(self._h, arr, cnt, cap, ctypes.byref(ng)))
         return [{"variant": _L.VARIANT_NAMES[arr[g].variant], "m": arr[g].m, "p": arr[g].p, "n": arr[g].n,
-                 "q": arr[g].q, "count": cnt[g], "Lmax": arr[g].L} for g in range(min(ng.value, cap))]
+                 "q": arr[g].q, "E_m": arr[g].E_m, "E_p": arr[g].E_p, "S": arr[g].S,
+                 "rows_per_block": arr[g].rows_per_block, "count": cnt[g], "Lmax": arr[g].L}
+                for g in range(min(ng.value, cap))]
 
-    def execute(self, inputs, outputs, stream=None):
-        """inputs: list (per convolution) of A tensors; outputs: list of tensors."""
+    def bind(self, inputs, outputs) -> "BoundBatch":
+        """Validate the tensors once and keep their device pointers: executes
+        of the returned object pass the pointer tables straight to the
+        library (the tensors must stay alive and in place meanwhile)."""
         torch = _torch()
         n = len(self.Ls)
         if len(inputs) != n or len(outputs) != n:
@@ -241,9 +251,11 @@ class BatchPlan:
             ptrs.extend(t.data_ptr() for t in ins)
         ins_c = (ctypes.c_void_p * len(ptrs))(*ptrs)
         outs_c = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outputs])
-        if stream is None:
-            stream = torch.cuda.current_stream(outputs[0].device)
-        _L.check(_L.lib().hdconv_execute_batched(self._h, ins_c, outs_c, ctypes.c_void_p(stream.cuda_stream)))
+        return BoundBatch(self, ins_c, outs_c, outputs[0].device, (inputs, outputs))
+
+    def execute(self, inputs, outputs, stream=None):
+        """inputs: list (per convolution) of A tensors; outputs: list of tensors."""
+        self.bind(inputs, outputs).execute(stream)
         return outputs
 
     def close(self):
@@ -262,6 +274,19 @@ class BatchPlan:
 
     def __exit__(self, *a):
         self.close()
+
+
+class BoundBatch:
+    """A batched plan with its tensors' pointer tables (see BatchPlan.bind)."""
+
+    def __init__(self, plan, ins_c, outs_c, device, keep):
+        self.plan, self._ins, self._outs, self.device, self._keep = plan, ins_c, outs_c, device, keep
+
+    def execute(self, stream=None):
+        if stream is None:
+            stream = _torch().cuda.current_stream(self.device)
+        _L.check(_L.lib().hdconv_execute_batched(self.plan._h, self._ins, self._outs,
+                                                 ctypes.c_void_p(stream.cuda_stream)))
 
 
 def convolve(*inputs, M=None, **kw):

@@ -101,3 +101,43 @@ def test_batched_pointer_change_between_executes(gpu):
         torch.cuda.synchronize()
     assert check_all(xs1, outs1, "c64") <= 1e-5
     assert check_all(xs2, outs2, "c64") <= 1e-5
+
+
+def _batch_ms(bp, ins, outs, reps=10):
+    import torch
+    bp.execute(ins, outs)
+    bp.execute(ins, outs)   # captured
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bp.execute(ins, outs)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
+def test_batched_tuned_per_bucket(gpu):
+    """Exhaustive per-group tuning: results stay exact, and the tuned batch is
+    not slower than the heuristic one (each group's default is a candidate)."""
+    import torch
+    Ls = [int(v) for v in synth.batched_lengths(count=96, lo_log2=6.0, span_log2=10.0, seed=31337)]
+    xs, ins, outs = batch_case(Ls, "c64", 2100)
+    with BatchPlan(Ls, dtype="c64") as bp:
+        t_heur = _batch_ms(bp, ins, outs)
+        ng_heur = len(bp.groups())
+    for o in outs:
+        o.fill_(float("nan"))
+    with BatchPlan(Ls, dtype="c64", tuner="exhaustive", tune_reps=3) as bp:
+        groups = bp.groups()
+        say("tuned groups", [(g["variant"], g["m"], g["p"], g["rows_per_block"], g["count"]) for g in groups])
+        assert sum(g["count"] for g in groups) == len(Ls)
+        t_tuned = _batch_ms(bp, ins, outs)
+        torch.cuda.synchronize()
+    worst = check_all(xs, outs, "c64")
+    say("groups %d -> %d, heuristic %.3f ms, tuned %.3f ms, worst rel L2 %.3e" % (ng_heur, len(groups), t_heur,
+                                                                                   t_tuned, worst))
+    assert worst <= TOL["c64"]
+    assert t_tuned <= 1.15 * t_heur
