@@ -138,7 +138,8 @@ def leg(wl, dtype, method, steps, warmup, tuner="heuristic"):
     n_out = 1
     for l in wl["L"]:
         n_out *= l
-    r = {"dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s, "ms": ms,
+    r = {"stats": stats, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
+         "candidates": info.get("tuned_candidates"), "timed_candidates": info.get("timed_candidates"), "ms": ms,
          "outputs_per_s": n_out / (ms * 1e-3),
          "ns_per_NlogN": ms * 1e6 / (n_out * math.log2(max(2, n_out))),
          "plan": [(d["variant"], d["m"], d["p"], d["n"], d["q"]) for d in info["dims"]],
@@ -190,6 +191,28 @@ def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=No
             "convolutions": count, "outputs": tot, "ms": ms, "outputs_per_s": tot / (ms * 1e-3),
             "compulsory_frac": 3 * w * tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "groups": [(g["variant"], g["m"], g["p"], g["q"], g["count"]) for g in groups]}
+
+
+def copy_baseline(nbytes, reps=50):
+    """GB/s of a plain device copy moving the same bytes (half read, half
+    written) as one launch of the dominant kernel: the practical ceiling for
+    a kernel of that size, beside the 8 TB/s peak."""
+    import torch
+    n = max(1, int(nbytes // 8))
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    return 8.0 * n / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(wl, xs_by_dtype, outs_by_dtype, budget_s):
@@ -260,6 +283,7 @@ def main():
     khash = kernel_hash()
     log("workload:", wl["workload"])
     main_leg, xs32, out32 = leg(wl, wl["dtype"], "hybrid", args.steps, args.warmup)
+    main_prof = main_leg.pop("stats")
     log("hybrid c64: %.4f ms, %.3e outputs/s, dominant %s" % (main_leg["ms"], main_leg["outputs_per_s"],
                                                                main_leg["dominant"]))
     compare = {}
@@ -280,6 +304,11 @@ def main():
         compare["hybrid_c64_tuned"] = r
         r, _, _ = leg(wl, "c128", "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
         compare["hybrid_c128_tuned"] = r
+        from paper_2303_17510_amd import tune as _tune
+        have_model = os.path.exists(_tune.TRAINED_MODEL)
+        if have_model:
+            r, _, _ = leg(wl, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="model")
+            compare["hybrid_c64_model"] = r
         if args.workload == "c2":
             w15 = workload("c2_1p5m")
             for dt in ("c64", "c128"):
@@ -291,8 +320,14 @@ def main():
                 compare["L1500000_explicit_%s" % dt] = r
             compare["batched_4096_c64"] = batched_leg(max(10, args.steps // 10), 3)
             compare["batched_4096_c64_tuned"] = batched_leg(max(10, args.steps // 10), 3, tuner="exhaustive")
+            if have_model:
+                r, _, _ = leg(w15, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="model")
+                compare["L1500000_hybrid_c64_model"] = r
+                compare["batched_4096_c64_model"] = batched_leg(max(10, args.steps // 10), 3, tuner="model")
             compare["C1_8192_copies_c128"] = batched_leg(max(10, args.steps // 10), 3, dtype="c128",
                                                           Ls=[1024] * 8192, config_id=0)
+        for v in compare.values():
+            v.pop("stats", None)
         for k, v in compare.items():
             dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
@@ -310,6 +345,8 @@ def main():
             agg_bytes = v["GBps"]
     achieved = agg_bytes
     traffic = read_traffic(dom["kernel"], args.workload, khash)
+    dom_bytes = [v["bytes"] / v["launches"] for k, v in dominant(main_prof)[3].items() if k == dom["kernel"]][0]
+    copy_gbps = copy_baseline(dom_bytes)
     n_out = 1
     for l in wl["L"]:
         n_out *= l
@@ -330,7 +367,8 @@ def main():
                    "plan": main_leg["plan"], "kernel_src": khash},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": traffic, "avg_ms": dom["avg_ms"]},
+                     "traffic": traffic, "avg_ms": dom["avg_ms"], "bytes_per_launch": dom_bytes,
+                     "copy_same_bytes_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps if achieved else None},
         "cpu_baseline": cpu,
         "err_rel_l2": errs,
         "compulsory_frac": main_leg["compulsory_frac"],

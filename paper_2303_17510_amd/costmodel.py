@@ -69,7 +69,7 @@ def collect(geoms, reps=3, dtype="c64", log=None, time_budget_s=None, ids=None):
 
 
 def save(data, path):
-    np.savez(path, **data)
+    np.savez_compressed(path, **data)
 
 
 def load(paths):
@@ -111,6 +111,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
+    c.add_argument("--geometry", default="", help="one geometry 'L1,L2,..:A' instead of the seeded list "
+                   "(M = A L per dimension)")
     c.add_argument("--seed", type=int, default=SEED_TRAIN)
     c.add_argument("--total", type=int, default=2000, help="geometries in the seeded list")
     c.add_argument("--start", type=int, default=0)
@@ -126,24 +128,38 @@ def main(argv=None):
     e = sub.add_parser("evaluate")
     e.add_argument("--model", required=True)
     e.add_argument("--data", nargs="+", required=True)
+    e.add_argument("--json", default="", help="also write the summary here")
     a = ap.parse_args(argv)
     log = lambda *s: print(*s, file=sys.stderr, flush=True)  # noqa: E731
     if a.cmd == "collect":
-        geoms = tune.geometries(a.total, a.seed)
-        sel = list(range(a.start, min(a.total, a.start + a.count)))
+        if a.geometry:
+            dims_s, A_s = a.geometry.split(":")
+            L = [int(v) for v in dims_s.split(",")]
+            geoms, sel = [{"L": L, "M": [int(A_s) * v for v in L], "A": int(A_s)}], [0]
+        else:
+            geoms = tune.geometries(a.total, a.seed)
+            sel = list(range(a.start, min(a.total, a.start + a.count)))
         d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None, ids=sel)
         save(d, a.out)
         log("saved %d rows from %d geometries to %s" % (len(d["y"]), len(np.unique(d["gid"])), a.out))
     elif a.cmd == "train":
         d = load(a.data)
+        t0 = time.time()
         m, loss = train(d, epochs=a.epochs, seed=a.seed)
-        m.save(a.out)
-        log("trained on %d rows, final normalised MSE %.4f, saved %s" % (len(d["y"]), loss, a.out))
+        m.save(a.out, meta={"train_rows": int(len(d["y"])), "train_geometries": int(len(np.unique(d["gid"]))),
+                            "epochs": a.epochs, "seed": a.seed, "final_normalised_mse": loss,
+                            "train_seconds": time.time() - t0, "data_seed": SEED_TRAIN})
+        log("trained on %d rows in %.1f s, final normalised MSE %.4f, saved %s" % (len(d["y"]), time.time() - t0,
+                                                                                   loss, a.out))
     else:
         m = tune.CostModel.load_file(a.model)
         r = evaluate(m, load(a.data))
         r.pop("rows")
         print(r)
+        if a.json:
+            import json
+            with open(a.json, "w") as fh:
+                json.dump(r, fh, indent=1)
 
 
 if __name__ == "__main__":

@@ -12,7 +12,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/hdconv.h"
+#include "hdconv.h"
 #include "hd_engine.hpp"
 #include "hd_plan.hpp"
 
@@ -119,6 +119,19 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
                        const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms);
 static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims);
 
+// Independent lines one launch of dimension d processes: the product of the
+// other dimensions' lengths (outer ones padded to about twice their length
+// by the residues), so 1 only for a single 1D convolution.
+static int64_t lines_of_shape(const int64_t* L, int dims, int d) {
+  int64_t n = 1;
+  for (int e = 0; e < dims; ++e)
+    if (e != d) n *= (e < d ? 2 : 1) * L[e];
+  return n;
+}
+static int64_t lines_of(const Plan* P, int d) {
+  return P->batch_rows > 1 ? P->batch_rows : lines_of_shape(P->L, P->dims, d);
+}
+
 static int build_dims(Plan* P, const hdconv_options* opt) {
   const int tb = tbytes_of(P->dtype);
   for (int d = 0; d < P->dims; ++d) {
@@ -157,7 +170,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
         }
         if (!finish_dim(&dp, P->A, tb, &why))
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
-      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, &dp, &why)) {
+      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
     } else {
@@ -472,7 +485,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.D = D;
     k3.S = dp.S;
     k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
-    k3.fd = dp.fd_p;
+    k3.fd = dp.fd_pb;
     k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k3.zq = (const cpx<T>*)P->dd[d].zq;
     {
@@ -480,7 +493,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
                           : (k3.acc_mode == ACC_FIRST ? 16.0 * dp.L
                                                       : (k3.acc_mode == ACC_ADD ? 32.0 * dp.L : 16.0 * dp.L + dp.L * wb));
       ProfScope ps(P, s, "cols_bwd", (double)nrows * ((double)D * dp.p * dp.m * wb + accb));
-      e = launch_cols_bwd<T>(k3, dp.E_p, s);
+      e = launch_cols_bwd<T>(k3, dp.E_pb, s);
     }
     if (e != hipSuccess) return hip_err(e, "cols_bwd launch");
   }
@@ -932,7 +945,7 @@ static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, 
   std::vector<DimPlan> base(dims);
   for (int d = 0; d < dims; ++d) {
     std::string why;
-    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, &base[d], &why))
+    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, lines_of_shape(L, dims, d), &base[d], &why))
       return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
   }
   auto push = [&](const std::vector<DimPlan>& s, int v) {
@@ -1562,7 +1575,7 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
   for (int64_t i = 0; i < count; ++i) {
     DimPlan dp;
     std::string why;
-    if (!choose_dim(L[i], M[i], A, tb, true, &dp, &why)) {
+    if (!choose_dim(L[i], M[i], A, tb, true, count, &dp, &why)) {
       set_err(HDCONV_EUNSUPPORTED, "convolution %lld (L=%lld): %s", (long long)i, (long long)L[i], why.c_str());
       free_batch(Bt);
       return nullptr;

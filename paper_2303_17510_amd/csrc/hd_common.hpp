@@ -87,6 +87,33 @@ struct RootTable {
   __device__ __forceinline__ cpx<T> pow_prod(int64_t a, int64_t b) const {
     return get((int64_t)((uint64_t)(a * b) % (uint64_t)N));
   }
+  // Calls f(e, zeta_N^{ex0 + e st}) for e = 0 .. E-1 (ex0, st < N).  The
+  // powers are composed from three lookups: base = zeta^{ex0}, w = zeta^{st}
+  // and w4 = zeta^{4 st}, with zeta^{e st} = w^{e mod 4} w4^{e div 4}
+  // (E <= 16), so each value is a product of at most five rounded factors
+  // instead of two table loads per point.
+  template <int E, typename F>
+  __device__ __forceinline__ void run(uint32_t ex0, uint32_t st, F&& f) const {
+    static_assert(E <= 16, "at most 16 powers per run");
+    const cpx<T> base = get(ex0);
+    cpx<T> p0[4], p1[4];
+    p0[0] = p1[0] = mk(T(1), T(0));
+    p0[1] = get(st);
+    p0[2] = cmul(p0[1], p0[1]);
+    p0[3] = cmul(p0[2], p0[1]);
+    if constexpr (E > 4) {
+      p1[1] = get((uint32_t)((4ull * st) % (uint64_t)N));
+      p1[2] = cmul(p1[1], p1[1]);
+      p1[3] = cmul(p1[2], p1[1]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      cpx<T> z = base;
+      if (e & 3) z = cmul(z, p0[e & 3]);
+      if (e >> 2) z = cmul(z, p1[e >> 2]);
+      f(e, z);
+    }
+  }
 };
 
 }  // namespace hd

@@ -71,10 +71,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      uint32_t ex = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const cpx<T> z = a.zqm.get(ex);
+      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
+      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) {
 #pragma unroll
         for (int ai = 0; ai < A; ++ai) {
           cpx<T> xv;
@@ -82,9 +80,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
           else xv = load(ai, t, e);
           w[ai][e] = w[ai][e] + cmul(xv, z);
         }
-        ex += st;
-        if (ex >= qm) ex -= qm;
-      }
+      });
     }
     gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
     cpx<T> prod[1][E];
@@ -98,13 +94,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      uint32_t ex = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        acc[t][e] = acc[t][e] + cmulc(prod[0][e], a.zqm.get(ex));
-        ex += st;
-        if (ex >= qm) ex -= qm;
-      }
+      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
+      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
     }
   }
   if (valid) {

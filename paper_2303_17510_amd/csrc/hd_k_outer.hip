@@ -38,14 +38,9 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
     for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      int64_t ex = (r * (t * m + g)) % qm;
-      const int64_t st = (r * G) % qm;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        w[0][e] = w[0][e] + cmul(x[t][e], a.zqm.get(ex));
-        ex += st;
-        if (ex >= qm) ex -= qm;
-      }
+      const uint32_t ex0 = (uint32_t)((r * (t * m + g)) % qm);
+      const uint32_t st = (uint32_t)((r * G) % qm);
+      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
     }
     gfft_any<T, E, +1, 1, kCtOuter>(w, g, a.fd, tw, xb);
     if (valid) {
@@ -86,14 +81,9 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
     gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      int64_t ex = (r * (t * m + g)) % qm;
-      const int64_t st = (r * G) % qm;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        acc[t][e] = acc[t][e] + cmulc(y[0][e], a.zqm.get(ex));
-        ex += st;
-        if (ex >= qm) ex -= qm;
-      }
+      const uint32_t ex0 = (uint32_t)((r * (t * m + g)) % qm);
+      const uint32_t st = (uint32_t)((r * G) % qm);
+      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
     }
   }
   if (!valid) return;

@@ -20,7 +20,7 @@
 #include <random>
 #include <vector>
 
-#include "../../include/hdconv.h"
+#include "hdconv.h"
 
 namespace hd {
 

@@ -1,6 +1,8 @@
 // hd_plan.cpp -- geometry rules and kernel-shape choices (host only).
 #include "hd_plan.hpp"
 
+#include <cmath>
+
 #include <math.h>
 
 #include <algorithm>
@@ -137,7 +139,9 @@ static bool pick_e_col(int64_t p, int tbytes, int* E) {
     *E = (int)p;
     return p == 1 || p == 2 || p == 4 || p == 8;
   }
-  const int e0 = tbytes == 4 ? 8 : 4;
+  // FP32: 16 points per lane from p = 256 (measured faster for the forward
+  // pass, which transforms one residue at a time), else 8; FP64: 4.
+  const int e0 = tbytes == 4 ? (p >= 256 ? 16 : 8) : 4;
   *E = p / e0 <= kMaxThreads ? e0 : (p / 8 <= kMaxThreads ? 8 : 16);
   return p / *E <= kMaxThreads;
 }
@@ -206,15 +210,22 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->E_p == 0 && !pick_e_col(dp->p, tbytes, &dp->E_p)) return fail("unsupported p for the column passes");
       if (!in_set(dp->E_p, {1, 2, 4, 8, 12, 16})) return fail("column points per lane must be 1, 2, 4, 8, 12 or 16");
       if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p with these points per lane");
+      // The backward column pass transforms two residues at once and keeps an
+      // accumulator, so in FP32 it runs with at most 8 points per lane
+      // (measured: 16 there costs registers and time); the forward pass uses
+      // the requested width.
+      dp->E_pb = (tbytes == 4 && dp->E_p > 8 && dp->E_p % 8 == 0) ? 8 : dp->E_p;
+      if (!make_fft_desc(dp->p, dp->E_pb, &dp->fd_pb)) return fail("no stage plan for the backward column pass");
       auto cneed = [&](int S) { return ((size_t)2 * dp->p * S + tw_words(dp->fd_p)) * cb; };
       dp->fd_p.twmode = dp->tw_pref == 2;
       if (dp->tw_pref == 0 && cneed(std::min(16, (int)dp->m)) > 81920) dp->fd_p.twmode = 0;
       if (dp->S == 0) {
         int S = 64;
-        while (S > 1 && (dp->m % S != 0 || S * dp->fd_p.G > kMaxThreads || cneed(S) > 81920)) S /= 2;
+        while (S > 1 && (dp->m % S != 0 || S * std::max(dp->fd_p.G, dp->fd_pb.G) > kMaxThreads || cneed(S) > 81920))
+          S /= 2;
         dp->S = S;
       }
-      if (dp->m % dp->S != 0 || dp->S * dp->fd_p.G > kMaxThreads || cneed(dp->S) > kLdsBudget)
+      if (dp->m % dp->S != 0 || dp->S * std::max(dp->fd_p.G, dp->fd_pb.G) > kMaxThreads || cneed(dp->S) > kLdsBudget)
         return fail("column tile does not fit");
       return true;
     }
@@ -257,29 +268,53 @@ static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min
   return true;
 }
 
-bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPlan* dp, std::string* why) {
+static int64_t pow2_ceil(int64_t x) {
+  int64_t r = 1;
+  while (r < x) r <<= 1;
+  return r;
+}
+
+bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
+                std::string* why) {
   std::string w;
   if (contiguous) {
-    int64_t m = std::max<int64_t>(8, next_fft_size(L));
-    if (m <= kMaxFusedM && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, A, tbytes, &w)) return true;
-    // large rows: inner form with a power-of-two m near 4096 and the least
-    // padding q m (ties keep the earlier m of the list)
+    // Whole rows in one workgroup.  A single convolution is latency-bound:
+    // one transform of m >= M (q = 1, no residue loop in the lone workgroup)
+    // up to 4096 points.  Many rows are throughput-bound: m >= L with the
+    // residues looped (q = 2 for M = 2L), half the transform work.  Powers
+    // of two only: sizes with a factor 3 measured slower at equal padding.
+    const int64_t m = std::max<int64_t>(8, pow2_ceil(lines <= 1 ? M : L));
+    if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, A, tbytes, &w)) return true;
+    // Inner form: the least padding q m over m = 1024 .. 8192 and p a power
+    // of two, or 3 * 2^k from 96 up (small column transforms with a factor 3
+    // measured slow; FP64 ones spill, so powers of two there).  Among equal
+    // padding the m nearest the measured best for that size: 2048 up to
+    // q m = 2^20, 4096 for 2^21, 8192 beyond.  Rows of 4096 points or more
+    // take 16 points per lane when there are enough of them (n p lines >=
+    // 512) to fill the chip, else 8.
     DimPlan best;
     bool found = false;
-    int64_t m0 = 4096;
-    while (m0 > 16 && m0 / 2 >= L) m0 /= 2;
-    for (int64_t mm : {m0, m0 / 2, m0 * 2, m0 / 4}) {
-      if (mm < 8 || mm > kMaxRowM) continue;
-      // FP64 column passes with a factor 3 spill registers: powers of two there
-      int64_t p = next_col_size(cdiv(L, mm));
-      if (tbytes == 8)
-        for (p = 1; p < cdiv(L, mm);) p <<= 1;
-      if (p > kMaxColP) continue;
-      DimPlan c;
-      if (!set_geom(&c, L, M, mm, p, VAR_MULTI) || !finish_dim(&c, A, tbytes, &w)) continue;
-      if (!found || c.q * c.m < best.q * best.m) {
-        best = c;
-        found = true;
+    double best_key = 0;
+    for (int64_t mm : {1024, 2048, 4096, 8192}) {
+      if (mm > kMaxRowM) continue;
+      const int64_t pmin = cdiv(L, mm);
+      std::vector<int64_t> ps = {pow2_ceil(pmin)};
+      const int64_t p3 = next_col_size(pmin);
+      if (tbytes == 4 && p3 % 3 == 0 && p3 >= 96) ps.push_back(p3);
+      for (int64_t p : ps) {
+        if (p > kMaxColP) continue;
+        DimPlan c;
+        if (!set_geom(&c, L, M, mm, p, VAR_MULTI)) continue;
+        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 512)) ? 16 : 8;
+        if (!finish_dim(&c, A, tbytes, &w)) continue;
+        const double qm = (double)(c.q * c.m);
+        const double mt = qm <= (double)(1 << 20) ? 2048.0 : (qm <= (double)(1 << 21) ? 4096.0 : 8192.0);
+        const double key = qm * 1e3 + std::fabs(std::log2((double)mm / mt));
+        if (!found || key < best_key) {
+          best = c;
+          best_key = key;
+          found = true;
+        }
       }
     }
     if (found) {
@@ -314,8 +349,9 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
     dp.E_m = E_m;
     if (finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
   };
+  const int64_t mlim = std::max<int64_t>(8, pow2_ceil(M));  // up to one transform of m >= M
   for (int64_t m : sizes) {
-    if (m > next_fft_size(M) && m > 8) break;
+    if (m > mlim) break;
     // widths of the m-point transform: 12 for sizes with a factor 3, else
     // 4, 8 and 16 points per lane
     std::vector<int> Es;

@@ -30,8 +30,10 @@ struct DimPlan {
   int variant = VAR_AUTO;
   FftDesc fd_m{};             // m-point transform
   int E_m = 0;
-  FftDesc fd_p{};             // p-point transform (inner form)
+  FftDesc fd_p{};             // p-point transform of the forward column pass (inner form)
   int E_p = 0;
+  FftDesc fd_pb{};            // the same transform as the backward column pass runs it
+  int E_pb = 0;               // (FP32: at most 8 points per lane there, see finish_dim)
   int S = 0;                  // columns per workgroup (column / outer kernels)
   int rows_per_block = 0;     // rows per workgroup (fused / row kernels)
   int tw_pref = 0;            // twiddles: 0 choose, 1 two-level table, 2 per-stage tables
@@ -62,8 +64,10 @@ bool make_fft_desc(int64_t N, int E, FftDesc* d);
 bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why);
 
 // Default (heuristic) choice for one dimension.  `contiguous` marks the
-// innermost dimension (rows), others are outer dimensions.
-bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, DimPlan* dp,
+// innermost dimension (rows), others are outer dimensions; `lines` is the
+// number of independent lines one launch of this dimension processes (1 for
+// a single 1D convolution: latency first; many: throughput first).
+bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
                 std::string* why);
 
 // Candidates for the autotuner: every supported (m, variant) of a dimension.

@@ -85,6 +85,10 @@ class Plan:
                      "model": _L.TUNER_MODEL}[tuner]
         opt.tune_reps = int(tune_reps)
         opt.margin = float(margin)
+        if tuner == "model" and model is None:
+            from .tune import load_default_model
+            model = load_default_model()
+        self._model = model
         opt.model = ctypes.c_void_p(model.handle if model is not None else None)
         self._db = db_path.encode() if db_path else None
         opt.db_path = self._db
@@ -211,6 +215,10 @@ class BatchPlan:
                      "model": _L.TUNER_MODEL}[tuner]
         opt.tune_reps = int(tune_reps)
         opt.margin = float(margin)
+        if tuner == "model" and model is None:
+            from .tune import load_default_model
+            model = load_default_model()
+        self._model = model
         opt.model = ctypes.c_void_p(model.handle if model is not None else None)
         n = len(Ls)
         h = _L.lib().hdconv_plan_batched((ctypes.c_int64 * n)(*Ls), (ctypes.c_int64 * n)(*Ms), n, A, B, 1,

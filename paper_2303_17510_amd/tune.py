@@ -127,13 +127,15 @@ class CostModel:
         _L.check(_L.lib().hdconv_model_grad(self.handle, xp, yp, len(y), gp, ctypes.byref(loss)))
         return g, float(loss.value)
 
-    def save(self, path: str):
+    def save(self, path: str, meta=None):
         """Parameters as little-endian float32 (path) plus a JSON header (path + '.json')."""
         p = self.params()
         p.astype("<f4").tofile(path)
+        hdr = {"hidden": self.hidden, "nfeatures": NF, "nparams": int(p.size),
+               "layout": "W1,b1,W2,b2,W3,b3,W4,b4,xmean,xstd,ymean,ystd"}
+        hdr.update(meta or {})
         with open(path + ".json", "w") as fh:
-            json.dump({"hidden": self.hidden, "nfeatures": NF, "nparams": int(p.size),
-                       "layout": "W1,b1,W2,b2,W3,b3,W4,b4,xmean,xstd,ymean,ystd"}, fh)
+            json.dump(hdr, fh, indent=1)
 
     @classmethod
     def load_file(cls, path: str) -> "CostModel":
@@ -153,6 +155,17 @@ class CostModel:
             self.close()
         except Exception:
             pass
+
+
+TRAINED_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "trained", "picker_mlp.f32")
+
+
+def load_default_model() -> "CostModel":
+    """The picker trained on this library's own autotuner timings (shipped
+    with the package as trained/picker_mlp.f32)."""
+    if not os.path.exists(TRAINED_MODEL):
+        raise FileNotFoundError("no trained cost model at " + TRAINED_MODEL)
+    return CostModel.load_file(TRAINED_MODEL)
 
 
 def geometries(count: int, seed: int, A_choices=(2, 3), mix=(0.60, 0.25, 0.15), l1=(256, 1 << 22),
