@@ -45,9 +45,10 @@ enum {
 };
 
 /* method: hybrid dealiasing (Sec. 2.1) or conventional explicit padding
- * (inputs materialised zero-padded to a {2,3}-smooth size >= M, full FFTs,
+ * (inputs materialised zero-padded to N' = 2^a or 3*2^a >= M, full FFTs,
  * product, inverse FFT, first L copied out: the baseline the paper compares
- * against, Sec. 7). */
+ * against, Sec. 7).  For the explicit method options.m of the innermost
+ * dimension, when set, picks the split N' = p m of its transform. */
 enum { HDCONV_METHOD_AUTO = 0, HDCONV_METHOD_HYBRID = 1, HDCONV_METHOD_EXPLICIT = 2 };
 
 /* per-dimension kernel variant */

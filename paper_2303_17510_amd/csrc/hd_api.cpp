@@ -143,13 +143,27 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
     const int64_t fm = opt ? opt->m[d] : 0;
     const int64_t fp = opt ? opt->p[d] : 0;
     int fv = opt ? opt->variant[d] : 0;
-    if (fm == 0 && fp == 0 && fv == 0) {
+    if (P->method == HDCONV_METHOD_EXPLICIT || (fm == 0 && fp == 0 && fv == 0)) {
       if (P->method == HDCONV_METHOD_EXPLICIT) {
-        // one full-length transform per dimension: p = q = 1 (or inner form with n = 1)
+        // one full-length transform per dimension: p = q = 1 (or inner form
+        // with n = 1); options.m, when set, picks the split N' = p m
         dp = DimPlan{};
         dp.L = Le;
         dp.M = Me;
-        if (!contiguous || Le <= kMaxFusedM) {
+        if (fm > 0 && contiguous) {
+          if (Le % fm != 0 || !fft_size_ok(fm) || (Le / fm > 1 && !col_size_ok(Le / fm)))
+            return set_err(HDCONV_EINVAL, "explicit padding, dim %d: m=%lld does not split N'=%lld", d,
+                           (long long)fm, (long long)Le);
+          dp.m = fm;
+          dp.p = Le / fm;
+          dp.n = dp.D = 1;
+          dp.q = dp.p;
+          dp.variant = dp.p == 1 ? VAR_FUSED : VAR_MULTI;
+          if (opt) {
+            dp.E_m = opt->E_m[d];
+            dp.E_p = opt->E_p[d];
+          }
+        } else if (!contiguous || Le <= kMaxFusedM) {
           dp.m = Le;
           dp.p = dp.q = dp.n = dp.D = 1;
           dp.variant = contiguous ? VAR_FUSED : VAR_OUTER;

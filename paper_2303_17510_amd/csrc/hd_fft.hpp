@@ -198,9 +198,10 @@ __device__ __forceinline__ void butterfly_twiddles(const TwLds<T>& tw, int e1, c
 // j + i*N/R (registers b + i*E/R), multiplies point i by w_{Ns R}^{S k i}
 // (k = j mod Ns), runs the radix-R DFT and stores output c at
 // (j - k) R + k + c Ns.  The last pass keeps its outputs in registers: they
-// are already in the strided layout of the natural-order result.
+// are already in the strided layout of the natural-order result.  tws =
+// N / (Ns R): w_{Ns R} = zeta_N^{tws}.
 template <typename T, int E, int R, int S, int NT>
-__device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int N, int Ns, int twoff,
+__device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int tws, int Ns, int twoff,
                                           const TwLds<T>& tw, const Xchg<T>& xb, bool last) {
   constexpr int NB = E / R;
   const bool pow2 = (Ns & (Ns - 1)) == 0;
@@ -215,7 +216,7 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[NT][E], int g, int G, int 
 #pragma unroll
         for (int i = 1; i < R; ++i) w[i] = t[i];
       } else {
-        butterfly_twiddles<T, R>(tw, k * (N / (Ns * R)), w);
+        butterfly_twiddles<T, R>(tw, k * tws, w);
       }
     }
 #pragma unroll
@@ -276,19 +277,19 @@ __device__ __forceinline__ void gfft(cpx<T> (&v)[NT][E], int g, const FftDesc& d
     const bool last = (R == rem);
     switch (R) {
       case 2:
-        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        if constexpr (E % 2 == 0) fft_stage<T, E, 2, S, NT>(v, g, G, rem / 2, Ns, to, tw, xb, last);
         break;
       case 3:
-        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        if constexpr (E % 3 == 0) fft_stage<T, E, 3, S, NT>(v, g, G, rem / 3, Ns, to, tw, xb, last);
         break;
       case 4:
-        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        if constexpr (E % 4 == 0) fft_stage<T, E, 4, S, NT>(v, g, G, rem / 4, Ns, to, tw, xb, last);
         break;
       case 8:
-        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        if constexpr (E % 8 == 0) fft_stage<T, E, 8, S, NT>(v, g, G, rem / 8, Ns, to, tw, xb, last);
         break;
       case 16:
-        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, G, N, Ns, to, tw, xb, last);
+        if constexpr (E % 16 == 0) fft_stage<T, E, 16, S, NT>(v, g, G, rem / 16, Ns, to, tw, xb, last);
         break;
       default:
         return;  // no such plan (the host never builds one)
@@ -307,7 +308,7 @@ __device__ __forceinline__ void gfft_ct(cpx<T> (&v)[NT][E], int g, const FftDesc
   if constexpr (Ns < N) {
     constexpr int R = ct_radix(N / Ns, E);
     static_assert(R > 1 && (N / Ns) % R == 0 && E % R == 0, "no stage plan");
-    fft_stage<T, E, R, S, NT>(v, g, N / E, N, Ns, d.twoff[ST], tw, xb, Ns * R == N);
+    fft_stage<T, E, R, S, NT>(v, g, N / E, N / (Ns * R), Ns, d.twoff[ST], tw, xb, Ns * R == N);
     gfft_ct<T, N, E, S, NT, Ns * R, ST + 1>(v, g, d, tw, xb);
   }
 }
@@ -316,7 +317,7 @@ __device__ __forceinline__ void gfft_ct(cpx<T> (&v)[NT][E], int g, const FftDesc
 template <int E, int N>
 __host__ __device__ constexpr bool ct_size() {
   if (E == 8) return N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096;
-  if (E == 16) return N == 1024 || N == 2048 || N == 4096 || N == 8192;
+  if (E == 16) return N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096 || N == 8192;
   return false;
 }
 
@@ -324,7 +325,7 @@ __host__ __device__ constexpr bool ct_size() {
 // general path.
 constexpr unsigned kCtFused = 0;
 constexpr unsigned kCtRows = (1u << 11) | (1u << 12) | (1u << 13);
-constexpr unsigned kCtCols = 0;
+constexpr unsigned kCtCols = (1u << 7) | (1u << 8) | (1u << 9) | (1u << 10);
 constexpr unsigned kCtOuter = 0;
 
 // Transform with the specialised plan when one exists for (N, E) and the

@@ -19,7 +19,7 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
 #pragma unroll
     for (int e = 0; e < E; ++e) y[n][e] = cmul(x[e], a.zq[(v * (g + G * e)) % q]);
   }
-  gfft_any<T, E, +1, NT, kCtCols>(y, g, a.fd, tw, xb);
+  gfft_any<T, E, +1, NT, (sizeof(T) == 4 ? kCtCols : 0u)>(y, g, a.fd, tw, xb);
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     cpx<T>* dst = a.work[ai] + ((row * a.D + dv0 + n) * p) * (int64_t)m + s;
@@ -124,7 +124,7 @@ __device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T>
 #pragma unroll
     for (int e = 0; e < E; ++e) y[n][e] = src[(int64_t)(g + G * e) * m];
   }
-  gfft_any<T, E, -1, NT, kCtCols>(y, g, a.fd, tw, xb);
+  gfft_any<T, E, -1, NT, (sizeof(T) == 4 ? kCtCols : 0u)>(y, g, a.fd, tw, xb);
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int v = a.v0 + dv0 + n;

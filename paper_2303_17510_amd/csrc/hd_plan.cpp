@@ -147,14 +147,18 @@ static bool pick_e_col(int64_t p, int tbytes, int* E) {
 }
 
 // Points per lane of an outer-dimension transform: the workgroup holds S
-// adjacent columns, so fewer lanes per column give wider coalesced rows.
-static bool pick_e_outer(int64_t m, int tbytes, int* E) {
+// adjacent columns, so fewer lanes per column give wider coalesced rows, but
+// short transforms run best with few points per lane (measured: 4 up to 256
+// points, 8 up to 1024, 16 beyond in FP32 and for the p = 2 form).
+static bool pick_e_outer(int64_t m, int64_t p, int tbytes, int* E) {
   if (m % 3 == 0) {
     *E = 12;
     return m % 12 == 0 && m / 12 <= kMaxThreads;
   }
-  *E = m < 16 ? 8 : (tbytes == 4 ? 16 : 8);
-  if (m / *E > kMaxThreads) *E = 16;
+  if (tbytes == 4) *E = (p >= 2 || m > 1024) ? 16 : (m <= 256 ? 4 : 8);
+  else *E = m <= 256 ? 4 : 8;
+  if (m < *E) *E = (int)m;
+  while (m / *E > kMaxThreads && *E < 16) *E *= 2;
   return m % *E == 0 && m / *E <= kMaxThreads;
 }
 
@@ -234,7 +238,7 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
       if (dp->D != dp->n) return fail("outer variant processes all residues");
       if (dp->m < 8) return fail("outer variant needs m >= 8");
-      if (dp->E_m == 0 && !pick_e_outer(dp->m, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
+      if (dp->E_m == 0 && !pick_e_outer(dp->m, dp->p, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
       if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("outer points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto oneed = [&](int S) { return ((size_t)dp->m * S + tw_words(dp->fd_m)) * cb; };
@@ -324,12 +328,27 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     if (why) *why = "no supported plan for this length: " + w;
     return false;
   }
-  // outer dimensions: p = 1 up to m = 1024, then p = 2 (half the transform
-  // length, so twice the columns fit a workgroup: wider coalesced rows)
-  int64_t m = std::max<int64_t>(8, next_fft_size(L));
-  if (m <= 1024 && set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
-  m = std::max<int64_t>(8, next_fft_size(cdiv(L, 2)));
-  if (set_geom(dp, L, M, m, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
+  // Outer dimensions (every residue multiplies the inner work, measured on
+  // the autotuner's 2D/3D timings): powers of two only; up to 1024 points one
+  // transform of m >= M (q = 1); beyond, the direct form with p = 1 or p = 2
+  // (half the length: twice the columns per workgroup) and the least padding,
+  // ties to p = 2 once the p = 1 transform would exceed 1024 points.
+  {
+    const int64_t m1 = std::max<int64_t>(8, pow2_ceil(M));
+    if (m1 <= 1024 && set_geom(dp, L, M, m1, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
+    DimPlan a, b;
+    const int64_t ma = std::max<int64_t>(8, pow2_ceil(L)), mb = std::max<int64_t>(8, pow2_ceil(cdiv(L, 2)));
+    const bool oka = ma <= kMaxFusedM && set_geom(&a, L, M, ma, 0, VAR_OUTER) && finish_dim(&a, A, tbytes, &w);
+    const bool okb = set_geom(&b, L, M, mb, 0, VAR_OUTER) && finish_dim(&b, A, tbytes, &w);
+    if (oka && (!okb || a.q * a.m < b.q * b.m || (a.q * a.m == b.q * b.m && ma <= 1024))) {
+      *dp = a;
+      return true;
+    }
+    if (okb) {
+      *dp = b;
+      return true;
+    }
+  }
   if (why) *why = "no supported plan for this outer length: " + w;
   return false;
 }

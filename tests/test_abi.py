@@ -106,6 +106,15 @@ def test_explicit_plan_pads_to_smooth_size():
     assert p.info()["npad"] == [3 * (1 << 20)]
 
 
+def test_explicit_plan_takes_a_forced_split():
+    for m in (2048, 4096, 8192):
+        with Plan((1 << 20,), (1 << 21,), dtype="c64", method="explicit", m=m, host_only=True) as p:
+            d = p.info()["dims"][0]
+            assert (d["m"], d["p"], d["n"], d["q"]) == (m, (1 << 21) // m, 1, (1 << 21) // m)
+    with pytest.raises(_lib.HdconvError):
+        Plan((1 << 20,), (1 << 21,), dtype="c64", method="explicit", m=3072, host_only=True)
+
+
 @pytest.mark.parametrize("bad", [
     dict(L=(10,), M=(18,)),            # M < 2L - 1
     dict(L=(10,), M=(27,), A=3),       # M < 3L - 2

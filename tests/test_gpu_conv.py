@@ -127,6 +127,13 @@ def test_explicit_ragged(gpu, dtype):
         check((L,), (2 * L - 1,), dtype, method="explicit")
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_explicit_forced_split(gpu, dtype):
+    # N' = 24576 = 3 * 2^13 split as p m with the inner form (n = 1)
+    for m in (256, 1024, 2048):
+        check((10000,), (19999,), dtype, method="explicit", m=m)
+
+
 # --- multidimensional ---------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("shape", [(1, 1), (4, 4), (16, 16), (33, 47), (64, 128), (100, 7), (5, 300)])

@@ -1,0 +1,80 @@
+"""The trained picker on the GPU.
+
+The package ships an MLP trained on this library's own autotuner timings
+(trained/picker_mlp.f32).  Checks: its HIP inference agrees with the FP64
+reference network; on held-out geometries (the held-out seed of the
+cost-model workload) the plan it picks is close to the exhaustive search's
+and at least as fast as the untuned default plan, while the model tuner times
+only a few candidates where the exhaustive one times them all.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+from paper_2303_17510_amd import Plan, costmodel, tune
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def small_heldout(count, max_points=1 << 21):
+    out = []
+    for g in tune.geometries(500, costmodel.SEED_HELDOUT):
+        if int(np.prod(g["L"])) <= max_points:
+            out.append(g)
+        if len(out) == count:
+            break
+    return out
+
+
+def test_trained_model_inference_matches_reference(gpu):
+    m = tune.load_default_model()
+    p = m.params().astype(np.float64)
+    X = []
+    for g in small_heldout(4):
+        for _, shp in tune.candidates(g["L"], g["M"], A=g["A"]):
+            X.append(tune.features(g["L"], g["M"], shp, A=g["A"]))
+    X = np.array(X, dtype=np.float32)
+    got = m.predict(X).astype(np.float64)
+    ref = mlp_ref.predict_log_ms(p, X.astype(np.float64), tune.NF, m.hidden)
+    say("max |pred - ref| = %.2e over %d rows" % (np.abs(got - ref).max(), len(X)))
+    assert np.abs(got - ref).max() < 1e-3
+
+
+def test_trained_picker_gain_over_default(gpu):
+    m = tune.load_default_model()
+    regrets, gains = [], []
+    for g in small_heldout(12):
+        cands = tune.candidates(g["L"], g["M"], A=g["A"])
+        X = np.array([tune.features(g["L"], g["M"], s, A=g["A"]) for _, s in cands], dtype=np.float32)
+        pred = m.predict(X)
+        t = np.array([tune.time_shape(g["L"], g["M"], s, A=g["A"], reps=7) for _, s in cands])
+        t_best, t_pick = t.min(), t[int(np.argmin(pred))]
+        t_def = t[[k for k, (v, _) in enumerate(cands) if v == -1][0]]
+        regrets.append(t_pick / t_best - 1.0)
+        gains.append(t_def / t_pick)
+        say("L=%s A=%d: best %.4f  model %.4f  default %.4f ms" % (g["L"], g["A"], t_best, t_pick, t_def))
+    reg = math.exp(np.mean(np.log1p(regrets))) - 1.0
+    gain = math.exp(np.mean(np.log(gains)))
+    say("geomean regret %.3f, gain over default %.3f" % (reg, gain))
+    # the shipped model's 5 % claim is over the 500 held-out geometries; a
+    # dozen live timings carry more noise
+    assert reg <= 0.10
+    assert gain >= 0.97
+
+
+def test_model_tuner_times_few_candidates(gpu):
+    L, M = (300000,), (600000,)
+    with Plan(L, M, tuner="exhaustive", tune_reps=3, host_only=False) as pe:
+        ie = pe.info()
+    with Plan(L, M, tuner="model", tune_reps=3) as pm:
+        im = pm.info()
+    say("exhaustive timed %d of %d, model timed %d of %d" % (ie["timed_candidates"], ie["tuned_candidates"],
+                                                               im["timed_candidates"], im["tuned_candidates"]))
+    assert im["timed_candidates"] <= 3 < ie["timed_candidates"]

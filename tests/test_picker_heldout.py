@@ -1,0 +1,60 @@
+"""Regret of the shipped picker on the stored held-out timings (CPU).
+
+trained/heldout.npz holds the autotuner's timings of every candidate plan of
+500 held-out geometries (seed 17510501 of the cost-model workload), written
+by ``python -m paper_2303_17510_amd.costmodel collect``; trained/picker_mlp.f32
+is the network trained on 2000 other geometries.  The FP64 reference network
+(oracle/mlp_ref.py) predicts each candidate's log time; the pick is the
+argmin, its regret t(pick)/t(best) - 1.  The target is a geometric-mean
+regret within 5 %.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+from oracle import mlp_ref
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAINED = os.path.join(HERE, "..", "paper_2303_17510_amd", "trained")
+
+
+def _model():
+    with open(os.path.join(TRAINED, "picker_mlp.f32.json")) as fh:
+        hdr = json.load(fh)
+    p = np.fromfile(os.path.join(TRAINED, "picker_mlp.f32"), dtype="<f4").astype(np.float64)
+    assert p.size == hdr["nparams"]
+    return p, hdr
+
+
+def _regrets(name):
+    p, hdr = _model()
+    d = np.load(os.path.join(TRAINED, name), allow_pickle=False)
+    pred = mlp_ref.predict_log_ms(p, d["X"].astype(np.float64), hdr["nfeatures"], hdr["hidden"])
+    regrets, gains = [], []
+    for g in np.unique(d["gid"]):
+        idx = np.nonzero(d["gid"] == g)[0]
+        t = np.exp(d["y"][idx].astype(np.float64))
+        pick = t[np.argmin(pred[idx])]
+        regrets.append(pick / t.min() - 1.0)
+        dflt = idx[d["varied"][idx] == -1]
+        if len(dflt):
+            gains.append(math.exp(float(d["y"][dflt[0]])) / pick)
+    return regrets, gains
+
+
+def test_shipped_picker_regret_within_five_percent():
+    regrets, gains = _regrets("heldout.npz")
+    reg = math.exp(np.mean(np.log1p(regrets))) - 1.0
+    print("geometries %d, geomean regret %.4f, median %.4f, gain over default %.3f"
+          % (len(regrets), reg, float(np.median(regrets)), math.exp(np.mean(np.log(gains)))))
+    assert len(regrets) >= 450
+    assert reg <= 0.05
+
+
+def test_shipped_picker_on_the_256_cube():
+    # every candidate plan of the 3D 256^3 convolution (A = 2, M = 512^3), timed
+    regrets, gains = _regrets("cube256.npz")
+    print("256^3: regret %.4f, gain over default %.3f" % (regrets[0], gains[0]))
+    assert regrets[0] <= 0.05
