@@ -28,13 +28,16 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
   }
 }
 
+// Grid x enumerates (row, column tile) pairs, column tiles fastest, so the
+// row count is not bound by the grid's y limit.
 template <typename T, int E>
 __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
   const int S = a.S, G = a.fd.G, m = a.m;
   const int c = threadIdx.x % S;
   const int g = threadIdx.x / S;
-  const int s = blockIdx.x * S + c;
-  const int64_t row = blockIdx.y;
+  const uint32_t tiles = (uint32_t)(m / S);
+  const int s = (int)(blockIdx.x % tiles) * S + c;
+  const int64_t row = blockIdx.x / tiles;
   const int ai = blockIdx.z;
   const cpx<T>* src = a.tasks ? a.tasks[row].in[ai] : a.in[ai] + row * a.in_stride;
   const int64_t L = a.tasks ? a.tasks[row].L : a.L;
@@ -138,8 +141,9 @@ __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
   const int S = a.S, G = a.fd.G, m = a.m;
   const int c = threadIdx.x % S;
   const int g = threadIdx.x / S;
-  const int s = blockIdx.x * S + c;
-  const int64_t row = blockIdx.y;
+  const uint32_t tiles = (uint32_t)(m / S);
+  const int s = (int)(blockIdx.x % tiles) * S + c;
+  const int64_t row = blockIdx.x / tiles;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, a.p * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
@@ -164,8 +168,10 @@ __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
 template <typename T>
 hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s) {
   const int nt = a.S * a.fd.G;
-  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 || a.nrows > 65535) return HD_BAD;
-  dim3 grid(a.m / a.S, (unsigned)a.nrows, A), block(nt);
+  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 ||
+      (int64_t)(a.m / a.S) * a.nrows > 0x7fffffff)
+    return HD_BAD;
+  dim3 grid((unsigned)((a.m / a.S) * a.nrows), 1, A), block(nt);
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
 #define C1(EE) \
   if (E == EE) return go(k_cols_fwd<T, EE>, grid, block, lds, s, a);
@@ -190,8 +196,10 @@ hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s
 template <typename T>
 hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s) {
   const int nt = a.S * a.fd.G;
-  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 || a.nrows > 65535) return HD_BAD;
-  dim3 grid(a.m / a.S, (unsigned)a.nrows), block(nt);
+  if (nt > 512 || !fft_fits(a.fd, E) || a.p != a.fd.N || a.m % a.S != 0 ||
+      (int64_t)(a.m / a.S) * a.nrows > 0x7fffffff)
+    return HD_BAD;
+  dim3 grid((unsigned)((a.m / a.S) * a.nrows)), block(nt);
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
 #define C1(EE) \
   if (E == EE) return go(k_cols_bwd<T, EE>, grid, block, lds, s, a);

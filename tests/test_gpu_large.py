@@ -28,13 +28,13 @@ def sample_idx(shape, n, seed):
     return np.unique(np.concatenate([head, tail, mid]))
 
 
-def run_case(shape, M, dtype, config_id, dist="disk", method="hybrid"):
+def run_case(shape, M, dtype, config_id, dist="disk", method="hybrid", **kw):
     import torch
     npdt = np.complex64 if dtype == "c64" else np.complex128
     xs = synth.inputs(config_id, 2, shape, dist, dtype=npdt)
     dev = [torch.from_numpy(x).cuda() for x in xs]
-    say("case", shape, M, dtype, method)
-    with Plan(shape, M, A=2, dtype=dtype, method=method) as p:
+    say("case", shape, M, dtype, method, kw)
+    with Plan(shape, M, A=2, dtype=dtype, method=method, **kw) as p:
         info = p.info()
         out = torch.empty_like(dev[0])
         p.execute(dev, out)
@@ -87,3 +87,14 @@ def test_c5_3d_256(gpu):
     e = sampled_err(ins, got, 24, 4)
     say("   sampled err %.3e" % e)
     assert e <= TOL["c64"]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_3d_inner_form_more_than_65535_rows(gpu, dtype):
+    # outer transforms of 256 points (q = 1) leave 256 * 256 = 65536 rows for
+    # the inner-form column passes of the last dimension
+    shape, M = (74, 74, 74), (148, 148, 148)
+    ins, got = run_case(shape, M, dtype, 4, m=(256, 256, 32), variant=("outer", "outer", "multipass"))
+    e = sampled_err(ins, got, 64, 5)
+    say("   sampled err %.3e" % e)
+    assert e <= TOL[dtype]

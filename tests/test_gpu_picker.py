@@ -33,6 +33,14 @@ def small_heldout(count, max_points=1 << 21):
     return out
 
 
+def _time(g, shape):
+    try:
+        return tune.time_shape(g["L"], g["M"], shape, A=g["A"], reps=7)
+    except Exception as e:  # reported by the assertion below
+        say("candidate failed: %s %s" % (shape, e))
+        return float("inf")
+
+
 def test_trained_model_inference_matches_reference(gpu):
     m = tune.load_default_model()
     p = m.params().astype(np.float64)
@@ -54,7 +62,8 @@ def test_trained_picker_gain_over_default(gpu):
         cands = tune.candidates(g["L"], g["M"], A=g["A"])
         X = np.array([tune.features(g["L"], g["M"], s, A=g["A"]) for _, s in cands], dtype=np.float32)
         pred = m.predict(X)
-        t = np.array([tune.time_shape(g["L"], g["M"], s, A=g["A"], reps=7) for _, s in cands])
+        t = np.array([_time(g, s) for _, s in cands])
+        assert np.isfinite(t).all(), "a candidate plan could not be timed"
         t_best, t_pick = t.min(), t[int(np.argmin(pred))]
         t_def = t[[k for k, (v, _) in enumerate(cands) if v == -1][0]]
         regrets.append(t_pick / t_best - 1.0)
