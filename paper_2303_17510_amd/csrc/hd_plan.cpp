@@ -292,10 +292,11 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // Inner form: the least padding q m over m = 1024 .. 8192 and p a power
     // of two, or 3 * 2^k from 96 up (small column transforms with a factor 3
     // measured slow; FP64 ones spill, so powers of two there).  Among equal
-    // padding the m nearest the measured best for that size: 2048 up to
-    // q m = 2^20, 4096 for 2^21, 8192 beyond.  Rows of 4096 points or more
-    // take 16 points per lane when there are enough of them (n p lines >=
-    // 512) to fill the chip, else 8.
+    // padding the m nearest the measured best for that size: for a single
+    // convolution 2048 up to q m = 2^20, 4096 for 2^21, 8192 beyond; for many
+    // rows (throughput) 4096.  Rows of 4096 points or more take 16 points per
+    // lane when there are enough of them (n p lines >= 512) to fill the
+    // chip, else 8.
     DimPlan best;
     bool found = false;
     double best_key = 0;
@@ -312,7 +313,8 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
         if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 512)) ? 16 : 8;
         if (!finish_dim(&c, A, tbytes, &w)) continue;
         const double qm = (double)(c.q * c.m);
-        const double mt = qm <= (double)(1 << 20) ? 2048.0 : (qm <= (double)(1 << 21) ? 4096.0 : 8192.0);
+        const double mt = lines > 1 ? 4096.0
+                                    : (qm <= (double)(1 << 20) ? 2048.0 : (qm <= (double)(1 << 21) ? 4096.0 : 8192.0));
         const double key = qm * 1e3 + std::fabs(std::log2((double)mm / mt));
         if (!found || key < best_key) {
           best = c;
