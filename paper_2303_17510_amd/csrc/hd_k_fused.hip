@@ -21,7 +21,7 @@ template <typename T, int E, int P, int A>
 __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   // Inputs small enough stay in registers across the residues; larger ones
   // are read again for each residue (from cache) to keep registers free.
-  constexpr bool kKeep = P * A * E <= 16;
+  constexpr bool kKeep = P * A * E <= 8;
   const int G = a.fd.G;
   const int m = a.m;
   const int slot = threadIdx.x / G;
