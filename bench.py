@@ -139,7 +139,7 @@ def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None):
     n_out = 1
     for l in wl["L"]:
         n_out *= l
-    r = {"stats": stats, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
+    r = {"stats": stats, "info": info, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
          "candidates": info.get("tuned_candidates"), "timed_candidates": info.get("timed_candidates"), "ms": ms,
          "outputs_per_s": n_out / (ms * 1e-3),
          "ns_per_NlogN": ms * 1e6 / (n_out * math.log2(max(2, n_out))),
@@ -208,6 +208,26 @@ def explicit_best(wl, dtype, steps, warmup):
     return best
 
 
+def kernel_flops(name, info, A=2):
+    """Algorithmic floating-point operations of one launch of a 1D plan's
+    kernel: 5 N log2 N per N-point complex FFT, 6 per complex multiply."""
+    import math
+    if len(info["dims"]) != 1:
+        return None
+    d = info["dims"][0]
+    m, p, D, q = d["m"], d["p"], d["D"], d["q"]
+    fft = lambda n: 5.0 * n * math.log2(n) if n > 1 else 0.0  # noqa: E731
+    if name == "rows_conv":
+        return D * p * ((A + 1) * fft(m) + 6.0 * m * (A + 1 + A - 1))
+    if name == "cols_fwd":
+        return A * D * m * (fft(p) + 6.0 * p)
+    if name == "cols_bwd":
+        return D * m * (fft(p) + 6.0 * p) + 2.0 * D * p * m
+    if name == "fused1d":
+        return q * ((A + 1) * fft(m) + 6.0 * m * (p * A + p + A - 1))
+    return None
+
+
 def copy_baseline(nbytes, reps=50):
     """GB/s of a plain device copy moving the same bytes (half read, half
     written) as one launch of the dominant kernel: the practical ceiling for
@@ -257,9 +277,17 @@ def cpu_baseline(wl, xs_by_dtype, outs_by_dtype, budget_s):
         oracle.conv_explicit(ins)
         t_total += time.perf_counter() - t0
         runs += 1
-    res = {"value": n_out * runs / t_total, "unit": "outputs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one run on a single thread too (the paper's T = 1 setting)
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.conv_explicit(ins)
+    t1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    res = {"value": n_out * runs / t_total, "unit": "outputs/s", "cores": cores, "kind": "oracle",
            "sample": "%d full runs of the workload through the FP64 oracle's explicitly padded FFT "
-                     "convolution (own radix-2 FFT, OpenMP), %.1f s total" % (runs, t_total)}
+                     "convolution (own radix-2 FFT, OpenMP), %.1f s total" % (runs, t_total),
+           "single_thread_value": n_out / t1}
     return res, errs
 
 
@@ -299,6 +327,7 @@ def main():
     log("workload:", wl["workload"])
     main_leg, xs32, out32 = leg(wl, wl["dtype"], "hybrid", args.steps, args.warmup)
     main_prof = main_leg.pop("stats")
+    main_info = main_leg.pop("info")
     log("hybrid c64: %.4f ms, %.3e outputs/s, dominant %s" % (main_leg["ms"], main_leg["outputs_per_s"],
                                                                main_leg["dominant"]))
     compare = {}
@@ -341,8 +370,24 @@ def main():
                 compare["batched_4096_c64_model"] = batched_leg(max(10, args.steps // 10), 3, tuner="model")
             compare["C1_8192_copies_c128"] = batched_leg(max(10, args.steps // 10), 3, dtype="c128",
                                                           Ls=[1024] * 8192, config_id=0)
+            # the 2D and 3D workloads, on the same GPU
+            w4, w5 = workload("c4"), workload("c5_3d")
+            for dt in ("c64", "c128"):
+                r, _, _ = leg(w4, dt, "hybrid", 20, 3)
+                compare["C4_2048x2048_hybrid_%s" % dt] = r
+            r, _, _ = leg(w4, "c64", "explicit", 10, 2)
+            compare["C4_2048x2048_explicit_c64"] = r
+            if have_model:
+                r, _, _ = leg(w4, "c64", "hybrid", 20, 3, tuner="model")
+                compare["C4_2048x2048_hybrid_c64_model"] = r
+            r, _, _ = leg(w5, "c64", "hybrid", 10, 2)
+            compare["C5_256cube_hybrid_c64"] = r
+            if have_model:
+                r, _, _ = leg(w5, "c64", "hybrid", 10, 2, tuner="model")
+                compare["C5_256cube_hybrid_c64_model"] = r
         for v in compare.values():
             v.pop("stats", None)
+            v.pop("info", None)
         for k, v in compare.items():
             dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
@@ -362,6 +407,15 @@ def main():
     traffic = read_traffic(dom["kernel"], args.workload, khash)
     dom_bytes = [v["bytes"] / v["launches"] for k, v in dominant(main_prof)[3].items() if k == dom["kernel"]][0]
     copy_gbps = copy_baseline(dom_bytes)
+    flops = kernel_flops(dom["kernel"], main_info, wl["A"])
+    alu = None
+    if flops:
+        tf = flops / (dom["avg_ms"] * 1e-3) / 1e12
+        # FP32 vector peak 157.3 TFLOP/s counts packed FP32 instructions,
+        # which this build does not emit: 78.6 TFLOP/s without them
+        pk = 157.3 if wl["dtype"] == "c64" else 78.6
+        alu = {"achieved": tf, "peak": pk, "unit": "TFLOP/s", "frac": tf / pk,
+               "peak_without_packed_fp32": 78.6, "flops_per_launch": flops}
     n_out = 1
     for l in wl["L"]:
         n_out *= l
@@ -383,7 +437,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic, "avg_ms": dom["avg_ms"], "bytes_per_launch": dom_bytes,
-                     "copy_same_bytes_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps if achieved else None},
+                     "copy_same_bytes_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps if achieved else None,
+                     "alu": alu},
         "cpu_baseline": cpu,
         "err_rel_l2": errs,
         "compulsory_frac": main_leg["compulsory_frac"],

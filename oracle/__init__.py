@@ -66,8 +66,9 @@ def _bind(path: str):
     lib.oracle_explicit.argtypes = [ctypes.POINTER(_dblp), ctypes.c_int, ctypes.c_int, _i64p, _dblp]
     lib.oracle_padded_dft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _dblp]
     lib.oracle_num_threads.argtypes = []
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit",
-               "oracle_padded_dft", "oracle_num_threads"):
+               "oracle_padded_dft", "oracle_num_threads", "oracle_set_num_threads"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -115,6 +116,11 @@ def _ip(a: np.ndarray):
 def num_threads() -> int:
     """OpenMP threads the oracle uses."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Set the OpenMP threads of the following oracle calls; returns the count."""
+    return int(_load().oracle_set_num_threads(int(n)))
 
 
 def _direct2(f: np.ndarray, g: np.ndarray, idx: np.ndarray | None) -> np.ndarray:

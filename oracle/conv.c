@@ -318,3 +318,14 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads for the parallel loops that follow (timing runs); returns the count. */
+int oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
