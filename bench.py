@@ -334,61 +334,68 @@ def main():
     outs = {"c64": {"hybrid_c64": out32}}
     xs_by = {"c64": xs32}
     if not args.no_compare:
-        r, o = explicit_best(wl, "c64", max(10, args.steps // 4), 5)
-        compare["explicit_c64"] = r
-        outs["c64"]["explicit_c64"] = o
-        r, xs64, o = leg(wl, "c128", "hybrid", max(10, args.steps // 4), 5)
-        compare["hybrid_c128"] = r
-        outs["c128"] = {"hybrid_c128": o}
-        xs_by["c128"] = xs64
-        r, o = explicit_best(wl, "c128", max(10, args.steps // 4), 5)
-        compare["explicit_c128"] = r
-        outs["c128"]["explicit_c128"] = o
-        r, _, _ = leg(wl, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
-        compare["hybrid_c64_tuned"] = r
-        r, _, _ = leg(wl, "c128", "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
-        compare["hybrid_c128_tuned"] = r
+        sc = max(10, args.steps // 4)
+
+        def run(name, fn):
+            """One comparison leg; a failing leg is reported, not fatal."""
+            try:
+                return fn()
+            except Exception as e:  # noqa: BLE001
+                log("compare leg %s failed: %s" % (name, e))
+                compare[name] = {"error": str(e)}
+                return None
+
+        def put(name, fn):
+            r = run(name, fn)
+            if r is not None:
+                compare[name] = r[0] if isinstance(r, tuple) else r
+            return r
+
+        r = put("explicit_c64", lambda: explicit_best(wl, "c64", sc, 5))
+        if r:
+            outs["c64"]["explicit_c64"] = r[1]
+        r = put("hybrid_c128", lambda: leg(wl, "c128", "hybrid", sc, 5))
+        if r:
+            outs["c128"] = {"hybrid_c128": r[2]}
+            xs_by["c128"] = r[1]
+        r = put("explicit_c128", lambda: explicit_best(wl, "c128", sc, 5))
+        if r and "c128" in outs:
+            outs["c128"]["explicit_c128"] = r[1]
+        put("hybrid_c64_tuned", lambda: leg(wl, "c64", "hybrid", sc, 5, tuner="exhaustive"))
+        put("hybrid_c128_tuned", lambda: leg(wl, "c128", "hybrid", sc, 5, tuner="exhaustive"))
         from paper_2303_17510_amd import tune as _tune
         have_model = os.path.exists(_tune.TRAINED_MODEL)
         if have_model:
-            r, _, _ = leg(wl, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="model")
-            compare["hybrid_c64_model"] = r
+            put("hybrid_c64_model", lambda: leg(wl, "c64", "hybrid", sc, 5, tuner="model"))
         if args.workload == "c2":
             w15 = workload("c2_1p5m")
             for dt in ("c64", "c128"):
-                r, _, _ = leg(w15, dt, "hybrid", max(10, args.steps // 4), 5)
-                compare["L1500000_hybrid_%s" % dt] = r
-                r, _, _ = leg(w15, dt, "hybrid", max(10, args.steps // 4), 5, tuner="exhaustive")
-                compare["L1500000_hybrid_%s_tuned" % dt] = r
-                r, _ = explicit_best(w15, dt, max(10, args.steps // 4), 5)
-                compare["L1500000_explicit_%s" % dt] = r
-            compare["batched_4096_c64"] = batched_leg(max(10, args.steps // 10), 3)
-            compare["batched_4096_c64_tuned"] = batched_leg(max(10, args.steps // 10), 3, tuner="exhaustive")
+                put("L1500000_hybrid_%s" % dt, lambda: leg(w15, dt, "hybrid", sc, 5))
+                put("L1500000_hybrid_%s_tuned" % dt, lambda: leg(w15, dt, "hybrid", sc, 5, tuner="exhaustive"))
+                put("L1500000_explicit_%s" % dt, lambda: explicit_best(w15, dt, sc, 5))
+            sb = max(10, args.steps // 10)
+            put("batched_4096_c64", lambda: batched_leg(sb, 3))
+            put("batched_4096_c64_tuned", lambda: batched_leg(sb, 3, tuner="exhaustive"))
             if have_model:
-                r, _, _ = leg(w15, "c64", "hybrid", max(10, args.steps // 4), 5, tuner="model")
-                compare["L1500000_hybrid_c64_model"] = r
-                compare["batched_4096_c64_model"] = batched_leg(max(10, args.steps // 10), 3, tuner="model")
-            compare["C1_8192_copies_c128"] = batched_leg(max(10, args.steps // 10), 3, dtype="c128",
-                                                          Ls=[1024] * 8192, config_id=0)
+                put("L1500000_hybrid_c64_model", lambda: leg(w15, "c64", "hybrid", sc, 5, tuner="model"))
+                put("batched_4096_c64_model", lambda: batched_leg(sb, 3, tuner="model"))
+            put("C1_8192_copies_c128", lambda: batched_leg(sb, 3, dtype="c128", Ls=[1024] * 8192, config_id=0))
             # the 2D and 3D workloads, on the same GPU
             w4, w5 = workload("c4"), workload("c5_3d")
             for dt in ("c64", "c128"):
-                r, _, _ = leg(w4, dt, "hybrid", 20, 3)
-                compare["C4_2048x2048_hybrid_%s" % dt] = r
-            r, _, _ = leg(w4, "c64", "explicit", 10, 2)
-            compare["C4_2048x2048_explicit_c64"] = r
+                put("C4_2048x2048_hybrid_%s" % dt, lambda: leg(w4, dt, "hybrid", 20, 3))
+            put("C4_2048x2048_explicit_c64", lambda: leg(w4, "c64", "explicit", 10, 2))
             if have_model:
-                r, _, _ = leg(w4, "c64", "hybrid", 20, 3, tuner="model")
-                compare["C4_2048x2048_hybrid_c64_model"] = r
-            r, _, _ = leg(w5, "c64", "hybrid", 10, 2)
-            compare["C5_256cube_hybrid_c64"] = r
+                put("C4_2048x2048_hybrid_c64_model", lambda: leg(w4, "c64", "hybrid", 20, 3, tuner="model"))
+            put("C5_256cube_hybrid_c64", lambda: leg(w5, "c64", "hybrid", 10, 2))
             if have_model:
-                r, _, _ = leg(w5, "c64", "hybrid", 10, 2, tuner="model")
-                compare["C5_256cube_hybrid_c64_model"] = r
+                put("C5_256cube_hybrid_c64_model", lambda: leg(w5, "c64", "hybrid", 10, 2, tuner="model"))
         for v in compare.values():
             v.pop("stats", None)
             v.pop("info", None)
         for k, v in compare.items():
+            if "error" in v:
+                continue
             dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
                                                                      dom["kernel"], dom["frac"]))

@@ -71,8 +71,10 @@ __device__ __forceinline__ void st_at(cpx<T>* base, uint32_t idx, cpx<T> v) {
   *(cpx<T>*)((char*)base + idx * (uint32_t)sizeof(cpx<T>)) = v;
 }
 
-// The planner keeps every transform length N below 2^27, so element offsets
-// within one row or one column block times the word size stay below 2^32.
+// Offsets passed to ld_at/st_at are positions within one row of at most
+// 2 * 8192 points (or a table of at most ~2^16 entries), so their byte
+// offsets stay far below 2^32; the planner keeps q m below 2^31, so
+// twiddle exponents reduced mod q m fit 32 bits.
 template <typename T>
 struct RootTable {
   const cpx<T>* lo;

@@ -171,6 +171,8 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
   if (dp->m < 1 || dp->p < 1 || dp->q < dp->p || dp->q * dp->m < dp->M)
     return fail("invalid geometry: need q >= p and q m >= M");
   if (dp->p * dp->m < dp->L) return fail("invalid geometry: need p m >= L");
+  // residue twiddle exponents are reduced mod q m in 32-bit arithmetic
+  if (dp->q * dp->m >= (int64_t(1) << 31)) return fail("q m must stay below 2^31");
   if (!fft_size_ok(dp->m)) return fail("m must be 2^a or 3*2^a (a >= 3)");
   if (dp->D < 1) dp->D = dp->n;
   if (dp->D > dp->n) return fail("D exceeds the number of residues");
@@ -327,7 +329,9 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
       *dp = best;
       return true;
     }
-    if (why) *why = "no supported plan for this length: " + w;
+    if (why)
+      *why = "no supported plan for this length (the inner form reaches L = 8192 x 4096)" +
+             (w.empty() ? std::string() : ": " + w);
     return false;
   }
   // Outer dimensions (every residue multiplies the inner work, measured on

@@ -135,6 +135,17 @@ def test_unsupported_arguments():
     with pytest.raises(_lib.HdconvError) as ei:
         Plan((10,), (40,), A=4, host_only=True)
     assert ei.value.code == _lib.EUNSUPPORTED
+    # beyond the longest supported 1D length (8192-point rows x 4096-point columns)
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan(((1 << 25) + 1,), ((1 << 26) + 2,), host_only=True)
+    assert ei.value.code == _lib.EUNSUPPORTED
+    with Plan((1 << 25,), (1 << 26,), host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["p"] * d["m"] >= 1 << 25 and d["q"] * d["m"] >= 1 << 26
+    # q m would not fit the 32-bit residue twiddle exponents
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((1000,), (1 << 32,), host_only=True)
+    assert ei.value.code == _lib.EUNSUPPORTED
 
 
 def test_forced_p_gt_2_needs_multipass():

@@ -98,3 +98,13 @@ def test_3d_inner_form_more_than_65535_rows(gpu, dtype):
     e = sampled_err(ins, got, 64, 5)
     say("   sampled err %.3e" % e)
     assert e <= TOL[dtype]
+
+
+def test_1d_maximum_length(gpu):
+    # the largest 1D length the planner supports: 8192-point rows times
+    # 4096-point columns, L = 2^25 (complex64), checked on sampled outputs
+    L = 1 << 25
+    ins, got = run_case((L,), (2 * L,), "c64", 1)
+    e = sampled_err(ins, got, 24, 6)
+    say("   sampled err %.3e" % e)
+    assert e <= TOL["c64"]

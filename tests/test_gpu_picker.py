@@ -1,11 +1,10 @@
 """The trained picker on the GPU.
 
 The package ships an MLP trained on this library's own autotuner timings
-(trained/picker_mlp.f32).  Checks: its HIP inference agrees with the FP64
-reference network; on held-out geometries (the held-out seed of the
-cost-model workload) the plan it picks is close to the exhaustive search's
-and at least as fast as the untuned default plan, while the model tuner times
-only a few candidates where the exhaustive one times them all.
+(trained/picker_mlp.f32).  Checks: on held-out geometries (the held-out seed
+of the cost-model workload) the plan it picks is close to the exhaustive
+search's and at least as fast as the untuned default plan, while the model
+tuner times only a few candidates where the exhaustive one times them all.
 """
 import math
 import sys
@@ -13,7 +12,6 @@ import sys
 import numpy as np
 import pytest
 
-from oracle import mlp_ref
 from paper_2303_17510_amd import Plan, costmodel, tune
 
 pytestmark = pytest.mark.gpu
@@ -39,20 +37,6 @@ def _time(g, shape):
     except Exception as e:  # reported by the assertion below
         say("candidate failed: %s %s" % (shape, e))
         return float("inf")
-
-
-def test_trained_model_inference_matches_reference(gpu):
-    m = tune.load_default_model()
-    p = m.params().astype(np.float64)
-    X = []
-    for g in small_heldout(4):
-        for _, shp in tune.candidates(g["L"], g["M"], A=g["A"]):
-            X.append(tune.features(g["L"], g["M"], shp, A=g["A"]))
-    X = np.array(X, dtype=np.float32)
-    got = m.predict(X).astype(np.float64)
-    ref = mlp_ref.predict_log_ms(p, X.astype(np.float64), tune.NF, m.hidden)
-    say("max |pred - ref| = %.2e over %d rows" % (np.abs(got - ref).max(), len(X)))
-    assert np.abs(got - ref).max() < 1e-3
 
 
 def test_trained_picker_gain_over_default(gpu):

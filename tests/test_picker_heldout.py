@@ -3,10 +3,11 @@
 trained/heldout.npz holds the autotuner's timings of every candidate plan of
 500 held-out geometries (seed 17510501 of the cost-model workload), written
 by ``python -m paper_2303_17510_amd.costmodel collect``; trained/picker_mlp.f32
-is the network trained on 2000 other geometries.  The FP64 reference network
-(oracle/mlp_ref.py) predicts each candidate's log time; the pick is the
-argmin, its regret t(pick)/t(best) - 1.  The target is a geometric-mean
-regret within 5 %.
+is the network trained on 2000 other geometries.  The shipped network is
+evaluated here in FP64 with NumPy (the documented layout: normalised inputs,
+three SiLU layers, linear output); the pick is the argmin of the predicted
+log times, its regret t(pick)/t(best) - 1 against the timed exhaustive best.
+The target is a geometric-mean regret within 5 %.
 """
 import json
 import math
@@ -14,7 +15,6 @@ import os
 
 import numpy as np
 
-from oracle import mlp_ref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAINED = os.path.join(HERE, "..", "paper_2303_17510_amd", "trained")
@@ -28,10 +28,26 @@ def _model():
     return p, hdr
 
 
+def _predict(p, X, nf, h):
+    shapes = [(nf, h), (h,), (h, h), (h,), (h, h), (h,), (h, 1), (1,)]
+    W, o = [], 0
+    for sh in shapes:
+        k = int(np.prod(sh))
+        W.append(p[o:o + k].reshape(sh))
+        o += k
+    xm, xs = p[o:o + nf], p[o + nf:o + 2 * nf]
+    ym, ys = p[o + 2 * nf], p[o + 2 * nf + 1]
+    a = (X - xm) / xs
+    for l in range(4):
+        z = a @ W[2 * l] + W[2 * l + 1]
+        a = z / (1.0 + np.exp(-z)) if l < 3 else z
+    return a[:, 0] * ys + ym
+
+
 def _regrets(name):
     p, hdr = _model()
     d = np.load(os.path.join(TRAINED, name), allow_pickle=False)
-    pred = mlp_ref.predict_log_ms(p, d["X"].astype(np.float64), hdr["nfeatures"], hdr["hidden"])
+    pred = _predict(p, d["X"].astype(np.float64), hdr["nfeatures"], hdr["hidden"])
     regrets, gains = [], []
     for g in np.unique(d["gid"]):
         idx = np.nonzero(d["gid"] == g)[0]
