@@ -72,8 +72,8 @@ typedef struct hdconv_options {
   int64_t p[3];      /* forced explicit block count, >= ceil(L/m) (0: minimal)  */
   int64_t D[3];      /* residues per block, innermost multipass dim (0: all)    */
   int variant[3];    /* HDCONV_VARIANT_* per dimension                          */
-  int E_m[3];        /* points per lane of the m-point transform (0: choose)    */
-  int E_p[3];        /* points per lane of the p-point transform (0: choose)    */
+  int E_m[3];        /* points per lane of the m-point transform: 4, 8, 12 or 16 (0: choose) */
+  int E_p[3];        /* points per lane of the p-point transform: 1, 2, 4, 8, 12 or 16 (0: choose) */
   int S[3];          /* columns per workgroup of column/outer kernels (0: choose) */
   int rows_per_block[3]; /* rows per workgroup of row kernels (0: choose)       */
   int twiddles[3];   /* FFT twiddles: 0 choose, 1 two-level root table, 2 exact per-stage tables */

@@ -1,6 +1,6 @@
 // hd_engine.hpp -- argument blocks and launchers of the hybrid-dealiasing
 // HIP kernels.  Host code fills these structs from a plan; the kernels live in
-// hd_kernels.hip.
+// hd_k_fused.hip, hd_k_multi.hip and hd_k_outer.hip.
 //
 // Notation (Murasko & Bowman, arXiv 2303.17510): a dimension of length L is
 // padded to at least M; m is the subtransform size, the input is explicitly

@@ -347,7 +347,7 @@ __device__ __forceinline__ void gfft_any(cpx<T> (&v)[NT][E], int g_in, const Fft
       return;                                                  \
     }                                                          \
   }
-  HD_CT(128) HD_CT(256) HD_CT(512) HD_CT(1024) HD_CT(2048) HD_CT(4096) HD_CT(8192) HD_CT(16384)
+  HD_CT(128) HD_CT(256) HD_CT(512) HD_CT(1024) HD_CT(2048) HD_CT(4096) HD_CT(8192)
 #undef HD_CT
   gfft<T, E, S, NT>(v, g, d, tw, xb);
 }

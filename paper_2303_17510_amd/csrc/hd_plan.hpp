@@ -17,7 +17,7 @@ enum Variant {
   VAR_OUTER = 3   // outer dimension of a multidimensional convolution, direct form
 };
 
-// Limits of the kernels (see hd_kernels.hip).
+// Limits of the kernels (hd_k_fused.hip, hd_k_multi.hip, hd_k_outer.hip).
 constexpr int kMaxThreads = 512;
 constexpr int64_t kMaxFusedM = 8192;   // m of the fused and outer kernels
 constexpr int64_t kMaxRowM = 8192;     // m of the row-convolution pass
