@@ -17,6 +17,13 @@ Functions (Murasko & Bowman, arXiv 2303.17510):
 * :func:`conv_explicit` -- O2, explicit zero padding to a power of two
   ``N' >= A(L-1)+1`` (the minimal padding of Sec. 2), this package's own FFT,
   pointwise product, inverse, truncation to the first ``L`` per dimension.
+* :func:`conv_centered_direct` -- OC, centered convolution (the paper's
+  centered case in one dimension, Sec. 5 per dimension): an extent-``L`` array
+  holds centered indices ``-H .. L-1-H`` (``H = floor(L/2)``) at positions
+  ``c + H``, and ``h_c = sum f_{c1} g_{c-c1}`` over the in-range ``c1``
+  (``A = 3``: the triple sum), evaluated as compensated direct sums.
+* :func:`conv_centered_explicit` -- OC by O2: entries ``(A-1)H ..
+  (A-1)H+L-1`` per dimension of the explicitly padded linear convolution.
 * :func:`padded_dft` -- the padded DFT of Sec. 2,
   ``F_k = sum_{j<L} zeta_N^{kj} f_j`` with ``zeta_N = exp(+2 pi i/N)``.
 * :func:`fft` / :func:`fft_nd` -- the unnormalised transform
@@ -64,11 +71,14 @@ def _bind(path: str):
     lib.oracle_fft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int]
     lib.oracle_fft_nd.argtypes = [_dblp, ctypes.c_int, _i64p, ctypes.c_int]
     lib.oracle_explicit.argtypes = [ctypes.POINTER(_dblp), ctypes.c_int, ctypes.c_int, _i64p, _dblp]
+    lib.oracle_explicit_centered.argtypes = [ctypes.POINTER(_dblp), ctypes.c_int, ctypes.c_int, _i64p, _dblp]
+    lib.oracle_direct_centered.argtypes = [_dblp, _i64p, _i64p, _dblp, _i64p, _i64p, ctypes.c_int, _i64p, _i64p,
+                                           _i64p, ctypes.c_int64, _dblp]
     lib.oracle_padded_dft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _dblp]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
-    for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit",
-               "oracle_padded_dft", "oracle_num_threads", "oracle_set_num_threads"):
+    for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit", "oracle_explicit_centered",
+               "oracle_direct_centered", "oracle_padded_dft", "oracle_num_threads", "oracle_set_num_threads"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -171,6 +181,67 @@ def conv_explicit(inputs) -> np.ndarray:
     rc = _load().oracle_explicit(ptrs, len(ins), len(shape), _ip(L), _dp(out))
     if rc != 0:
         raise ValueError("oracle_explicit failed (%d)" % rc)
+    return out
+
+
+def _direct_centered(a: np.ndarray, ha, b: np.ndarray, hb, lo, ho, idx) -> np.ndarray:
+    dims = a.ndim
+    La = np.array(a.shape, dtype=np.int64)
+    Lb = np.array(b.shape, dtype=np.int64)
+    Lo = np.array(lo, dtype=np.int64)
+    Ha = np.array(ha, dtype=np.int64)
+    Hb = np.array(hb, dtype=np.int64)
+    Ho = np.array(ho, dtype=np.int64)
+    if idx is None:
+        idx = np.arange(int(np.prod(Lo)), dtype=np.int64)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).ravel())
+    out = np.empty(idx.size, dtype=np.complex128)
+    rc = _load().oracle_direct_centered(_dp(a), _ip(La), _ip(Ha), _dp(b), _ip(Lb), _ip(Hb), dims, _ip(Lo), _ip(Ho),
+                                        _ip(idx), idx.size, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_direct_centered failed (%d)" % rc)
+    return out
+
+
+def conv_centered_direct(inputs, idx=None) -> np.ndarray:
+    """OC: centered convolution of ``A`` (2 or 3) arrays of one shape.
+
+    Position ``i`` of a dimension of extent ``L`` holds centered index
+    ``i - floor(L/2)``, for the inputs and the output alike; the output is
+    ``h_c = sum_{c1 + ... + cA = c} f_{c1} ... `` over in-range indices.  With
+    ``idx`` (flat output positions) only those outputs are returned.
+    """
+    ins = [_c128(x) for x in inputs]
+    if len(ins) not in (2, 3) or any(x.shape != ins[0].shape for x in ins):
+        raise ValueError("need 2 or 3 inputs of one shape")
+    if ins[0].ndim not in (1, 2, 3):
+        raise ValueError("1 to 3 dimensions")
+    shape = ins[0].shape
+    H = [n // 2 for n in shape]
+    if len(ins) == 2:
+        out = _direct_centered(ins[0], H, ins[1], H, shape, H, idx)
+    else:
+        # the full centered product of the first two factors: extent 2L-1,
+        # centered indices -2H .. 2(L-1-H) at positions c + 2H
+        full = [2 * n - 1 for n in shape]
+        H2 = [2 * h for h in H]
+        t = _direct_centered(ins[0], H, ins[1], H, full, H2, None).reshape(full)
+        out = _direct_centered(t, H2, ins[2], H, shape, H, idx)
+    return out if idx is not None else out.reshape(shape)
+
+
+def conv_centered_explicit(inputs) -> np.ndarray:
+    """OC by explicit zero padding: the centered window of the linear convolution."""
+    ins = [_c128(x) for x in inputs]
+    if len(ins) not in (2, 3) or any(x.shape != ins[0].shape for x in ins):
+        raise ValueError("need 2 or 3 inputs of one shape")
+    shape = ins[0].shape
+    L = np.array(shape, dtype=np.int64)
+    ptrs = (_dblp * len(ins))(*[_dp(x) for x in ins])
+    out = np.empty(shape, dtype=np.complex128)
+    rc = _load().oracle_explicit_centered(ptrs, len(ins), len(shape), _ip(L), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_explicit_centered failed (%d)" % rc)
     return out
 
 

@@ -26,6 +26,16 @@
  *      inverse transformed, divided by N', and truncated to the first L
  *      entries per dimension.  N' is this file's own choice.
  *
+ *  OC  centered convolutions (the paper's section on centered convolutions
+ *      in one dimension, eq. centDFT; Sec. 5 per dimension): an array of L
+ *      entries holds f_c for the centered indices c = -H .. L-1-H,
+ *      H = floor(L/2), at position c + H, and the convolution is
+ *          h_c = sum_{c1} f_{c1} g_{c-c1},   c = -H .. L-1-H,
+ *      over every c1 with both c1 and c - c1 in range (A = 3: the triple
+ *      sum, formed from the full pairwise convolution).  Evaluated as direct
+ *      compensated sums, and as O2 on the full linear convolution whose
+ *      entries (A-1)H .. (A-1)H+L-1 per dimension are the centered outputs.
+ *
  *  PD  the padded DFT of Sec. 2, F_k = sum_{j<L} zeta_N^{kj} f_j with
  *      zeta_N = exp(+2 pi i / N), evaluated term by term at requested k with
  *      the phase k*j reduced modulo N in exact integer arithmetic.  Used to
@@ -214,8 +224,13 @@ int oracle_fft_nd(double* x, int dims, const int64_t* N, int sign) {
  * inputs: A pointers to complex arrays of prod(L) entries; out: prod(L)
  * complex.  A in {2, 3}; mult = product of the A transforms.
  */
-int oracle_explicit(const double* const* inputs, int A, int dims, const int64_t* L, double* out) {
+/* O2 with the output box starting at position off[d] of the full linear
+ * convolution (0 for O1's first L outputs, (A-1)H for the centered ones). */
+static int explicit_window(const double* const* inputs, int A, int dims, const int64_t* L, const int64_t* off,
+                           double* out) {
   if (A < 2 || A > 3 || dims < 1 || dims > 3) return -1;
+  for (int d = 0; d < dims; ++d)
+    if (off[d] < 0 || off[d] + L[d] > (int64_t)A * (L[d] - 1) + 1) return -1;
   int64_t N[3], total = 1, ltotal = 1;
   for (int d = 0; d < dims; ++d) {
 #if ORACLE_MUTANT == 5 /* padding one short of the minimal A(L-1)+1 */
@@ -273,7 +288,7 @@ int oracle_explicit(const double* const* inputs, int A, int dims, const int64_t*
     for (int64_t j = 0; j < ltotal; ++j) {
       int64_t rem = j, src = 0, mul = 1;
       for (int d = dims - 1; d >= 0; --d) {
-        int64_t c = rem % L[d];
+        int64_t c = rem % L[d] + off[d];
         rem /= L[d];
         src += c * mul;
         mul *= N[d];
@@ -285,6 +300,80 @@ int oracle_explicit(const double* const* inputs, int A, int dims, const int64_t*
 done:
   for (int a = 0; a < A; ++a) free(buf[a]);
   return rc;
+}
+
+int oracle_explicit(const double* const* inputs, int A, int dims, const int64_t* L, double* out) {
+  const int64_t off[3] = {0, 0, 0};
+  return explicit_window(inputs, A, dims, L, off, out);
+}
+
+/* OC by O2: the centered outputs are entries (A-1)H .. (A-1)H+L-1 of the
+ * full linear convolution of the arrays (every centered index shifted by H). */
+int oracle_explicit_centered(const double* const* inputs, int A, int dims, const int64_t* L, double* out) {
+  if (A < 2 || A > 3 || dims < 1 || dims > 3) return -1;
+  int64_t off[3] = {0, 0, 0};
+#if ORACLE_MUTANT == 9 /* centre rounded up instead of down */
+  for (int d = 0; d < dims; ++d) off[d] = (int64_t)(A - 1) * ((L[d] + 1) / 2);
+#else
+  for (int d = 0; d < dims; ++d) off[d] = (int64_t)(A - 1) * (L[d] / 2);
+#endif
+  return explicit_window(inputs, A, dims, L, off, out);
+}
+
+/* ---- OC: centered direct sums ------------------------------------------
+ * Operand a has extents La and centre offsets Ha (entry at position k holds
+ * centered index k - Ha), operand b likewise (Lb, Hb); output position i
+ * holds centered index i - Ho (extents Lo).  For every requested flat output
+ * position: out = sum over positions k of a with
+ *     c1 = k - Ha,  c2 = (i - Ho) - c1  and  0 <= c2 + Hb < Lb
+ * of a[k] * b[c2 + Hb], per dimension.
+ */
+int oracle_direct_centered(const double* fa, const int64_t* La, const int64_t* Ha, const double* fb,
+                           const int64_t* Lb, const int64_t* Hb, int dims, const int64_t* Lo, const int64_t* Ho,
+                           const int64_t* idx, int64_t nidx, double* out) {
+  if (dims < 1 || dims > 3) return -1;
+  int64_t ea[3] = {1, 1, 1}, ha[3] = {0, 0, 0}, eb[3] = {1, 1, 1}, hb[3] = {0, 0, 0};
+  int64_t eo[3] = {1, 1, 1}, ho[3] = {0, 0, 0};
+  for (int d = 0; d < dims; ++d) {
+    const int k = 3 - dims + d;
+    ea[k] = La[d];
+    ha[k] = Ha[d];
+    eb[k] = Lb[d];
+    hb[k] = Hb[d];
+    eo[k] = Lo[d];
+    ho[k] = Ho[d];
+  }
+  const int64_t total = eo[0] * eo[1] * eo[2];
+  for (int64_t n = 0; n < nidx; ++n)
+    if (idx[n] < 0 || idx[n] >= total) return -2;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t n = 0; n < nidx; ++n) {
+    const int64_t j = idx[n];
+    const int64_t o[3] = {j / (eo[1] * eo[2]), (j / eo[2]) % eo[1], j % eo[2]};
+    nsum_t re = {0, 0}, im = {0, 0};
+    for (int64_t k0 = 0; k0 < ea[0]; ++k0) {
+      const int64_t b0 = (o[0] - ho[0]) - (k0 - ha[0]) + hb[0];
+      if (b0 < 0 || b0 >= eb[0]) continue;
+      for (int64_t k1 = 0; k1 < ea[1]; ++k1) {
+        const int64_t b1 = (o[1] - ho[1]) - (k1 - ha[1]) + hb[1];
+        if (b1 < 0 || b1 >= eb[1]) continue;
+        for (int64_t k2 = 0; k2 < ea[2]; ++k2) {
+#if ORACLE_MUTANT == 8 /* centre of the second operand off by one (last axis) */
+          const int64_t b2 = (o[2] - ho[2]) - (k2 - ha[2]) + hb[2] + 1;
+#else
+          const int64_t b2 = (o[2] - ho[2]) - (k2 - ha[2]) + hb[2];
+#endif
+          if (b2 < 0 || b2 >= eb[2]) continue;
+          const int64_t a = (k0 * ea[1] + k1) * ea[2] + k2;
+          const int64_t b = (b0 * eb[1] + b1) * eb[2] + b2;
+          cmac(&re, &im, fa[2 * a], fa[2 * a + 1], fb[2 * b], fb[2 * b + 1]);
+        }
+      }
+    }
+    out[2 * n] = nsum_get(&re);
+    out[2 * n + 1] = nsum_get(&im);
+  }
+  return 0;
 }
 
 /* ---- PD: padded DFT at requested frequencies ------------------------------

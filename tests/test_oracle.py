@@ -6,7 +6,11 @@ convolution, closed forms of the linear convolution (delta, all-ones,
 geometric sequences, separable products), and invariants (linearity,
 commutativity, shift equivariance).  The definition being pinned is the
 linear convolution of Sec. 2 (its first L outputs, which Algorithm 1 returns)
-and the padded DFT with zeta_N = exp(+2 pi i/N) (Sec. 2).
+and the padded DFT with zeta_N = exp(+2 pi i/N) (Sec. 2).  The centered
+convolution (the paper's centered case: indices -H .. L-1-H, H = floor(L/2))
+is pinned by a literal dictionary evaluation of its definition on tiny inputs,
+by the Fourier coefficients of a product of trigonometric polynomials (numpy's
+FFT), by centered deltas and by a geometric closed form.
 """
 import numpy as np
 import pytest
@@ -213,3 +217,108 @@ def test_explicit_closed_form_geometric_large():
 def test_rel_l2():
     assert oracle.rel_l2([1, 0], [1, 0]) == 0
     assert abs(oracle.rel_l2([1, 1], [1, 0]) - 1.0) < 1e-15
+
+
+# ------------------------------------------------- centered convolution ----
+def _centered_brute(ins):
+    """h_c = sum over c1 + ... + cA = c of the product, every c_k in
+    -H .. L-1-H, written with dictionaries keyed by centered index (1D)."""
+    L = len(ins[0])
+    H = L // 2
+    rng = range(-H, L - H)
+    arrs = [{c: x[c + H] for c in rng} for x in ins]
+    acc = {0: 1.0 + 0j}
+    for a in arrs:
+        nxt = {}
+        for c0, v in acc.items():
+            for c1 in rng:
+                nxt[c0 + c1] = nxt.get(c0 + c1, 0) + v * a[c1]
+        acc = nxt
+    return np.array([acc[c] for c in rng])
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 9])
+def test_centered_brute_force_tiny(L):
+    for A in (2, 3):
+        ins = [rnd(L, 50 + 7 * L + k) for k in range(A)]
+        ref = _centered_brute(ins)
+        np.testing.assert_allclose(oracle.conv_centered_direct(ins), ref, atol=1e-14)
+        np.testing.assert_allclose(oracle.conv_centered_explicit(ins), ref, atol=1e-14)
+
+
+def _centered_by_fourier_product(ins):
+    """Coefficients of the product of the trigonometric polynomials
+    sum_c f_c exp(i c.theta): sample each on an N-point grid per dimension
+    (N > A(L-1), so no coefficient of the product wraps), multiply, and read
+    the coefficients -H .. L-1-H back with numpy's forward FFT."""
+    shape = ins[0].shape
+    A = len(ins)
+    H = [n // 2 for n in shape]
+    N = [A * (n - 1) + 1 for n in shape]
+    prod = np.ones(N, complex)
+    for x in ins:
+        arr = np.zeros(N, complex)
+        pos = np.ix_(*[(np.arange(n) - h) % m for n, h, m in zip(shape, H, N)])
+        arr[pos] = x
+        prod *= np.fft.ifftn(arr) * np.prod(N)
+    coef = np.fft.fftn(prod) / np.prod(N)
+    return coef[np.ix_(*[(np.arange(n) - h) % m for n, h, m in zip(shape, H, N)])]
+
+
+@pytest.mark.parametrize("shape", [(10,), (11,), (64,), (6, 7), (4, 5, 3)])
+def test_centered_matches_fourier_product(shape):
+    for A in (2, 3):
+        ins = [rnd(shape, 70 + k) for k in range(A)]
+        ref = _centered_by_fourier_product(ins)
+        assert oracle.rel_l2(oracle.conv_centered_direct(ins), ref) < 1e-13
+        assert oracle.rel_l2(oracle.conv_centered_explicit(ins), ref) < 1e-13
+
+
+def test_centered_delta_identity_and_shift():
+    for shape in [(9,), (10,), (5, 6), (3, 4, 5)]:
+        g = rnd(shape, 90)
+        H = tuple(n // 2 for n in shape)
+        d = np.zeros(shape, complex)
+        d[H] = 1  # centered index 0
+        np.testing.assert_array_equal(oracle.conv_centered_direct([d, g]), g)
+        np.testing.assert_allclose(oracle.conv_centered_explicit([d, g]), g, atol=1e-14)
+        np.testing.assert_array_equal(oracle.conv_centered_direct([d, d, g]), g)
+    # delta at centered index s: h_c = g_{c-s} where c - s is in range
+    L, s = 12, -3
+    H = L // 2
+    g = rnd(L, 91)
+    d = np.zeros(L, complex)
+    d[s + H] = 1
+    ref = np.zeros(L, complex)
+    for c in range(-H, L - H):
+        if -H <= c - s < L - H:
+            ref[c + H] = g[c - s + H]
+    np.testing.assert_array_equal(oracle.conv_centered_direct([d, g]), ref)
+    np.testing.assert_allclose(oracle.conv_centered_explicit([d, g]), ref, atol=1e-14)
+
+
+@pytest.mark.parametrize("L", [255, 256])
+def test_centered_geometric_closed_form(L):
+    # f_c = a^c, g_c = b^c: h_c = b^c sum_{c1=lo}^{hi} (a/b)^{c1}
+    H = L // 2
+    a, b = 0.99 * np.exp(0.03j), 1.01 * np.exp(-0.05j)
+    c = np.arange(-H, L - H)
+    f, g = a ** c, b ** c
+    lo = np.maximum(-H, c - (L - 1 - H))
+    hi = np.minimum(L - 1 - H, c + H)
+    r = a / b
+    ref = b ** c * (r ** lo - r ** (hi + 1)) / (1 - r)
+    assert oracle.rel_l2(oracle.conv_centered_direct([f, g]), ref) < 1e-13
+    assert oracle.rel_l2(oracle.conv_centered_explicit([f, g]), ref) < 1e-13
+
+
+def test_centered_sampled_and_commutative():
+    shape = (9, 14)
+    f, g, h = rnd(shape, 95), rnd(shape, 96), rnd(shape, 97)
+    full = oracle.conv_centered_direct([f, g])
+    np.testing.assert_allclose(oracle.conv_centered_direct([g, f]), full, atol=1e-14)
+    idx = np.array([0, 5, 17, 63, 125])
+    np.testing.assert_array_equal(oracle.conv_centered_direct([f, g], idx=idx), full.ravel()[idx])
+    full3 = oracle.conv_centered_direct([f, g, h])
+    np.testing.assert_allclose(oracle.conv_centered_direct([h, f, g]), full3, atol=1e-13)
+    np.testing.assert_array_equal(oracle.conv_centered_direct([f, g, h], idx=idx), full3.ravel()[idx])
