@@ -62,8 +62,22 @@ enum {
 /* plan flags */
 enum {
   HDCONV_PLAN_HOST_ONLY = 1, /* plan geometry only: no device memory, cannot execute */
-  HDCONV_BATCH_NO_GRAPH = 2  /* batched plans: launch eagerly on every execute      */
+  HDCONV_BATCH_NO_GRAPH = 2, /* batched plans: launch eagerly on every execute      */
+  HDCONV_PLAN_CENTERED = 4   /* centered convolution (see below); plans and batches */
 };
+
+/* Centered convolutions (the paper's section on centered convolutions in one
+ * dimension, eq. centDFT, with its inner form, and Sec. 5 per dimension).
+ * With HDCONV_PLAN_CENTERED an array of extent L holds the signed indices
+ * c = -H .. L-1-H, H = floor(L/2), at positions c + H (index 0 in the
+ * middle), for the inputs and the output alike, and the output is
+ *     h_c = sum_{c_1 + ... + c_A = c} f_{c_1} ... g_{c_A},   c = -H .. L-1-H,
+ * over in-range indices (per dimension for d = 2, 3).  The hybrid method runs
+ * the centered transforms: p = ceil(H/m) + ceil((L-H)/m) blocks of m points
+ * (2 for m >= L/2) holding the signed indices, twiddles of the signed index.
+ * The padding needed is smaller: M >= max(A(L-1-H)+H, L-1-H+AH) + 1, i.e.
+ * 3L/2 for A = 2 and even L, instead of A(L-1)+1.  The explicit method pads
+ * the arrays as they are and copies out entries (A-1)H .. (A-1)H+L-1. */
 
 typedef struct hdconv_options {
   int method;        /* HDCONV_METHOD_*                                         */
@@ -99,6 +113,9 @@ typedef struct hdconv_dim_info {
   int S;             /* columns per workgroup (column / outer kernels)          */
   int rows_per_block;/* rows per workgroup (row kernels)                        */
   int tw_m, tw_p;    /* twiddle mode of the m- and p-point transforms (1 two-level, 2 per-stage) */
+  int centered;      /* 1: centered transforms (HDCONV_PLAN_CENTERED); shapes
+                        passed to hdconv_time_shape / hdconv_features take the
+                        flag from dimension 0's field                          */
 } hdconv_dim_info_t;
 
 typedef struct hdconv_plan_info {
@@ -121,7 +138,9 @@ typedef struct hdconv_plan_info {
  * for a problem the way the paper's optimizer decouples it (Sec. 7): the
  * default plan, and that plan with one dimension's shape replaced by each of
  * its candidates.  Candidate k is out[k*dims .. k*dims+dims); varied[k] is the
- * dimension it changes (-1 for the default plan).  Host only. */
+ * dimension it changes (-1 for the default plan).  Uncentered problems;
+ * centered plans are tuned through hdconv_plan_ex with options.tuner.  Host
+ * only. */
 int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                       hdconv_dim_info_t* out, int* varied, int cap, int* count);
 
@@ -142,7 +161,8 @@ void hdconv_options_init(hdconv_options* opt);
 /* Create a plan on the current HIP device.  L[d], M[d] for d < dims
  * (dims in {1,2,3}); A in {2,3}; B = 1; dtype HDCONV_C64 or HDCONV_C128.
  * Requires L[d] >= 1 and M[d] >= A (L[d]-1) + 1 (the padding that keeps the
- * product of A inputs unaliased, Sec. 2).  Allocates twiddle tables (FP64
+ * product of A inputs unaliased, Sec. 2; centered plans: the centered minimum
+ * above).  Allocates twiddle tables (FP64
  * generated, stored in dtype) and workspace with hipMalloc.  Returns NULL on
  * error (hdconv_last_error gives the reason). */
 void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype);

@@ -19,6 +19,7 @@ METHOD_AUTO, METHOD_HYBRID, METHOD_EXPLICIT = 0, 1, 2
 VARIANT_AUTO, VARIANT_FUSED, VARIANT_MULTIPASS, VARIANT_OUTER = 0, 1, 2, 3
 PLAN_HOST_ONLY = 1
 BATCH_NO_GRAPH = 2
+PLAN_CENTERED = 4
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
 NFEATURES = 44
 
@@ -41,7 +42,7 @@ class DimInfo(ctypes.Structure):
     _fields_ = [("L", _i64), ("M", _i64), ("m", _i64), ("p", _i64), ("n", _i64), ("q", _i64),
                 ("D", _i64), ("variant", ctypes.c_int), ("E_m", ctypes.c_int), ("E_p", ctypes.c_int),
                 ("S", ctypes.c_int), ("rows_per_block", ctypes.c_int), ("tw_m", ctypes.c_int),
-                ("tw_p", ctypes.c_int)]
+                ("tw_p", ctypes.c_int), ("centered", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):

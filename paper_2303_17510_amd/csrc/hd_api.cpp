@@ -134,6 +134,9 @@ static int64_t lines_of(const Plan* P, int d) {
 
 static int build_dims(Plan* P, const hdconv_options* opt) {
   const int tb = tbytes_of(P->dtype);
+  // centered hybrid plans run centered transforms; the explicit method pads
+  // the arrays as they are and reads the centered window out of the result
+  const int ctr = (P->flags & HDCONV_PLAN_CENTERED) && P->method != HDCONV_METHOD_EXPLICIT ? 1 : 0;
   for (int d = 0; d < P->dims; ++d) {
     const bool contiguous = (d == P->dims - 1);
     int64_t Le = P->L[d], Me = P->M[d];
@@ -184,23 +187,23 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
         }
         if (!finish_dim(&dp, P->A, tb, &why))
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
-      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why)) {
+      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
     } else {
       if (fv == HDCONV_VARIANT_AUTO) {
-        Geometry g = geometry(Le, Me, fm ? fm : next_fft_size(Le), fp, false);
+        Geometry g = geometry_c(Le, Me, fm ? fm : next_fft_size(Le), fp, false, ctr);
         fv = contiguous ? (g.inner ? VAR_MULTI : VAR_FUSED) : VAR_OUTER;
       }
       if (contiguous && fv == VAR_OUTER) return set_err(HDCONV_EINVAL, "dim %d: outer variant on the innermost dimension", d);
       if (!contiguous && fv != VAR_OUTER) return set_err(HDCONV_EUNSUPPORTED, "dim %d: outer dimensions use the outer variant", d);
       int64_t m = fm ? fm : next_fft_size(fv == VAR_MULTI ? cdiv(Le, std::max<int64_t>(fp, 4)) : Le);
-      Geometry g = geometry(Le, Me, m, fp, fv == VAR_MULTI);
+      Geometry g = geometry_c(Le, Me, m, fp, fv == VAR_MULTI, ctr);
       if (g.inner && fv != VAR_MULTI)
         return set_err(HDCONV_EINVAL, "dim %d: m=%lld gives p=%lld > 2, which needs the multipass variant", d,
                        (long long)m, (long long)g.p);
       if (fv == VAR_MULTI && !col_size_ok(g.p)) {
-        g = geometry(Le, Me, m, next_col_size(g.p), true);
+        g = geometry_c(Le, Me, m, next_col_size(g.p), true, ctr);
       }
       dp = DimPlan{};
       dp.L = Le;
@@ -211,6 +214,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       dp.q = g.q;
       dp.D = (opt && opt->D[d] > 0) ? std::min<int64_t>(opt->D[d], g.n) : g.n;
       dp.variant = fv;
+      dp.ctr = ctr;
       if (opt) {
         dp.E_m = opt->E_m[d];
         dp.E_p = opt->E_p[d];
@@ -424,6 +428,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     a.m = (int)dp.m;
     a.q = (int)dp.q;
     a.rows_per_block = dp.rows_per_block;
+    a.ctr = dp.ctr;
     a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     a.fd = dp.fd_m;
     a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
@@ -454,6 +459,8 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k1.v0 = v0;
     k1.D = D;
     k1.S = dp.S;
+    k1.ctr = dp.ctr;
+    k1.fold = centered_folds(dp) ? 1 : 0;
     k1.fd = dp.fd_p;
     k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k1.zq = (const cpx<T>*)P->dd[d].zq;
@@ -498,6 +505,8 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.v0 = v0;
     k3.D = D;
     k3.S = dp.S;
+    k3.ctr = dp.ctr;
+    k3.fold = centered_folds(dp) ? 1 : 0;
     k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     k3.fd = dp.fd_pb;
     k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
@@ -569,6 +578,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     o.r0 = 0;
     o.D = (int)dp.q;
     o.S = dp.S;
+    o.ctr = dp.ctr;
     o.fd = dp.fd_m;
     o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     o.zqm = rtab<T>(P, d);
@@ -606,6 +616,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     o.r0 = 0;
     o.D = (int)dp.q;
     o.S = dp.S;
+    o.ctr = dp.ctr;
     o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     o.fd = dp.fd_m;
     o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
@@ -624,6 +635,10 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     for (int d = 0; d < P->dims; ++d) {
       b.L[3 - P->dims + d] = P->L[d];
       b.N[3 - P->dims + d] = P->npad[d];
+      // centered: entries (A-1)H .. (A-1)H+L-1 of the padded product are the
+      // outputs -H .. L-1-H (the arrays were padded as they are, index c at
+      // position c + H, so a product of A of them sits A H further on)
+      if (P->flags & HDCONV_PLAN_CENTERED) b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
     }
     b.pad = 0;
     {
@@ -701,9 +716,11 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
       set_err(HDCONV_EINVAL, "L[%d] = %lld out of range", d, (long long)L[d]);
       return nullptr;
     }
-    if (M[d] < (int64_t)A * (L[d] - 1) + 1) {
-      set_err(HDCONV_EINVAL, "M[%d] = %lld is below A(L-1)+1 = %lld, so the product would alias", d,
-              (long long)M[d], (long long)(A * (L[d] - 1) + 1));
+    const bool ctr = opt && (opt->flags & HDCONV_PLAN_CENTERED);
+    const int64_t Mmin = ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1;
+    if (M[d] < Mmin) {
+      set_err(HDCONV_EINVAL, "M[%d] = %lld is below %s = %lld, so the product would alias", d, (long long)M[d],
+              ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1", (long long)Mmin);
       return nullptr;
     }
   }
@@ -807,6 +824,7 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
     di.rows_per_block = dp.rows_per_block;
     di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
     di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
+    di.centered = (P->flags & HDCONV_PLAN_CENTERED) ? 1 : 0;
   }
   out->workspace_bytes = P->work_bytes;
   out->table_bytes = P->table_bytes;
@@ -930,6 +948,7 @@ static void fill_dim_info(const DimPlan& dp, hdconv_dim_info_t* di) {
   di->rows_per_block = dp.rows_per_block;
   di->tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
   di->tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
+  di->centered = dp.ctr;
 }
 
 // options that reproduce the per-dimension shapes exactly
@@ -937,6 +956,7 @@ static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims) {
   hdconv_options o;
   memset(&o, 0, sizeof(o));
   o.method = HDCONV_METHOD_HYBRID;
+  if (shp[0].centered) o.flags |= HDCONV_PLAN_CENTERED;
   for (int d = 0; d < dims; ++d) {
     o.m[d] = shp[d].m;
     o.p[d] = shp[d].p;
@@ -953,13 +973,13 @@ static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims) {
 
 // default plan plus, per dimension, that plan with the dimension replaced by
 // each of its candidates (Sec. 7: dimensions are tuned independently)
-static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, int dtype,
+static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, int dtype, int ctr,
                            std::vector<hdconv_dim_info_t>* out, std::vector<int>* varied) {
   const int tb = tbytes_of(dtype);
   std::vector<DimPlan> base(dims);
   for (int d = 0; d < dims; ++d) {
     std::string why;
-    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, lines_of_shape(L, dims, d), &base[d], &why))
+    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, lines_of_shape(L, dims, d), &base[d], &why, ctr))
       return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
   }
   auto push = [&](const std::vector<DimPlan>& s, int v) {
@@ -972,7 +992,7 @@ static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, 
   };
   push(base, -1);
   for (int d = 0; d < dims; ++d) {
-    for (const DimPlan& c : dim_candidates(L[d], M[d], A, tb, d == dims - 1)) {
+    for (const DimPlan& c : dim_candidates(L[d], M[d], A, tb, d == dims - 1, ctr)) {
       const DimPlan& b = base[d];
       if (c.variant == b.variant && c.m == b.m && c.p == b.p && c.E_m == b.E_m && c.E_p == b.E_p && c.S == b.S &&
           c.rows_per_block == b.rows_per_block)
@@ -1059,7 +1079,7 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
                        const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms) {
   std::vector<hdconv_dim_info_t> cand;
   std::vector<int> varied;
-  int rc = list_candidates(L, M, A, dims, dtype, &cand, &varied);
+  int rc = list_candidates(L, M, A, dims, dtype, (opt->flags & HDCONV_PLAN_CENTERED) ? 1 : 0, &cand, &varied);
   if (rc != HDCONV_OK) return rc;
   const int nc = (int)varied.size();
   *ncand = nc;
@@ -1135,7 +1155,7 @@ int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims
     return set_err(HDCONV_EINVAL, "invalid problem");
   std::vector<hdconv_dim_info_t> cand;
   std::vector<int> var;
-  int rc = list_candidates(L, M, A, dims, dtype, &cand, &var);
+  int rc = list_candidates(L, M, A, dims, dtype, 0, &cand, &var);
   if (rc != HDCONV_OK) return rc;
   if (count) *count = (int)var.size();
   for (int k = 0; k < (int)var.size() && k < cap; ++k) {
@@ -1165,7 +1185,7 @@ int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, 
   clear_err();
   if (!shape || !out) return set_err(HDCONV_EINVAL, "need a shape and out");
   hdconv_options o = opts_from_shape(shape, dims);
-  o.flags = HDCONV_PLAN_HOST_ONLY;
+  o.flags |= HDCONV_PLAN_HOST_ONLY;
   Plan* P = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
   if (!P) return g_err_code;
   auto lg = [](double x) { return (float)std::log2(std::max(x, 1.0)); };
@@ -1466,7 +1486,7 @@ static int tune_batch_groups(int A, int B, int dtype, int device, const hdconv_o
         if (same(u, c)) return;
       cands.push_back(c);
     };
-    for (const DimPlan& c : dim_candidates(base.L, base.M, A, tb, true)) {
+    for (const DimPlan& c : dim_candidates(base.L, base.M, A, tb, true, base.ctr)) {
       add(c);
       if (c.variant == VAR_FUSED)
         for (int f : {2, 4}) {
@@ -1558,10 +1578,13 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
     set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128");
     return nullptr;
   }
+  const int ctr = (opt && (opt->flags & HDCONV_PLAN_CENTERED)) ? 1 : 0;
   for (int64_t i = 0; i < count; ++i)
-    if (L[i] < 1 || M[i] < (int64_t)A * (L[i] - 1) + 1) {
-      set_err(HDCONV_EINVAL, "convolution %lld: need L >= 1 and M >= A(L-1)+1 (L=%lld, M=%lld)", (long long)i,
-              (long long)L[i], (long long)M[i]);
+    if (L[i] < 1 || L[i] > (int64_t(1) << 31) ||
+        M[i] < (ctr ? centered_min_padding(L[i], A) : (int64_t)A * (L[i] - 1) + 1)) {
+      set_err(HDCONV_EINVAL, "convolution %lld: need L >= 1 and M >= %s (L=%lld, M=%lld)", (long long)i,
+              ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1", (long long)L[i],
+              (long long)M[i]);
       return nullptr;
     }
   int ndev = 0;
@@ -1589,7 +1612,7 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
   for (int64_t i = 0; i < count; ++i) {
     DimPlan dp;
     std::string why;
-    if (!choose_dim(L[i], M[i], A, tb, true, count, &dp, &why)) {
+    if (!choose_dim(L[i], M[i], A, tb, true, count, &dp, &why, ctr)) {
       set_err(HDCONV_EUNSUPPORTED, "convolution %lld (L=%lld): %s", (long long)i, (long long)L[i], why.c_str());
       free_batch(Bt);
       return nullptr;
@@ -1699,6 +1722,7 @@ int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* cou
       di.rows_per_block = dp.rows_per_block;
       di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
       di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
+      di.centered = dp.ctr;
     }
     if (counts) counts[g] = (int64_t)Bt->members[g].size();
   }

@@ -10,6 +10,20 @@
 //  * inner form (Sec. 6.1, q = n p): n residues v of size p*m; the sum over t
 //    becomes p-point DFTs of zeta_q^{vt} f_{tm+s}, then zeta_{qm}^{(un+v)s}
 //    and an m-point FFT per u.
+//  * centered dimensions (ctr = 1; the paper's centered case, eq. centDFT,
+//    and its inner form): the array of L entries holds the signed indices
+//    c = -H .. L-1-H (H = floor(L/2)) at positions c + H, and the transform
+//    runs over c itself.  The p blocks then cover c in
+//    [-tneg m, (p - tneg) m) with tneg = ceil(H/m); block t (0-based) holds
+//    c = (t - tneg) m + s at array position t m + s - sh, sh = tneg m - H,
+//    and the twiddle exponents use the signed c (r c mod q m).  In the inner
+//    form the p-point column DFT takes block t = c div m at position t mod p,
+//    with twiddle zeta_q^{v t}; when p is below the span (fold = 1) the
+//    negative block t - p shares position t with block t (the paper's
+//    p/2-term sum of the centered inner form), and the inverse hands the
+//    value at position t to both output blocks, each with its own twiddle.
+//    The inverse stores output c at position c + H, so the result is the
+//    centered convolution.
 #pragma once
 #include "hd_common.hpp"
 #include "hd_fft.hpp"
@@ -49,6 +63,7 @@ struct FusedArgs {
   int64_t L;
   int m, q;
   int rows_per_block;
+  int ctr;  // 1: centered rows (H = floor(L/2) of each row's own L)
   T scale;  // 1/(q m)
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -67,6 +82,8 @@ struct ColFwdArgs {
   int64_t nrows;
   int64_t L;
   int m, p, q, v0, D, S;
+  int ctr;   // 1: centered rows
+  int fold;  // 1: two blocks per column position (centered, p below the span)
   FftDesc fd;  // p points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   const cpx<T>* zq;  // zeta_q^k, k < q
@@ -101,6 +118,8 @@ struct ColBwdArgs {
   int64_t nrows;
   int64_t L;
   int m, p, q, v0, D, S;
+  int ctr;   // 1: centered rows
+  int fold;  // 1: two blocks per column position (centered, p below the span)
   T scale;
   FftDesc fd;  // p points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -117,6 +136,7 @@ struct OuterFwdArgs {
   int64_t nb, in_bstride, R;
   int64_t L;
   int m, q, r0, D, S;
+  int ctr;  // 1: centered dimension
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   RootTable<T> zqm;
@@ -131,6 +151,7 @@ struct OuterBwdArgs {
   int64_t nb, out_bstride, R;
   int64_t L;
   int m, q, r0, D, S;
+  int ctr;  // 1: centered dimension
   T scale;
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -144,6 +165,7 @@ struct BoxCopyArgs {
   const cpx<T>* src;
   cpx<T>* dst;
   int64_t L[3], N[3];  // leading unused extents are 1
+  int64_t off[3];      // truncation: dst[i] = src[i + off] (0, or the centered window start)
   int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
 };
 

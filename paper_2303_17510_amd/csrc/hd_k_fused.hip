@@ -16,7 +16,10 @@ namespace hd {
 // and finally out_j = h_j / (qm).  With P = 2 the backward step is the
 // corrected form of Algorithm 6 (the second half carries zeta_{qm}^{-rj},
 // j = m+s, as eq. invStan requires).  The A forward transforms of a residue
-// run together (shared twiddles and barriers).
+// run together (shared twiddles and barriers).  Centered rows (a.ctr, the
+// paper's centered case with p = 2, eq. forCent/wDef): block t holds the
+// signed indices c = (t - tneg) m + s at array position t m + s - sh, and the
+// twiddles are zeta_{qm}^{r c}; the output c goes back to position c + H.
 template <typename T, int E, int P, int A>
 __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   // Inputs small enough stay in registers across the residues; larger ones
@@ -32,6 +35,11 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   const RowTask<T>* tk = (a.tasks && valid) ? a.tasks + row : nullptr;
   const uint32_t L = valid ? (uint32_t)(tk ? tk->L : a.L) : 0u;
   const uint32_t qm = (uint32_t)a.q * (uint32_t)m;
+  // centered rows: tneg blocks left of index 0, block position j holds array
+  // position j - sh (both 0 for an ordinary row)
+  const uint32_t H = a.ctr ? (L >> 1) : 0u;
+  const uint32_t tneg = (H + (uint32_t)m - 1) / (uint32_t)m;
+  const uint32_t sh = tneg * (uint32_t)m - H;
   const cpx<T>* src[A];
 #pragma unroll
   for (int ai = 0; ai < A; ++ai) src[ai] = tk ? tk->in[ai] : a.in[ai] + row * a.in_stride;
@@ -41,8 +49,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
 
   // the row's inputs (zero beyond L)
   auto load = [&](int ai, int t, int e) -> cpx<T> {
-    const uint32_t j = (uint32_t)(t * m + g + G * e);
-    return j < L ? ld_at(src[ai], j) : czero<T>();
+    const uint32_t i = (uint32_t)(t * m + g + G * e) - sh;  // wraps above L when j < sh
+    return i < L ? ld_at(src[ai], i) : czero<T>();
   };
   cpx<T> x[kKeep ? A : 1][kKeep ? P : 1][kKeep ? E : 1];
   if constexpr (kKeep) {
@@ -64,6 +72,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   for (int r = 0; r < a.q; ++r) {
     // exponents of zeta_{qm}^{r j} for j = t m + g + G e advance by r G per e
     const uint32_t st = (uint32_t)(((uint64_t)r * G) % qm);
+    // exponent r c = r j - r tneg m, kept in [0, qm)
+    const uint64_t rneg = qm - (uint32_t)(((uint64_t)r * (tneg * (uint32_t)m)) % qm);
     cpx<T> w[A][E];
 #pragma unroll
     for (int ai = 0; ai < A; ++ai)
@@ -71,7 +81,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
+      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g) + rneg) % qm);
       a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) {
 #pragma unroll
         for (int ai = 0; ai < A; ++ai) {
@@ -94,7 +104,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g)) % qm);
+      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g) + rneg) % qm);
       a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
     }
   }
@@ -104,8 +114,8 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     for (int t = 0; t < P; ++t)
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const uint32_t j = (uint32_t)(t * m + g + G * e);
-        if (j < L) st_at(dst, j, cscale(acc[t][e], a.scale));
+        const uint32_t i = (uint32_t)(t * m + g + G * e) - sh;
+        if (i < L) st_at(dst, i, cscale(acc[t][e], a.scale));
       }
   }
 }

@@ -4,12 +4,26 @@
 namespace hd {
 
 // ---------------------------------------------------------------------------
+// Block index of column position tau (0 <= tau < p): tau itself, or for a
+// centered row with tneg blocks left of index 0 the signed block tau - p once
+// tau >= p - tneg (the p-point DFT is periodic in the block index).
+__device__ __forceinline__ int signed_block(int tau, int p, int tneg) { return tau < p - tneg ? tau : tau - p; }
+// zeta_q^{v t} index for a signed block t (|v t| < q)
+__device__ __forceinline__ int zq_index(int v, int t, int q) {
+  const int k = (v * t) % q;
+  return k < 0 ? k + q : k;
+}
+
 // Inner form, pass 1 (Sec. 6.1, forward): columns s of the p x m view.  For
 // each residue v the column is scaled by zeta_q^{vt} and p-point transformed;
-// residues are taken two at a time (shared twiddles and barriers).
-template <typename T, int E, int NT>
-__device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const cpx<T> (&x)[E], int dv0, int g,
-                                                  int s, int64_t row, int ai, const TwLds<T>& tw,
+// residues are taken two at a time (shared twiddles and barriers).  Centered
+// rows (the paper's centered inner form) use the signed block index t; with
+// FOLD, position tau carries block tau (x) and the negative block tau - p
+// (x1), each with its own twiddle.
+template <typename T, int E, int NT, bool FOLD>
+__device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const cpx<T> (&x)[E],
+                                                  const cpx<T> (&x1)[FOLD ? E : 1], int dv0, int g, int s,
+                                                  int64_t row, int ai, int tneg, const TwLds<T>& tw,
                                                   const Xchg<T>& xb) {
   const int G = a.fd.G, m = a.m, p = a.p, q = a.q;
   cpx<T> y[NT][E];
@@ -17,7 +31,14 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
   for (int n = 0; n < NT; ++n) {
     const int v = a.v0 + dv0 + n;
 #pragma unroll
-    for (int e = 0; e < E; ++e) y[n][e] = cmul(x[e], a.zq[(v * (g + G * e)) % q]);
+    for (int e = 0; e < E; ++e) {
+      const int tau = g + G * e;
+      if constexpr (FOLD) {
+        y[n][e] = cmul(x[e], a.zq[(v * tau) % q]) + cmul(x1[FOLD ? e : 0], a.zq[zq_index(v, tau - p, q)]);
+      } else {
+        y[n][e] = cmul(x[e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
+      }
+    }
   }
   gfft_any<T, E, +1, NT, (sizeof(T) == 4 ? kCtCols : 0u)>(y, g, a.fd, tw, xb);
 #pragma unroll
@@ -30,7 +51,7 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
 
 // Grid x enumerates (row, column tile) pairs, column tiles fastest, so the
 // row count is not bound by the grid's y limit.
-template <typename T, int E>
+template <typename T, int E, bool FOLD>
 __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
   const int S = a.S, G = a.fd.G, m = a.m;
   const int c = threadIdx.x % S;
@@ -41,15 +62,24 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
   const int ai = blockIdx.z;
   const cpx<T>* src = a.tasks ? a.tasks[row].in[ai] : a.in[ai] + row * a.in_stride;
   const int64_t L = a.tasks ? a.tasks[row].L : a.L;
+  const int64_t H = a.ctr ? L / 2 : 0;  // array position of index 0
+  const int tneg = (int)((H + m - 1) / m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, a.p * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
 
-  cpx<T> x[E];
+  cpx<T> x[E], x1[FOLD ? E : 1];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int64_t j = (int64_t)(g + G * e) * m + s;
-    x[e] = (j < L) ? src[j] : czero<T>();
+    const int tau = g + G * e;
+    if constexpr (FOLD) {
+      const int64_t i0 = (int64_t)tau * m + s + H, i1 = (int64_t)(tau - a.p) * m + s + H;
+      x[e] = i0 < L ? src[i0] : czero<T>();
+      x1[FOLD ? e : 0] = (i1 >= 0 && i1 < L) ? src[i1] : czero<T>();
+    } else {
+      const int64_t i = (int64_t)signed_block(tau, a.p, tneg) * m + s + H;
+      x[e] = (i >= 0 && i < L) ? src[i] : czero<T>();
+    }
   }
   __syncthreads();
   // FP32 transforms one residue at a time (fewer registers, twice the
@@ -57,8 +87,8 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
   constexpr int NT = sizeof(T) == 4 ? 1 : 2;
   int dv = 0;
   if constexpr (NT == 2)
-    for (; dv + 2 <= a.D; dv += 2) cols_fwd_residues<T, E, 2>(a, x, dv, g, s, row, ai, tw, xb);
-  for (; dv < a.D; ++dv) cols_fwd_residues<T, E, 1>(a, x, dv, g, s, row, ai, tw, xb);
+    for (; dv + 2 <= a.D; dv += 2) cols_fwd_residues<T, E, 2, FOLD>(a, x, x1, dv, g, s, row, ai, tneg, tw, xb);
+  for (; dv < a.D; ++dv) cols_fwd_residues<T, E, 1, FOLD>(a, x, x1, dv, g, s, row, ai, tneg, tw, xb);
 }
 
 // Inner form, pass 2: m-point convolution rows.  The A rows are loaded
@@ -115,10 +145,12 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
 
 
 
-// Inner form, pass 3 (eq. invInner): columns back to the p x m view.
-template <typename T, int E, int NT>
-__device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T> (&acc)[E], int dv0, int g, int s,
-                                                  int64_t row, const TwLds<T>& tw, const Xchg<T>& xb) {
+// Inner form, pass 3 (eq. invInner): columns back to the p x m view.  With
+// FOLD the value at position tau also feeds the negative block tau - p (acc1).
+template <typename T, int E, int NT, bool FOLD>
+__device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T> (&acc)[E],
+                                                  cpx<T> (&acc1)[FOLD ? E : 1], int dv0, int g, int s,
+                                                  int64_t row, int tneg, const TwLds<T>& tw, const Xchg<T>& xb) {
   const int G = a.fd.G, m = a.m, p = a.p, q = a.q;
   cpx<T> y[NT][E];
 #pragma unroll
@@ -132,11 +164,19 @@ __device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T>
   for (int n = 0; n < NT; ++n) {
     const int v = a.v0 + dv0 + n;
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = acc[e] + cmulc(y[n][e], a.zq[(v * (g + G * e)) % q]);
+    for (int e = 0; e < E; ++e) {
+      const int tau = g + G * e;
+      if constexpr (FOLD) {
+        acc[e] = acc[e] + cmulc(y[n][e], a.zq[(v * tau) % q]);
+        acc1[FOLD ? e : 0] = acc1[FOLD ? e : 0] + cmulc(y[n][e], a.zq[zq_index(v, tau - p, q)]);
+      } else {
+        acc[e] = acc[e] + cmulc(y[n][e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
+      }
+    }
   }
 }
 
-template <typename T, int E>
+template <typename T, int E, bool FOLD>
 __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
   const int S = a.S, G = a.fd.G, m = a.m;
   const int c = threadIdx.x % S;
@@ -149,19 +189,31 @@ __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(a.p, S, 2));
   __syncthreads();
 
-  cpx<T> acc[E];
+  const int64_t L = a.tasks ? a.tasks[row].L : a.L;
+  const int64_t H = a.ctr ? L / 2 : 0;  // array position of index 0
+  const int tneg = (int)((H + m - 1) / m);
+  cpx<T> acc[E], acc1[FOLD ? E : 1];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = czero<T>();
+  if constexpr (FOLD)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc1[FOLD ? e : 0] = czero<T>();
   int dv = 0;
-  for (; dv + 2 <= a.D; dv += 2) cols_bwd_residues<T, E, 2>(a, acc, dv, g, s, row, tw, xb);
-  if (dv < a.D) cols_bwd_residues<T, E, 1>(a, acc, dv, g, s, row, tw, xb);
+  for (; dv + 2 <= a.D; dv += 2) cols_bwd_residues<T, E, 2, FOLD>(a, acc, acc1, dv, g, s, row, tneg, tw, xb);
+  if (dv < a.D) cols_bwd_residues<T, E, 1, FOLD>(a, acc, acc1, dv, g, s, row, tneg, tw, xb);
   cpx<T>* dst = a.tasks ? a.tasks[row].out : a.out + row * a.out_stride;
-  const int64_t L = a.tasks ? a.tasks[row].L : a.L;
   double* acc64 = a.acc ? a.acc + 2 * row * a.out_stride : nullptr;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int64_t j = (int64_t)(g + G * e) * m + s;
-    if (j < L) acc_store(dst, acc64, a.acc_mode, j, acc[e], a.scale);
+    const int tau = g + G * e;
+    if constexpr (FOLD) {
+      const int64_t i0 = (int64_t)tau * m + s + H, i1 = (int64_t)(tau - a.p) * m + s + H;
+      if (i0 < L) acc_store(dst, acc64, a.acc_mode, i0, acc[e], a.scale);
+      if (i1 >= 0 && i1 < L) acc_store(dst, acc64, a.acc_mode, i1, acc1[FOLD ? e : 0], a.scale);
+    } else {
+      const int64_t i = (int64_t)signed_block(tau, a.p, tneg) * m + s + H;
+      if (i >= 0 && i < L) acc_store(dst, acc64, a.acc_mode, i, acc[e], a.scale);
+    }
   }
 }
 
@@ -173,8 +225,10 @@ hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s) 
     return HD_BAD;
   dim3 grid((unsigned)((a.m / a.S) * a.nrows), 1, A), block(nt);
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
-#define C1(EE) \
-  if (E == EE) return go(k_cols_fwd<T, EE>, grid, block, lds, s, a);
+#define C1(EE)                                                                   \
+  if (E == EE)                                                                   \
+    return a.fold ? go(k_cols_fwd<T, EE, true>, grid, block, lds, s, a)         \
+                  : go(k_cols_fwd<T, EE, false>, grid, block, lds, s, a);
   C1(1) C1(2) C1(4) C1(8) C1(12) C1(16)
 #undef C1
   return HD_BAD;
@@ -201,8 +255,10 @@ hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s) {
     return HD_BAD;
   dim3 grid((unsigned)((a.m / a.S) * a.nrows)), block(nt);
   const size_t lds = lds_cols(a.p, a.S, tw_words(a.fd), sizeof(T));
-#define C1(EE) \
-  if (E == EE) return go(k_cols_bwd<T, EE>, grid, block, lds, s, a);
+#define C1(EE)                                                                   \
+  if (E == EE)                                                                   \
+    return a.fold ? go(k_cols_bwd<T, EE, true>, grid, block, lds, s, a)         \
+                  : go(k_cols_bwd<T, EE, false>, grid, block, lds, s, a);
   C1(1) C1(2) C1(4) C1(8) C1(12) C1(16)
 #undef C1
   return HD_BAD;

@@ -5,6 +5,18 @@
 namespace hd {
 
 // ---------------------------------------------------------------------------
+// Position of index 0 and block shift of a centered outer dimension (the
+// transform then runs over the signed indices c = (t - tneg) m + s, stored at
+// array position t m + s - sh); all zero for an ordinary dimension.
+struct CtrShift {
+  int64_t tneg, sh;
+};
+__device__ __forceinline__ CtrShift ctr_shift(int ctr, int64_t L, int m) {
+  const int64_t H = ctr ? L / 2 : 0;
+  const int64_t tneg = (H + m - 1) / m;
+  return CtrShift{tneg, tneg * m - H};
+}
+
 // Outer dimension, direct form, forward: S adjacent columns per workgroup.
 template <typename T, int E, int P>
 __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
@@ -18,6 +30,7 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
   const cpx<T>* src = a.in[ai] + b * a.in_bstride + col;
+  const CtrShift cs = ctr_shift(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
@@ -27,18 +40,20 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
   for (int t = 0; t < P; ++t)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t j = (int64_t)t * m + g + G * e;
-      x[t][e] = (valid && j < a.L) ? src[j * R] : czero<T>();
+      const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
+      x[t][e] = (valid && i >= 0 && i < a.L) ? src[i * R] : czero<T>();
     }
   __syncthreads();
   for (int dr = 0; dr < a.D; ++dr) {
     const int64_t r = a.r0 + dr;
+    // exponent r c = r j - r tneg m, kept in [0, qm)
+    const int64_t rneg = qm - (r * cs.tneg * m) % qm;
     cpx<T> w[1][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)((r * (t * m + g)) % qm);
+      const uint32_t ex0 = (uint32_t)((r * (t * m + g) + rneg) % qm);
       const uint32_t st = (uint32_t)((r * G) % qm);
       a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
     }
@@ -62,6 +77,7 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
   const int64_t b = blockIdx.y;
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
+  const CtrShift cs = ctr_shift(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
@@ -79,9 +95,10 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) y[0][e] = valid ? src[(int64_t)(g + G * e) * R] : czero<T>();
     gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
+    const int64_t rneg = qm - (r * cs.tneg * m) % qm;
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)((r * (t * m + g)) % qm);
+      const uint32_t ex0 = (uint32_t)((r * (t * m + g) + rneg) % qm);
       const uint32_t st = (uint32_t)((r * G) % qm);
       a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
     }
@@ -93,8 +110,8 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
   for (int t = 0; t < P; ++t)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t j = (int64_t)t * m + g + G * e;
-      if (j < a.L) acc_store(dst, acc64, a.acc_mode, j * R, acc[t][e], a.scale);
+      const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
+      if (i >= 0 && i < a.L) acc_store(dst, acc64, a.acc_mode, i * R, acc[t][e], a.scale);
     }
 }
 
@@ -104,15 +121,17 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
   // one destination row (i0, i1) per blockIdx.y step; lanes run along i2
   const int64_t* D = a.pad ? a.N : a.L;
   const int64_t* Sx = a.pad ? a.L : a.N;
+  // source offsets (truncation only: the window of the padded result)
+  const int64_t o0 = a.pad ? 0 : a.off[0], o1 = a.pad ? 0 : a.off[1], o2 = a.pad ? 0 : a.off[2];
   const int64_t rows = D[0] * D[1];
   for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
     const int64_t i1 = row % D[1], i0 = row / D[1];
-    const bool in_src = i0 < Sx[0] && i1 < Sx[1];
-    const cpx<T>* src = a.src + (i0 * Sx[1] + i1) * Sx[2];
+    const bool in_src = i0 + o0 < Sx[0] && i1 + o1 < Sx[1];
+    const cpx<T>* src = a.src + ((i0 + o0) * Sx[1] + i1 + o1) * Sx[2] + o2;
     cpx<T>* dst = a.dst + row * D[2];
     for (int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i2 < D[2];
          i2 += (int64_t)gridDim.x * blockDim.x)
-      dst[i2] = (in_src && i2 < Sx[2]) ? src[i2] : czero<T>();
+      dst[i2] = (in_src && i2 + o2 < Sx[2]) ? src[i2] : czero<T>();
   }
 }
 

@@ -28,6 +28,40 @@ Geometry geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inn
   return g;
 }
 
+int64_t centered_blocks(int64_t L, int64_t m) {
+  const int64_t H = L / 2;
+  return cdiv(H, m) + cdiv(L - H, m);
+}
+
+int64_t centered_pos_blocks(int64_t L, int64_t m) { return cdiv(L - L / 2, m); }
+
+bool centered_folds(const DimPlan& dp) {
+  return dp.ctr && dp.variant == VAR_MULTI && dp.p < centered_blocks(dp.L, dp.m);
+}
+
+Geometry geometry_c(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inner, int ctr) {
+  if (!ctr) return geometry(L, M, m, p_min, force_inner);
+  Geometry g{};
+  g.m = m;
+  const int64_t pd = std::max(p_min, centered_blocks(L, m));
+  if (pd <= 2 && !force_inner) {
+    g.p = pd;
+    g.n = g.q = cdiv(M, m);
+    g.inner = false;
+  } else {
+    g.p = std::max(p_min, centered_pos_blocks(L, m));
+    g.n = cdiv(M, g.p * m);
+    g.q = g.n * g.p;
+    g.inner = true;
+  }
+  return g;
+}
+
+int64_t centered_min_padding(int64_t L, int A) {
+  const int64_t H = L / 2, P = L - 1 - H;  // most negative and most positive index
+  return std::max<int64_t>((int64_t)A * P + H, P + (int64_t)A * H) + 1;
+}
+
 bool fft_size_ok(int64_t N) {
   if (N < 1) return false;
   if ((N & (N - 1)) == 0) return true;
@@ -168,9 +202,14 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
     if (why) *why = s;
     return false;
   };
-  if (dp->m < 1 || dp->p < 1 || dp->q < dp->p || dp->q * dp->m < dp->M)
-    return fail("invalid geometry: need q >= p and q m >= M");
-  if (dp->p * dp->m < dp->L) return fail("invalid geometry: need p m >= L");
+  if (dp->m < 1 || dp->p < 1 || dp->q * dp->m < dp->M) return fail("invalid geometry: need q m >= M");
+  // (a centered dimension may have q < p: p = 2 whenever m >= L/2)
+  if (!dp->ctr && dp->q < dp->p) return fail("invalid geometry: need q >= p");
+  if (!dp->ctr && dp->p * dp->m < dp->L) return fail("invalid geometry: need p m >= L");
+  if (dp->ctr && dp->variant != VAR_MULTI && dp->p < centered_blocks(dp->L, dp->m))
+    return fail("invalid geometry: a centered direct form needs p >= ceil(H/m) + ceil((L-H)/m)");
+  if (dp->ctr && dp->variant == VAR_MULTI && dp->p < centered_pos_blocks(dp->L, dp->m))
+    return fail("invalid geometry: a centered inner form needs p >= ceil((L-H)/m)");
   // residue twiddle exponents are reduced mod q m in 32-bit arithmetic
   if (dp->q * dp->m >= (int64_t(1) << 31)) return fail("q m must stay below 2^31");
   if (!fft_size_ok(dp->m)) return fail("m must be 2^a or 3*2^a (a >= 3)");
@@ -259,8 +298,8 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
   }
 }
 
-static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min, int variant) {
-  Geometry g = geometry(L, M, m, p_min, variant == VAR_MULTI);
+static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min, int variant, int ctr = 0) {
+  Geometry g = geometry_c(L, M, m, p_min, variant == VAR_MULTI, ctr);
   if ((variant == VAR_FUSED || variant == VAR_OUTER) && g.inner) return false;
   dp->L = L;
   dp->M = M;
@@ -270,6 +309,7 @@ static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min
   dp->q = g.q;
   dp->D = g.n;
   dp->variant = variant;
+  dp->ctr = ctr;
   dp->E_m = dp->E_p = dp->S = dp->rows_per_block = 0;
   return true;
 }
@@ -280,8 +320,92 @@ static int64_t pow2_ceil(int64_t x) {
   return r;
 }
 
+// Centered dimensions: the least padding q m over the supported shapes.
+// Whole rows (p = 2 once m >= L/2): a single convolution takes one transform
+// of m >= M (q = 1) up to 4096 points; many rows the least q m with m up to
+// 4096, powers of two first, then the smallest such m (the transform work
+// q m log m falls with m at equal q m).  Beyond, the inner form with the
+// least q m over every column size p (a factor 3 in p reaches p m = 3L/2,
+// the centered padding, with one residue block), then m nearest 4096.  Outer dimensions: the least q m over m up to 8192
+// with p <= 2, powers of two first, then the larger m.
+static bool choose_dim_centered(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines,
+                                DimPlan* dp, std::string* why) {
+  std::string w;
+  std::vector<int64_t> sizes;
+  for (int64_t s = 8; s <= kMaxRowM; s <<= 1) {
+    sizes.push_back(s);
+    if (3 * s <= kMaxRowM) sizes.push_back(3 * s);
+  }
+  std::sort(sizes.begin(), sizes.end());
+  auto pow2 = [](int64_t m) { return (m & (m - 1)) == 0; };
+  // better(a, b): less padding, then a power of two, then the preferred size
+  auto pick = [&](int variant, int64_t mmax, bool prefer_large) {
+    DimPlan best;
+    bool found = false;
+    for (int64_t m : sizes) {
+      if (m > mmax) break;
+      DimPlan c;
+      if (!set_geom(&c, L, M, m, 0, variant, 1) || !finish_dim(&c, A, tbytes, &w)) continue;
+      bool take = !found;
+      if (found) {
+        const int64_t a = c.q * c.m, b = best.q * best.m;
+        if (a != b) take = a < b;
+        else if (pow2(c.m) != pow2(best.m)) take = pow2(c.m);
+        else take = prefer_large ? c.m > best.m : c.m < best.m;
+      }
+      if (take) {
+        best = c;
+        found = true;
+      }
+    }
+    if (found) *dp = best;
+    return found;
+  };
+  if (contiguous) {
+    if (lines <= 1) {
+      const int64_t m = std::max<int64_t>(8, next_fft_size(M));
+      if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_FUSED, 1) && finish_dim(dp, A, tbytes, &w)) return true;
+    }
+    if (pick(VAR_FUSED, 4096, false)) return true;
+    DimPlan best;
+    bool found = false;
+    double best_key = 0;
+    for (int64_t mm : {1024, 2048, 4096, 8192}) {
+      if (mm > kMaxRowM) continue;
+      // every column size from the folded span (negative blocks on the
+      // positive ones) up to the full span or one residue block (n = 1,
+      // p m >= M): q m = ceil(M/(p m)) p m is not monotone in p
+      const int64_t pmin = centered_pos_blocks(L, mm);
+      const int64_t pmax = std::max(next_col_size(centered_blocks(L, mm)), next_col_size(cdiv(M, mm)));
+      for (int64_t p = next_col_size(pmin); p <= pmax; p = next_col_size(p + 1)) {
+        if (p > kMaxColP) break;
+        DimPlan c;
+        if (!set_geom(&c, L, M, mm, p, VAR_MULTI, 1)) continue;
+        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 512)) ? 16 : 8;
+        if (!finish_dim(&c, A, tbytes, &w)) continue;
+        const double key = (double)(c.q * c.m) * 1e3 + std::fabs(std::log2((double)mm / 4096.0));
+        if (!found || key < best_key) {
+          best = c;
+          best_key = key;
+          found = true;
+        }
+      }
+    }
+    if (found) {
+      *dp = best;
+      return true;
+    }
+    if (why) *why = "no supported plan for this centered length" + (w.empty() ? std::string() : ": " + w);
+    return false;
+  }
+  if (pick(VAR_OUTER, kMaxFusedM, true)) return true;
+  if (why) *why = "no supported plan for this centered outer length: " + w;
+  return false;
+}
+
 bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
-                std::string* why) {
+                std::string* why, int ctr) {
+  if (ctr) return choose_dim_centered(L, M, A, tbytes, contiguous, lines, dp, why);
   std::string w;
   if (contiguous) {
     // Whole rows in one workgroup.  A single convolution is latency-bound:
@@ -359,7 +483,7 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
   return false;
 }
 
-std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous) {
+std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int ctr) {
   std::vector<DimPlan> out;
   std::vector<int64_t> sizes;
   for (int64_t s = 8; s <= kMaxRowM; s <<= 1) {
@@ -370,7 +494,7 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
   auto add = [&](int64_t m, int64_t pmin, int variant, int E_m) {
     DimPlan dp;
     std::string w;
-    if (!set_geom(&dp, L, M, m, pmin, variant)) return;
+    if (!set_geom(&dp, L, M, m, pmin, variant, ctr)) return;
     dp.E_m = E_m;
     if (finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
   };
@@ -382,24 +506,33 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
     std::vector<int> Es;
     if (m % 3 == 0) Es = {12};
     else Es = {4, 8, 16};
+    // blocks of m points the inputs span
+    const int64_t pneed = ctr ? centered_blocks(L, m) : cdiv(L, m);
     if (contiguous) {
       // whole rows in one workgroup (p <= 2)
-      if (cdiv(L, m) <= 2)
+      if (pneed <= 2)
         for (int E : Es) add(m, 0, VAR_FUSED, E);
       // inner form: p rounded up to a supported size, and to a power of two
-      if (m >= 16 && m >= L / kMaxColP) {
-        const int64_t p0 = cdiv(L, m);
+      // (centered: from the folded span up to the full span or n = 1)
+      const int64_t pin = ctr ? centered_pos_blocks(L, m) : pneed;
+      if (m >= 16 && pin <= kMaxColP) {
+        const int64_t p0 = pin;
         int64_t p2 = 1;
         while (p2 < p0) p2 <<= 1;
         std::vector<int64_t> ps = {next_col_size(p0)};
         if (p2 != ps[0]) ps.push_back(p2);
+        if (ctr)
+          for (int64_t p = next_col_size(p0 + 1);
+               p <= std::max(next_col_size(pneed), next_col_size(cdiv(M, m))) && p <= kMaxColP;
+               p = next_col_size(p + 1))
+            if (std::find(ps.begin(), ps.end(), p) == ps.end()) ps.push_back(p);
         for (int64_t p : ps) {
           if (p > kMaxColP) continue;
           for (int E : Es) add(m, p, VAR_MULTI, E);
         }
       }
     } else {
-      if (cdiv(L, m) <= 2)
+      if (pneed <= 2)
         for (int E : Es) add(m, 0, VAR_OUTER, E);
     }
   }

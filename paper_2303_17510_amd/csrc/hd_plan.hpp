@@ -37,7 +37,24 @@ struct DimPlan {
   int S = 0;                  // columns per workgroup (column / outer kernels)
   int rows_per_block = 0;     // rows per workgroup (fused / row kernels)
   int tw_pref = 0;            // twiddles: 0 choose, 1 two-level table, 2 per-stage tables
+  int ctr = 0;                // 1: centered convolution (indices -H .. L-1-H, H = floor(L/2))
 };
+
+// Blocks of m points a centered dimension spans (the centered transform of
+// the paper's one-dimensional centered case): the signed indices -H .. L-1-H
+// lie in blocks -ceil(H/m) .. ceil((L-H)/m)-1, so p is at least
+// ceil(H/m) + ceil((L-H)/m) (2 whenever m >= L/2 and L >= 2).
+int64_t centered_blocks(int64_t L, int64_t m);
+// Blocks of the non-negative indices 0 .. L-1-H: ceil((L-H)/m).
+int64_t centered_pos_blocks(int64_t L, int64_t m);
+// True when an inner-form centered dimension folds two blocks onto one
+// column position (p below the full span centered_blocks(L, m)).
+bool centered_folds(const struct DimPlan& dp);
+
+// Least M for which a centered product of A inputs is not aliased: the
+// index sums of A inputs span -A H .. A(L-1-H), and an output index c in
+// -H .. L-1-H must not meet another sum congruent to it modulo q m.
+int64_t centered_min_padding(int64_t L, int A);
 
 // Paper's geometry rules for a given m (Algorithm 1, Sec. 2.1, Sec. 6.1):
 //   p = ceil(L/m) (or the caller's larger p_min), then
@@ -48,6 +65,15 @@ struct Geometry {
   bool inner;
 };
 Geometry geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inner);
+
+// The same rules for a centered dimension (ctr = 1; the paper's centered case
+// and its inner form): the direct form spans p = ceil(H/m) + ceil((L-H)/m)
+// blocks (p <= 2, q = n = ceil(M/m)); the inner form folds the blocks of
+// negative indices onto the column positions of the positive ones (the
+// paper's padded DFT of p/2 terms in the centered inner form), so p only has
+// to reach ceil((L-H)/m), and n = ceil(M/(p m)), q = n p.  ctr = 0 is
+// geometry().
+Geometry geometry_c(int64_t L, int64_t M, int64_t m, int64_t p_min, bool force_inner, int ctr);
 
 bool fft_size_ok(int64_t N);            // 2^a, or 3 * 2^a with a >= 3
 int64_t next_fft_size(int64_t n);       // smallest size >= n accepted by fft_size_ok
@@ -67,11 +93,12 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why);
 // innermost dimension (rows), others are outer dimensions; `lines` is the
 // number of independent lines one launch of this dimension processes (1 for
 // a single 1D convolution: latency first; many: throughput first).
+// `ctr` selects the centered convolution.
 bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
-                std::string* why);
+                std::string* why, int ctr = 0);
 
 // Candidates for the autotuner: every supported (m, variant) of a dimension.
-std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous);
+std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int ctr = 0);
 
 // FP64 two-level table of zeta_N for a descriptor (interleaved re, im):
 // lo[j] = zeta_N^j for j < 2^kb, then hi[h] = zeta_N^{h 2^kb} for h < ceil(N / 2^kb).

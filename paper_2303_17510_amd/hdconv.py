@@ -49,30 +49,43 @@ def geometry(L: int, M: int, m: int, p_min: int = 0, force_inner: bool = False) 
             "variant": _L.VARIANT_NAMES[out.variant]}
 
 
+def centered_min_padding(L: int, A: int = 2) -> int:
+    """Least M of a centered dimension (indices -H .. L-1-H, H = L // 2):
+    the A-fold index sums span -A H .. A(L-1-H), and no output index may meet
+    another sum congruent to it modulo the padded length."""
+    H = L // 2
+    P = L - 1 - H
+    return max(A * P + H, P + A * H) + 1
+
+
 class Plan:
     """A planned convolution of ``A`` inputs of shape ``L`` padded to ``M``.
 
     ``method``: "hybrid" (default) or "explicit" (materialised zero padding).
     ``m``, ``p``, ``D``, ``variant`` force per-dimension choices (None: the
     planner decides).  ``host_only`` plans geometry without device memory.
+    ``centered``: arrays hold the indices -L//2 .. L-1-L//2 (index 0 at
+    position L//2) and the result is the centered convolution; ``M`` then
+    defaults to the centered minimum (3L/2 for A = 2, even L).
     """
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
-                 db_path: str | None = None):
+                 db_path: str | None = None, centered: bool = False):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
-            M = tuple(A * l for l in L)
+            M = tuple(centered_min_padding(l, A) if centered else A * l for l in L)
         M = (int(M),) if isinstance(M, int) else tuple(int(v) for v in M)
         self.L, self.M, self.A, self.B, self.dims = L, M, A, B, dims
         self.dtype_code = dtype_code(dtype)
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.method = _METHODS[method]
-        opt.flags = _L.PLAN_HOST_ONLY if host_only else 0
+        opt.flags = (_L.PLAN_HOST_ONLY if host_only else 0) | (_L.PLAN_CENTERED if centered else 0)
+        self.centered = bool(centered)
         if dims > 3 or len(M) != dims:
             raise ValueError("L and M need 1 to 3 matching dimensions")
         for d, v in enumerate(_tup(m, dims)):
@@ -117,7 +130,8 @@ class Plan:
             di = out.dim[d]
             dims.append({"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
                          "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p,
-                         "S": di.S, "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p})
+                         "S": di.S, "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p,
+                         "centered": bool(di.centered)})
         return {"dims": dims, "A": out.A, "B": out.B, "dtype": "c64" if out.dtype == 0 else "c128",
                 "method": {1: "hybrid", 2: "explicit"}.get(out.method, "auto"),
                 "npad": list(out.npad)[: out.dims], "workspace_bytes": out.workspace_bytes,
@@ -201,16 +215,20 @@ class BatchPlan:
     """
 
     def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True,
-                 tuner: str = "heuristic", model=None, tune_reps: int = 5, margin: float = 0.05):
+                 tuner: str = "heuristic", model=None, tune_reps: int = 5, margin: float = 0.05,
+                 centered: bool = False):
         Ls = [int(v) for v in Ls]
-        Ms = [A * v for v in Ls] if Ms is None else [int(v) for v in Ms]
+        if Ms is None:
+            Ms = [centered_min_padding(v, A) if centered else A * v for v in Ls]
+        Ms = [int(v) for v in Ms]
         if len(Ms) != len(Ls):
             raise ValueError("Ls and Ms differ in length")
         self.Ls, self.Ms, self.A, self.B = Ls, Ms, A, B
         self.dtype_code = dtype_code(dtype)
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
-        opt.flags = 0 if graph else _L.BATCH_NO_GRAPH
+        opt.flags = (0 if graph else _L.BATCH_NO_GRAPH) | (_L.PLAN_CENTERED if centered else 0)
+        self.centered = bool(centered)
         opt.tuner = {"heuristic": _L.TUNER_HEURISTIC, "exhaustive": _L.TUNER_EXHAUSTIVE,
                      "model": _L.TUNER_MODEL}[tuner]
         opt.tune_reps = int(tune_reps)
@@ -236,7 +254,8 @@ class BatchPlan:
         _L.check(_L.lib().hdconv_batch_info(self._h, arr, cnt, cap, ctypes.byref(ng)))
         return [{"variant": _L.VARIANT_NAMES[arr[g].variant], "m": arr[g].m, "p": arr[g].p, "n": arr[g].n,
                  "q": arr[g].q, "E_m": arr[g].E_m, "E_p": arr[g].E_p, "S": arr[g].S,
-                 "rows_per_block": arr[g].rows_per_block, "count": cnt[g], "Lmax": arr[g].L}
+                 "rows_per_block": arr[g].rows_per_block, "count": cnt[g], "Lmax": arr[g].L,
+                 "centered": bool(arr[g].centered)}
                 for g in range(min(ng.value, cap))]
 
     def bind(self, inputs, outputs) -> "BoundBatch":

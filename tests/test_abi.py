@@ -181,3 +181,63 @@ def test_every_config_plans():
     for L, M, dt in cases:
         for method in ("hybrid", "explicit"):
             Plan(L, M, dtype=dt, method=method, host_only=True).close()
+
+
+# ------------------------------------------------------ centered plans ----
+def _centered_min(L, A):
+    # -H .. L-1-H per input; A-fold sums must not alias an output index
+    H = L // 2
+    P = L - 1 - H
+    return max(A * P + H, P + A * H) + 1
+
+
+@pytest.mark.parametrize("L,A", [(1, 2), (2, 2), (7, 2), (8, 2), (1024, 2), (1023, 2), (100, 3), (101, 3)])
+def test_centered_padding_rule(L, A):
+    Mc = _centered_min(L, A)
+    if L % 2 == 0 and A == 2:
+        assert Mc == 3 * L // 2  # the padding the paper quotes for the centered case
+    with Plan((L,), (Mc,), A=A, centered=True, host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["centered"] and d["q"] * d["m"] >= Mc
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((L,), (Mc - 1,), A=A, centered=True, host_only=True)
+    assert ei.value.code == _lib.EINVAL
+    if Mc < A * (L - 1) + 1:  # below the uncentered minimum: only centered plans take it
+        with pytest.raises(_lib.HdconvError):
+            Plan((L,), (Mc,), A=A, host_only=True)
+
+
+def test_centered_shapes():
+    from paper_2303_17510_amd.hdconv import centered_min_padding
+    for L in (10, 1000, 1024, 4096, 8192, 16384, 1 << 16, 1 << 20):
+        for dt in ("c64", "c128"):
+            with Plan((L,), A=2, dtype=dt, centered=True, host_only=True) as p:
+                d = p.info()["dims"][0]
+                assert p.M == (centered_min_padding(L, 2),)
+                H = L // 2
+                tneg, tpos = -(-H // d["m"]), -(-(L - H) // d["m"])
+                if d["variant"] == "fused":
+                    assert d["p"] == tneg + tpos <= 2
+                else:
+                    assert tpos <= d["p"] and d["q"] == d["n"] * d["p"]
+                assert d["q"] * d["m"] >= p.M[0]
+                if L in (1024, 1 << 16, 1 << 20):
+                    assert d["q"] * d["m"] == 3 * L // 2  # the centered padding is reached
+    # forced shapes: direct form p = 2 with m = L/2, and the folded inner form
+    with Plan((1024,), (1536,), centered=True, m=512, host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert (d["variant"], d["p"], d["q"]) == ("fused", 2, 3)
+    with Plan((1 << 20,), (3 << 19,), centered=True, m=4096, p=128, variant="multipass", host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert (d["p"], d["n"], d["q"]) == (128, 3, 384)
+    # a smaller p is a minimum only: the positive half needs 128 blocks
+    with Plan((1 << 20,), (3 << 19,), centered=True, m=4096, p=64, variant="multipass", host_only=True) as p:
+        assert p.info()["dims"][0]["p"] == 128
+
+
+def test_centered_multidim_and_explicit_plans():
+    with Plan((256, 256), centered=True, host_only=True) as p:
+        for d in p.info()["dims"]:
+            assert d["centered"] and d["q"] * d["m"] == 384
+    with Plan((1024,), centered=True, method="explicit", host_only=True) as p:
+        assert p.info()["npad"] == [1536]
