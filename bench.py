@@ -54,6 +54,13 @@ def workload(name: str):
     if name == "c5_3d":
         return {"workload": "3D complex conv, A=2, B=1, 256^3, M=512^3, complex64, unit disk, hybrid",
                 "L": [256] * 3, "M": [512] * 3, "A": 2, "dtype": "c64", "config_id": 4}
+    if name == "c2_centered":
+        return {"workload": "1D centered complex conv, A=2, B=1, L=2^20, M=3*2^19, complex64, unit disk, hybrid",
+                "L": [1 << 20], "M": [3 << 19], "A": 2, "dtype": "c64", "config_id": 1, "centered": True}
+    if name == "c4_centered":
+        return {"workload": "2D centered complex conv, A=2, B=1, 2048x2048, M=3072x3072, complex64, Gaussian, hybrid",
+                "L": [2048, 2048], "M": [3072, 3072], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss",
+                "centered": True}
     raise SystemExit("unknown workload " + name)
 
 
@@ -125,12 +132,16 @@ def read_traffic(kernel: str, wlname: str, khash: str):
         return None
 
 
-def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None):
+def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None, **plan_kw):
     import math
     from paper_2303_17510_amd import Plan
     xs, dev = make_inputs(wl, dtype)
     t0 = time.perf_counter()
-    kw = {"m": m} if m else {}
+    kw = dict(plan_kw)
+    if m:
+        kw["m"] = m
+    if wl.get("centered"):
+        kw["centered"] = True
     with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method, tuner=tuner, **kw) as p:
         plan_s = time.perf_counter() - t0
         info = p.info()
@@ -296,7 +307,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c2_1p5m", "c4", "c5_3d"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2_1p5m", "c4", "c5_3d", "c2_centered",
+                                                         "c4_centered"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-compare", action="store_true", help="skip explicit / FP64 / other-size legs")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -390,6 +402,17 @@ def main():
             put("C5_256cube_hybrid_c64", lambda: leg(w5, "c64", "hybrid", 10, 2))
             if have_model:
                 put("C5_256cube_hybrid_c64_model", lambda: leg(w5, "c64", "hybrid", 10, 2, tuner="model"))
+            # centered convolutions (padding 3L/2 per dimension)
+            wc, wc4 = workload("c2_centered"), workload("c4_centered")
+            for dt in ("c64", "c128"):
+                put("centered_1M_hybrid_%s" % dt, lambda: leg(wc, dt, "hybrid", sc, 5))
+                put("centered_1M_hybrid_%s_folded" % dt,
+                    lambda: leg(wc, dt, "hybrid", sc, 5, m=4096, p=128, variant="multipass"))
+                put("centered_1M_hybrid_%s_tuned" % dt, lambda: leg(wc, dt, "hybrid", sc, 5, tuner="exhaustive"))
+                put("centered_1M_explicit_%s" % dt, lambda: explicit_best(wc, dt, sc, 5))
+            put("centered_2048x2048_hybrid_c64", lambda: leg(wc4, "c64", "hybrid", 20, 3))
+            put("centered_2048x2048_hybrid_c64_tuned", lambda: leg(wc4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
+            put("centered_2048x2048_explicit_c64", lambda: leg(wc4, "c64", "explicit", 10, 2))
         for v in compare.values():
             v.pop("stats", None)
             v.pop("info", None)
