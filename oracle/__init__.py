@@ -24,6 +24,11 @@ Functions (Murasko & Bowman, arXiv 2303.17510):
   (``A = 3``: the triple sum), evaluated as compensated direct sums.
 * :func:`conv_centered_explicit` -- OC by O2: entries ``(A-1)H ..
   (A-1)H+L-1`` per dimension of the explicitly padded linear convolution.
+* :func:`conv_hermitian_direct` / :func:`conv_hermitian_explicit` -- OH,
+  Hermitian convolutions (1D): arrays of ``Lh`` entries hold ``f_0 ..
+  f_{Lh-1}`` of the centered Hermitian array ``f_{-j} = conj(f_j)`` (``f_0``
+  taken real); the result is the centered convolution of the expanded arrays
+  at ``c = 0 .. Lh-1`` (:func:`hermitian_expand` does the expansion).
 * :func:`padded_dft` -- the padded DFT of Sec. 2,
   ``F_k = sum_{j<L} zeta_N^{kj} f_j`` with ``zeta_N = exp(+2 pi i/N)``.
 * :func:`fft` / :func:`fft_nd` -- the unnormalised transform
@@ -74,11 +79,13 @@ def _bind(path: str):
     lib.oracle_explicit_centered.argtypes = [ctypes.POINTER(_dblp), ctypes.c_int, ctypes.c_int, _i64p, _dblp]
     lib.oracle_direct_centered.argtypes = [_dblp, _i64p, _i64p, _dblp, _i64p, _i64p, ctypes.c_int, _i64p, _i64p,
                                            _i64p, ctypes.c_int64, _dblp]
+    lib.oracle_hermitian_expand.argtypes = [_dblp, ctypes.c_int64, _dblp]
     lib.oracle_padded_dft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _dblp]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit", "oracle_explicit_centered",
-               "oracle_direct_centered", "oracle_padded_dft", "oracle_num_threads", "oracle_set_num_threads"):
+               "oracle_direct_centered", "oracle_hermitian_expand", "oracle_padded_dft", "oracle_num_threads",
+               "oracle_set_num_threads"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -243,6 +250,40 @@ def conv_centered_explicit(inputs) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_explicit_centered failed (%d)" % rc)
     return out
+
+
+def hermitian_expand(f) -> np.ndarray:
+    """The centered array ``f_{-(Lh-1)} .. f_{Lh-1}`` (``f_{-j} = conj(f_j)``,
+    ``f_0`` real) that ``Lh`` stored entries ``f_0 .. f_{Lh-1}`` stand for."""
+    f = _c128(f).ravel()
+    out = np.empty(2 * f.size - 1, dtype=np.complex128)
+    rc = _load().oracle_hermitian_expand(_dp(f), f.size, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_hermitian_expand failed (%d)" % rc)
+    return out
+
+
+def conv_hermitian_direct(inputs, idx=None) -> np.ndarray:
+    """OH: Hermitian convolution of ``A`` (2 or 3) stored halves of one length
+    ``Lh`` (1D); returns ``h_0 .. h_{Lh-1}`` (or the entries ``idx``)."""
+    ins = [_c128(x).ravel() for x in inputs]
+    if len(ins) not in (2, 3) or any(x.size != ins[0].size for x in ins):
+        raise ValueError("need 2 or 3 inputs of one length")
+    Lh = ins[0].size
+    full = [hermitian_expand(x) for x in ins]
+    pos = np.arange(Lh, dtype=np.int64) if idx is None else np.asarray(idx, dtype=np.int64).ravel()
+    if np.any(pos < 0) or np.any(pos >= Lh):
+        raise ValueError("idx out of range")
+    return conv_centered_direct(full, idx=pos + (Lh - 1))
+
+
+def conv_hermitian_explicit(inputs) -> np.ndarray:
+    """OH by explicit zero padding of the expanded arrays."""
+    ins = [_c128(x).ravel() for x in inputs]
+    if len(ins) not in (2, 3) or any(x.size != ins[0].size for x in ins):
+        raise ValueError("need 2 or 3 inputs of one length")
+    Lh = ins[0].size
+    return conv_centered_explicit([hermitian_expand(x) for x in ins])[Lh - 1:]
 
 
 def padded_dft(f, N: int, ks) -> np.ndarray:

@@ -36,6 +36,13 @@
  *      compensated sums, and as O2 on the full linear convolution whose
  *      entries (A-1)H .. (A-1)H+L-1 per dimension are the centered outputs.
  *
+ *  OH  Hermitian convolutions (the paper's section on Hermitian symmetric
+ *      convolutions): an array of Lh entries holds f_0 .. f_{Lh-1}, and the
+ *      array it stands for is the centered f_{-(Lh-1)} .. f_{Lh-1} with
+ *      f_{-j} = conj(f_j) (f_0 taken real).  The result is the centered
+ *      convolution of the expanded arrays at c = 0 .. Lh-1.  The expansion is
+ *      here (oracle_hermitian_expand); the sums are OC's.
+ *
  *  PD  the padded DFT of Sec. 2, F_k = sum_{j<L} zeta_N^{kj} f_j with
  *      zeta_N = exp(+2 pi i / N), evaluated term by term at requested k with
  *      the phase k*j reduced modulo N in exact integer arithmetic.  Used to
@@ -372,6 +379,28 @@ int oracle_direct_centered(const double* fa, const int64_t* La, const int64_t* H
     }
     out[2 * n] = nsum_get(&re);
     out[2 * n + 1] = nsum_get(&im);
+  }
+  return 0;
+}
+
+/* ---- OH: Hermitian expansion --------------------------------------------
+ * f holds f_0 .. f_{Lh-1}; out (2 Lh - 1 entries) receives the centered array
+ * f_{-(Lh-1)} .. f_{Lh-1} at positions c + Lh - 1, with f_{-j} = conj(f_j)
+ * and f_0 replaced by its real part (a Hermitian array has a real centre). */
+int oracle_hermitian_expand(const double* f, int64_t Lh, double* out) {
+  if (Lh < 1) return -1;
+  const int64_t H = Lh - 1;
+  for (int64_t c = -H; c <= H; ++c) {
+    const int64_t j = c < 0 ? -c : c;
+    double re = f[2 * j], im = f[2 * j + 1];
+#if ORACLE_MUTANT == 10 /* mirror without the conjugate */
+    if (c == 0) im = 0.0;
+#else
+    if (c < 0) im = -im;
+    if (c == 0) im = 0.0;
+#endif
+    out[2 * (c + H)] = re;
+    out[2 * (c + H) + 1] = im;
   }
   return 0;
 }

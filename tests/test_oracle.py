@@ -10,7 +10,10 @@ and the padded DFT with zeta_N = exp(+2 pi i/N) (Sec. 2).  The centered
 convolution (the paper's centered case: indices -H .. L-1-H, H = floor(L/2))
 is pinned by a literal dictionary evaluation of its definition on tiny inputs,
 by the Fourier coefficients of a product of trigonometric polynomials (numpy's
-FFT), by centered deltas and by a geometric closed form.
+FFT), by centered deltas and by a geometric closed form.  The Hermitian
+convolution is pinned by a dictionary evaluation with an explicit conjugate
+mirror and by products of real functions evaluated and read back with numpy's
+real FFTs.
 """
 import numpy as np
 import pytest
@@ -322,3 +325,72 @@ def test_centered_sampled_and_commutative():
     full3 = oracle.conv_centered_direct([f, g, h])
     np.testing.assert_allclose(oracle.conv_centered_direct([h, f, g]), full3, atol=1e-13)
     np.testing.assert_array_equal(oracle.conv_centered_direct([f, g, h], idx=idx), full3.ravel()[idx])
+
+
+# ------------------------------------------------ Hermitian convolution ----
+def _hermitian_brute(ins):
+    """h_c for c >= 0 of the expanded arrays f_{-j} = conj(f_j), written with
+    dictionaries keyed by signed index (f_0 taken real)."""
+    Lh = len(ins[0])
+    rng = range(-(Lh - 1), Lh)
+    arrs = []
+    for x in ins:
+        d = {c: (x[c] if c > 0 else (np.conj(x[-c]) if c < 0 else x[0].real + 0j)) for c in rng}
+        arrs.append(d)
+    acc = {0: 1.0 + 0j}
+    for a in arrs:
+        nxt = {}
+        for c0, v in acc.items():
+            for c1 in rng:
+                nxt[c0 + c1] = nxt.get(c0 + c1, 0) + v * a[c1]
+        acc = nxt
+    return np.array([acc[c] for c in range(Lh)])
+
+
+@pytest.mark.parametrize("Lh", [1, 2, 3, 5, 8])
+def test_hermitian_brute_force_tiny(Lh):
+    for A in (2, 3):
+        ins = [rnd(Lh, 150 + 7 * Lh + k) for k in range(A)]
+        ref = _hermitian_brute(ins)
+        np.testing.assert_allclose(oracle.conv_hermitian_direct(ins), ref, atol=1e-14)
+        np.testing.assert_allclose(oracle.conv_hermitian_explicit(ins), ref, atol=1e-14)
+
+
+@pytest.mark.parametrize("Lh", [1, 7, 64, 257])
+def test_hermitian_matches_real_function_product(Lh):
+    # f(theta) = sum_{|c| < Lh} f_c e^{i c theta} is real for f_{-c} = conj(f_c):
+    # numpy's inverse real FFT evaluates it from the stored half, the product of
+    # A such functions is real, and numpy's real FFT reads back its
+    # coefficients c = 0 .. Lh-1 (N > 2 A (Lh-1): no coefficient wraps).
+    for A in (2, 3):
+        ins = [rnd(Lh, 170 + k) for k in range(A)]
+        N = 2 * A * (Lh - 1) + 2
+        prod = np.ones(N)
+        for x in ins:
+            spec = np.zeros(N // 2 + 1, complex)
+            spec[:Lh] = x
+            spec[0] = x[0].real
+            prod *= np.fft.irfft(spec, N) * N
+        ref = np.fft.rfft(prod)[:Lh] / N
+        assert oracle.rel_l2(oracle.conv_hermitian_direct(ins), ref) < 1e-13
+        assert oracle.rel_l2(oracle.conv_hermitian_explicit(ins), ref) < 1e-13
+
+
+def test_hermitian_delta_real_centre_and_sampling():
+    Lh = 40
+    g = rnd(Lh, 180)
+    g[0] = g[0].real
+    d = np.zeros(Lh, complex)
+    d[0] = 1.0
+    np.testing.assert_allclose(oracle.conv_hermitian_direct([d, g]), g, atol=1e-15)
+    # the imaginary part of a stored centre is not part of a Hermitian array
+    d[0] = 1.0 + 5.0j
+    np.testing.assert_allclose(oracle.conv_hermitian_direct([d, g]), g, atol=1e-15)
+    f, h = rnd(Lh, 181), rnd(Lh, 182)
+    full = oracle.conv_hermitian_direct([f, h])
+    assert abs(full[0].imag) < 1e-14 * abs(full[0])  # h_0 of a real product is real
+    idx = np.array([0, 3, 39])
+    np.testing.assert_array_equal(oracle.conv_hermitian_direct([f, h], idx=idx), full[idx])
+    # expansion: conjugate mirror around a real centre
+    e = oracle.hermitian_expand(np.array([2 + 1j, 3 - 4j]))
+    np.testing.assert_array_equal(e, np.array([3 + 4j, 2 + 0j, 3 - 4j]))

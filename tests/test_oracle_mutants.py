@@ -3,7 +3,8 @@
 The oracle is rebuilt with -DORACLE_MUTANT=k (a conjugated operand, a dropped
 term, a transposed operand, a flipped twiddle sign, padding one short of the
 minimal length, a wrong normalisation, the wrong root of unity, a centered
-operand read one place off, a centre rounded up instead of down) and the pins
+operand read one place off, a centre rounded up instead of down, a Hermitian
+mirror without the conjugate) and the pins
 of tests/test_oracle.py are run against each build; every build must fail at
 least one of them.  The default build is checked to pass them all.
 """
@@ -17,7 +18,7 @@ import test_oracle as pins
 
 MUTANTS = {1: "conjugated operand", 2: "dropped term", 3: "transposed operand",
            4: "twiddle sign", 5: "padding too short", 6: "normalisation", 7: "root of unity",
-           8: "centered operand off by one", 9: "centre rounded up"}
+           8: "centered operand off by one", 9: "centre rounded up", 10: "Hermitian mirror without conjugate"}
 
 
 def _pin_calls():
