@@ -20,6 +20,7 @@ VARIANT_AUTO, VARIANT_FUSED, VARIANT_MULTIPASS, VARIANT_OUTER = 0, 1, 2, 3
 PLAN_HOST_ONLY = 1
 BATCH_NO_GRAPH = 2
 PLAN_CENTERED = 4
+PLAN_HERMITIAN = 8
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
 NFEATURES = 44
 

@@ -57,6 +57,7 @@ struct DimDev {
 struct Plan {
   int dims = 0, A = 0, B = 0, dtype = 0, method = 0, flags = 0;
   int64_t L[3] = {1, 1, 1}, M[3] = {1, 1, 1};
+  int64_t Lio[3] = {1, 1, 1};  // stored extents (Hermitian: ceil(L/2))
   int64_t npad[3] = {0, 0, 0};
   DimPlan dp[3];
   int device = -1;
@@ -115,6 +116,11 @@ struct ProfScope {
 
 static int tbytes_of(int dtype) { return dtype == HDCONV_C64 ? 4 : 8; }
 
+// Hermitian arrays of nominal length L store ceil(L/2) entries and stand for
+// the centered array of length 2 ceil(L/2) - 1 the engine transforms.
+static int64_t herm_stored(int64_t L) { return (L + 1) / 2; }
+static int64_t herm_full(int64_t L) { return 2 * herm_stored(L) - 1; }
+
 static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                        const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms);
 static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims);
@@ -136,10 +142,12 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
   const int tb = tbytes_of(P->dtype);
   // centered hybrid plans run centered transforms; the explicit method pads
   // the arrays as they are and reads the centered window out of the result
-  const int ctr = (P->flags & HDCONV_PLAN_CENTERED) && P->method != HDCONV_METHOD_EXPLICIT ? 1 : 0;
+  const int herm = (P->flags & HDCONV_PLAN_HERMITIAN) && P->method != HDCONV_METHOD_EXPLICIT ? 1 : 0;
+  const int ctr = ((P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) &&
+                   P->method != HDCONV_METHOD_EXPLICIT) ? 1 : 0;
   for (int d = 0; d < P->dims; ++d) {
     const bool contiguous = (d == P->dims - 1);
-    int64_t Le = P->L[d], Me = P->M[d];
+    int64_t Le = herm ? herm_full(P->L[d]) : P->L[d], Me = P->M[d];
     if (P->method == HDCONV_METHOD_EXPLICIT) Le = Me = P->npad[d];
     DimPlan& dp = P->dp[d];
     std::string why;
@@ -166,7 +174,15 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
             dp.E_m = opt->E_m[d];
             dp.E_p = opt->E_p[d];
           }
-        } else if (!contiguous || Le <= kMaxFusedM) {
+        } else if (!contiguous || (Le <= kMaxFusedM && [&] {
+                     // one whole-row transform, if it fits the row kernel (LDS)
+                     DimPlan t = dp;
+                     t.m = Le;
+                     t.p = t.q = t.n = t.D = 1;
+                     t.variant = VAR_FUSED;
+                     std::string w;
+                     return finish_dim(&t, P->A, tb, &w);
+                   }())) {
           dp.m = Le;
           dp.p = dp.q = dp.n = dp.D = 1;
           dp.variant = contiguous ? VAR_FUSED : VAR_OUTER;
@@ -190,6 +206,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
+      dp.herm = herm;
     } else {
       if (fv == HDCONV_VARIANT_AUTO) {
         Geometry g = geometry_c(Le, Me, fm ? fm : next_fft_size(Le), fp, false, ctr);
@@ -215,6 +232,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       dp.D = (opt && opt->D[d] > 0) ? std::min<int64_t>(opt->D[d], g.n) : g.n;
       dp.variant = fv;
       dp.ctr = ctr;
+      dp.herm = herm;
       if (opt) {
         dp.E_m = opt->E_m[d];
         dp.E_p = opt->E_p[d];
@@ -240,7 +258,7 @@ static double plan_traffic(const Plan* P, int* launches) {
   for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
   double ltot = 1, etot = 1;
   for (int d = 0; d < P->dims; ++d) {
-    ltot *= (double)P->L[d];
+    ltot *= (double)P->Lio[d];
     etot *= (double)Le[d];
   }
   if (P->method == HDCONV_METHOD_EXPLICIT) {
@@ -259,7 +277,8 @@ static double plan_traffic(const Plan* P, int* launches) {
     nb *= (double)(dp.q * dp.m);
   }
   const DimPlan& dl = P->dp[P->dims - 1];
-  const double rows = nb, Lr = (double)Le[P->dims - 1];
+  // words each row reads per input and writes (Hermitian rows: the stored half)
+  const double rows = nb, Lr = (double)(dl.herm ? P->Lio[P->dims - 1] : Le[P->dims - 1]);
   if (dl.variant == VAR_FUSED) {
     bytes += rows * (A + B) * Lr * w;
     nl += 1;
@@ -422,13 +441,14 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     a.tasks = tasks;
     for (int i = 0; i < A; ++i) a.in[i] = in ? in[i] : nullptr;
     a.out = out;
-    a.in_stride = a.out_stride = dp.L;
+    a.in_stride = a.out_stride = dp.herm ? herm_stored(dp.L) : dp.L;
     a.nrows = nrows;
     a.L = dp.L;
     a.m = (int)dp.m;
     a.q = (int)dp.q;
     a.rows_per_block = dp.rows_per_block;
     a.ctr = dp.ctr;
+    a.herm = dp.herm;
     a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     a.fd = dp.fd_m;
     a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
@@ -450,7 +470,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
       k1.in[i] = in ? in[i] : nullptr;
       k1.work[i] = (cpx<T>*)P->rowwork[i];
     }
-    k1.in_stride = dp.L;
+    k1.in_stride = dp.herm ? herm_stored(dp.L) : dp.L;
     k1.nrows = nrows;
     k1.L = dp.L;
     k1.m = (int)dp.m;
@@ -461,6 +481,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k1.S = dp.S;
     k1.ctr = dp.ctr;
     k1.fold = centered_folds(dp) ? 1 : 0;
+    k1.herm = dp.herm;
     k1.fd = dp.fd_p;
     k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k1.zq = (const cpx<T>*)P->dd[d].zq;
@@ -496,7 +517,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.out = out;
     k3.acc = P->acc64;
     k3.acc_mode = nblk == 1 ? ACC_WRITE : (blk == 0 ? ACC_FIRST : (blk == nblk - 1 ? ACC_LAST : ACC_ADD));
-    k3.out_stride = dp.L;
+    k3.out_stride = dp.herm ? herm_stored(dp.L) : dp.L;
     k3.nrows = nrows;
     k3.L = dp.L;
     k3.m = (int)dp.m;
@@ -507,6 +528,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.S = dp.S;
     k3.ctr = dp.ctr;
     k3.fold = centered_folds(dp) ? 1 : 0;
+    k3.herm = dp.herm;
     k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     k3.fd = dp.fd_pb;
     k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
@@ -538,14 +560,18 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
       b.dst = (cpx<T>*)P->pad_in[a];
       for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
       for (int d = 0; d < P->dims; ++d) {
-        b.L[3 - P->dims + d] = P->L[d];
+        b.L[3 - P->dims + d] = P->Lio[d];
         b.N[3 - P->dims + d] = P->npad[d];
       }
       b.pad = 1;
+      if (P->flags & HDCONV_PLAN_HERMITIAN) {  // 1D: the expanded centered array
+        b.herm = 1;
+        b.hH = P->Lio[0] - 1;
+      }
       {
         double lt = 1, nt = 1;
         for (int d = 0; d < P->dims; ++d) {
-          lt *= (double)P->L[d];
+          lt *= (double)P->Lio[d];
           nt *= (double)P->npad[d];
         }
         ProfScope ps(P, s, "pad", (lt + nt) * 2.0 * sizeof(T));
@@ -633,17 +659,19 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     b.dst = (cpx<T>*)out_v;
     for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
     for (int d = 0; d < P->dims; ++d) {
-      b.L[3 - P->dims + d] = P->L[d];
+      b.L[3 - P->dims + d] = P->Lio[d];
       b.N[3 - P->dims + d] = P->npad[d];
       // centered: entries (A-1)H .. (A-1)H+L-1 of the padded product are the
       // outputs -H .. L-1-H (the arrays were padded as they are, index c at
-      // position c + H, so a product of A of them sits A H further on)
-      if (P->flags & HDCONV_PLAN_CENTERED) b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
+      // position c + H, so a product of A of them sits A H further on);
+      // Hermitian: the outputs c >= 0 start at A H (H = Lh - 1)
+      if (P->flags & HDCONV_PLAN_HERMITIAN) b.off[3 - P->dims + d] = (int64_t)A * (P->Lio[d] - 1);
+      else if (P->flags & HDCONV_PLAN_CENTERED) b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
     }
     b.pad = 0;
     {
       double lt = 1;
-      for (int d = 0; d < P->dims; ++d) lt *= (double)P->L[d];
+      for (int d = 0; d < P->dims; ++d) lt *= (double)P->Lio[d];
       ProfScope ps(P, s, "truncate", 2.0 * lt * 2.0 * sizeof(T));
       e = launch_box_copy<T>(b, s);
     }
@@ -711,16 +739,24 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128 (got %d)", dtype);
     return nullptr;
   }
+  const bool herm = opt && (opt->flags & HDCONV_PLAN_HERMITIAN);
+  if (herm && dims != 1) {
+    set_err(HDCONV_EUNSUPPORTED, "Hermitian plans are one-dimensional in this build (got dims = %d)", dims);
+    return nullptr;
+  }
   for (int d = 0; d < dims; ++d) {
     if (L[d] < 1 || L[d] > (int64_t(1) << 31)) {
       set_err(HDCONV_EINVAL, "L[%d] = %lld out of range", d, (long long)L[d]);
       return nullptr;
     }
-    const bool ctr = opt && (opt->flags & HDCONV_PLAN_CENTERED);
-    const int64_t Mmin = ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1;
+    const bool ctr = opt && (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN));
+    const int64_t Mmin = herm ? centered_min_padding(herm_full(L[d]), A)
+                              : (ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1);
     if (M[d] < Mmin) {
       set_err(HDCONV_EINVAL, "M[%d] = %lld is below %s = %lld, so the product would alias", d, (long long)M[d],
-              ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1", (long long)Mmin);
+              herm ? "the Hermitian minimum (A+1)(ceil(L/2)-1)+1"
+                   : (ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1"),
+              (long long)Mmin);
       return nullptr;
     }
   }
@@ -756,6 +792,7 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
   for (int d = 0; d < dims; ++d) {
     P->L[d] = L[d];
+    P->Lio[d] = herm ? herm_stored(L[d]) : L[d];
     P->M[d] = M[d];
     if (P->method == HDCONV_METHOD_EXPLICIT) P->npad[d] = std::max<int64_t>(8, next_fft_size(M[d]));
   }
@@ -807,7 +844,7 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
     out->M[d] = d < P->dims ? P->M[d] : 0;
     out->npad[d] = P->npad[d];
     if (d >= P->dims) continue;
-    ltot *= (double)P->L[d];
+    ltot *= (double)P->Lio[d];
     const DimPlan& dp = P->dp[d];
     hdconv_dim_info_t& di = out->dim[d];
     di.L = dp.L;
@@ -824,7 +861,7 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
     di.rows_per_block = dp.rows_per_block;
     di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
     di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
-    di.centered = (P->flags & HDCONV_PLAN_CENTERED) ? 1 : 0;
+    di.centered = (P->flags & HDCONV_PLAN_HERMITIAN) ? 2 : ((P->flags & HDCONV_PLAN_CENTERED) ? 1 : 0);
   }
   out->workspace_bytes = P->work_bytes;
   out->table_bytes = P->table_bytes;
@@ -843,7 +880,7 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
   Plan* P = (Plan*)plan;
   if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
   size_t bytes = 2 * (size_t)tbytes_of(P->dtype);
-  for (int d = 0; d < P->dims; ++d) bytes *= (size_t)P->L[d];
+  for (int d = 0; d < P->dims; ++d) bytes *= (size_t)P->Lio[d];
   for (int a = 0; a < P->A; ++a)
     if (!inputs[a]) return set_err(HDCONV_EINVAL, "inputs[%d] is NULL", a);
   if (!outputs[0]) return set_err(HDCONV_EINVAL, "outputs[0] is NULL");
@@ -948,7 +985,7 @@ static void fill_dim_info(const DimPlan& dp, hdconv_dim_info_t* di) {
   di->rows_per_block = dp.rows_per_block;
   di->tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
   di->tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
-  di->centered = dp.ctr;
+  di->centered = dp.herm ? 2 : dp.ctr;
 }
 
 // options that reproduce the per-dimension shapes exactly
@@ -956,7 +993,8 @@ static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims) {
   hdconv_options o;
   memset(&o, 0, sizeof(o));
   o.method = HDCONV_METHOD_HYBRID;
-  if (shp[0].centered) o.flags |= HDCONV_PLAN_CENTERED;
+  if (shp[0].centered == 1) o.flags |= HDCONV_PLAN_CENTERED;
+  if (shp[0].centered == 2) o.flags |= HDCONV_PLAN_HERMITIAN;
   for (int d = 0; d < dims; ++d) {
     o.m[d] = shp[d].m;
     o.p[d] = shp[d].p;
@@ -1079,8 +1117,15 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
                        const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms) {
   std::vector<hdconv_dim_info_t> cand;
   std::vector<int> varied;
-  int rc = list_candidates(L, M, A, dims, dtype, (opt->flags & HDCONV_PLAN_CENTERED) ? 1 : 0, &cand, &varied);
+  // candidates are shapes of the engine's lengths (Hermitian: the full centered length)
+  const bool herm = (opt->flags & HDCONV_PLAN_HERMITIAN) != 0;
+  int64_t Lc[3];
+  for (int d = 0; d < dims; ++d) Lc[d] = herm ? herm_full(L[d]) : L[d];
+  int rc = list_candidates(Lc, M, A, dims, dtype,
+                           (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) ? 1 : 0, &cand, &varied);
   if (rc != HDCONV_OK) return rc;
+  if (herm)
+    for (auto& c : cand) c.centered = 2;
   const int nc = (int)varied.size();
   *ncand = nc;
   *ntimed = 0;
@@ -1282,6 +1327,7 @@ static Plan* make_group_plan(int A, int B, int dtype, const DimPlan& dp, int64_t
   P->dtype = dtype;
   P->method = HDCONV_METHOD_HYBRID;
   P->L[0] = dp.L;
+  P->Lio[0] = dp.herm ? herm_stored(dp.L) : dp.L;
   P->M[0] = dp.M;
   P->dp[0] = dp;
   P->batch_rows = rows;
@@ -1486,7 +1532,8 @@ static int tune_batch_groups(int A, int B, int dtype, int device, const hdconv_o
         if (same(u, c)) return;
       cands.push_back(c);
     };
-    for (const DimPlan& c : dim_candidates(base.L, base.M, A, tb, true, base.ctr)) {
+    for (DimPlan c : dim_candidates(base.L, base.M, A, tb, true, base.ctr)) {
+      c.herm = base.herm;
       add(c);
       if (c.variant == VAR_FUSED)
         for (int f : {2, 4}) {
@@ -1578,13 +1625,16 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
     set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128");
     return nullptr;
   }
-  const int ctr = (opt && (opt->flags & HDCONV_PLAN_CENTERED)) ? 1 : 0;
+  const int herm = (opt && (opt->flags & HDCONV_PLAN_HERMITIAN)) ? 1 : 0;
+  const int ctr = (opt && (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))) ? 1 : 0;
   for (int64_t i = 0; i < count; ++i)
     if (L[i] < 1 || L[i] > (int64_t(1) << 31) ||
-        M[i] < (ctr ? centered_min_padding(L[i], A) : (int64_t)A * (L[i] - 1) + 1)) {
+        M[i] < (herm ? centered_min_padding(herm_full(L[i]), A)
+                     : (ctr ? centered_min_padding(L[i], A) : (int64_t)A * (L[i] - 1) + 1))) {
       set_err(HDCONV_EINVAL, "convolution %lld: need L >= 1 and M >= %s (L=%lld, M=%lld)", (long long)i,
-              ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1", (long long)L[i],
-              (long long)M[i]);
+              herm ? "the Hermitian minimum (A+1)(ceil(L/2)-1)+1"
+                   : (ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1"),
+              (long long)L[i], (long long)M[i]);
       return nullptr;
     }
   int ndev = 0;
@@ -1604,7 +1654,9 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
   Bt->dtype = dtype;
   Bt->flags = opt ? opt->flags : 0;
   Bt->count = count;
-  Bt->L.assign(L, L + count);
+  Bt->L.assign(L, L + count);  // engine lengths (Hermitian: the full centered length)
+  if (herm)
+    for (auto& v : Bt->L) v = herm_full(v);
   Bt->M.assign(M, M + count);
   const int tb = tbytes_of(dtype);
   std::map<GroupKey, std::vector<int64_t>> byk;
@@ -1612,11 +1664,12 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
   for (int64_t i = 0; i < count; ++i) {
     DimPlan dp;
     std::string why;
-    if (!choose_dim(L[i], M[i], A, tb, true, count, &dp, &why, ctr)) {
+    if (!choose_dim(Bt->L[i], M[i], A, tb, true, count, &dp, &why, ctr)) {
       set_err(HDCONV_EUNSUPPORTED, "convolution %lld (L=%lld): %s", (long long)i, (long long)L[i], why.c_str());
       free_batch(Bt);
       return nullptr;
     }
+    dp.herm = herm;
     GroupKey k{dp.variant, dp.m, dp.p, dp.n, dp.q, dp.E_m, dp.E_p, dp.S, dp.rows_per_block};
     auto it = shape.find(k);
     if (it == shape.end()) shape[k] = dp;
@@ -1722,7 +1775,7 @@ int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* cou
       di.rows_per_block = dp.rows_per_block;
       di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
       di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
-      di.centered = dp.ctr;
+      di.centered = dp.herm ? 2 : dp.ctr;
     }
     if (counts) counts[g] = (int64_t)Bt->members[g].size();
   }

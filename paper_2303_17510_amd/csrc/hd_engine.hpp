@@ -24,6 +24,10 @@
 //    value at position t to both output blocks, each with its own twiddle.
 //    The inverse stores output c at position c + H, so the result is the
 //    centered convolution.
+//  * Hermitian rows (herm = 1; the paper's Hermitian symmetric case): L is the
+//    full centered length 2 Lh - 1 and the arrays hold only f_0 .. f_{Lh-1};
+//    a load of a negative index c reads conj(f_{-c}) (f_0 real), and only the
+//    outputs c >= 0 are stored, at position c.
 #pragma once
 #include "hd_common.hpp"
 #include "hd_fft.hpp"
@@ -63,7 +67,8 @@ struct FusedArgs {
   int64_t L;
   int m, q;
   int rows_per_block;
-  int ctr;  // 1: centered rows (H = floor(L/2) of each row's own L)
+  int ctr;   // 1: centered rows (H = floor(L/2) of each row's own L)
+  int herm;  // 1: Hermitian rows (half storage, see above)
   T scale;  // 1/(q m)
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -84,6 +89,7 @@ struct ColFwdArgs {
   int m, p, q, v0, D, S;
   int ctr;   // 1: centered rows
   int fold;  // 1: two blocks per column position (centered, p below the span)
+  int herm;  // 1: Hermitian rows
   FftDesc fd;  // p points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   const cpx<T>* zq;  // zeta_q^k, k < q
@@ -120,6 +126,7 @@ struct ColBwdArgs {
   int m, p, q, v0, D, S;
   int ctr;   // 1: centered rows
   int fold;  // 1: two blocks per column position (centered, p below the span)
+  int herm;  // 1: Hermitian rows
   T scale;
   FftDesc fd;  // p points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -167,6 +174,8 @@ struct BoxCopyArgs {
   int64_t L[3], N[3];  // leading unused extents are 1
   int64_t off[3];      // truncation: dst[i] = src[i + off] (0, or the centered window start)
   int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
+  int herm;            // padding of a 1D Hermitian array: dst[c + hH] = f_c for |c| <= hH,
+  int64_t hH;          // with f_{-c} = conj f_c read from the L = hH + 1 stored entries
 };
 
 // Launchers (return the launch status).  E, P and A select the template

@@ -20,7 +20,7 @@ namespace hd {
 // paper's centered case with p = 2, eq. forCent/wDef): block t holds the
 // signed indices c = (t - tneg) m + s at array position t m + s - sh, and the
 // twiddles are zeta_{qm}^{r c}; the output c goes back to position c + H.
-template <typename T, int E, int P, int A>
+template <typename T, int E, int P, int A, bool HERM>
 __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   // Inputs small enough stay in registers across the residues; larger ones
   // are read again for each residue (from cache) to keep registers free.
@@ -36,9 +36,10 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   const uint32_t L = valid ? (uint32_t)(tk ? tk->L : a.L) : 0u;
   const uint32_t qm = (uint32_t)a.q * (uint32_t)m;
   // centered rows: tneg blocks left of index 0, block position j holds array
-  // position j - sh (both 0 for an ordinary row)
-  const uint32_t H = a.ctr ? (L >> 1) : 0u;
-  const uint32_t tneg = (H + (uint32_t)m - 1) / (uint32_t)m;
+  // position j - sh (both 0 for an ordinary row; a centered row spans two
+  // blocks unless L = 1, so P = 1 never shifts)
+  const uint32_t H = (P == 2 && a.ctr) ? (L >> 1) : 0u;
+  const uint32_t tneg = H ? (H + (uint32_t)m - 1) / (uint32_t)m : 0u;
   const uint32_t sh = tneg * (uint32_t)m - H;
   const cpx<T>* src[A];
 #pragma unroll
@@ -47,10 +48,15 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
 
-  // the row's inputs (zero beyond L)
+  // the row's inputs (zero beyond L; Hermitian rows mirror the stored half,
+  // and a one-block Hermitian row is the lone real centre, L = 1).  HERM is a
+  // template parameter: the mirror sits in the residue loop when the inputs
+  // are re-read there, and ordinary rows must not pay its registers.
+  constexpr bool herm = HERM;
   auto load = [&](int ai, int t, int e) -> cpx<T> {
     const uint32_t i = (uint32_t)(t * m + g + G * e) - sh;  // wraps above L when j < sh
-    return i < L ? ld_at(src[ai], i) : czero<T>();
+    if (!(i < L)) return czero<T>();
+    return herm ? herm_value(src[ai], (int64_t)i - (int64_t)H) : ld_at(src[ai], i);
   };
   cpx<T> x[kKeep ? A : 1][kKeep ? P : 1][kKeep ? E : 1];
   if constexpr (kKeep) {
@@ -69,11 +75,19 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
 
+  // Residue twiddle exponents without division: r g and r G stay below qm
+  // (r < q, g < G <= m).  Block t starts at the signed index
+  // c = (t - tneg) m + g, whose exponent is r g + m ((r (t - tneg)) mod q),
+  // with t - tneg in {-1, 0, 1} (P <= 2).
   for (int r = 0; r < a.q; ++r) {
-    // exponents of zeta_{qm}^{r j} for j = t m + g + G e advance by r G per e
-    const uint32_t st = (uint32_t)(((uint64_t)r * G) % qm);
-    // exponent r c = r j - r tneg m, kept in [0, qm)
-    const uint64_t rneg = qm - (uint32_t)(((uint64_t)r * (tneg * (uint32_t)m)) % qm);
+    const uint32_t eg = (uint32_t)r * (uint32_t)g, st = (uint32_t)r * (uint32_t)G;
+    auto ex_of = [&](int t) -> uint32_t {
+      const int d = t - (int)tneg;
+      const uint32_t rm = (uint32_t)r * (uint32_t)m;
+      const uint32_t add = d == 0 ? 0u : (d > 0 ? rm : (r ? qm - rm : 0u));
+      const uint32_t e = eg + add;
+      return e >= qm ? e - qm : e;
+    };
     cpx<T> w[A][E];
 #pragma unroll
     for (int ai = 0; ai < A; ++ai)
@@ -81,8 +95,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g) + rneg) % qm);
-      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) {
+      a.zqm.template run<E>(ex_of(t), st, [&](int e, cpx<T> z) {
 #pragma unroll
         for (int ai = 0; ai < A; ++ai) {
           cpx<T> xv;
@@ -104,8 +117,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)(((uint64_t)r * (uint32_t)(t * m + g) + rneg) % qm);
-      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
+      a.zqm.template run<E>(ex_of(t), st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
     }
   }
   if (valid) {
@@ -115,7 +127,9 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const uint32_t i = (uint32_t)(t * m + g + G * e) - sh;
-        if (i < L) st_at(dst, i, cscale(acc[t][e], a.scale));
+        // Hermitian rows keep the outputs c = i - H >= 0, at c
+        const uint32_t o = herm ? i - H : i;
+        if (i < L && (!herm || i >= H)) st_at(dst, o, cscale(acc[t][e], a.scale));
       }
   }
 }
@@ -143,8 +157,10 @@ hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_
   if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N) return HD_BAD;
   dim3 grid((unsigned)((a.nrows + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
   const size_t lds = lds_fused1d(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
-#define F1(EE, PP, AA) \
-  if (E == EE && P == PP && A == AA) return go(k_fused1d<T, EE, PP, AA>, grid, block, lds, s, a);
+#define F1(EE, PP, AA)                                                                     \
+  if (E == EE && P == PP && A == AA)                                                       \
+    return a.herm ? go(k_fused1d<T, EE, PP, AA, true>, grid, block, lds, s, a)             \
+                  : go(k_fused1d<T, EE, PP, AA, false>, grid, block, lds, s, a);
   F1(4, 1, 2) F1(4, 2, 2) F1(4, 1, 3) F1(4, 2, 3)
   F1(8, 1, 2) F1(8, 2, 2) F1(8, 1, 3) F1(8, 2, 3)
   F1(12, 1, 2) F1(12, 2, 2) F1(12, 1, 3) F1(12, 2, 3)

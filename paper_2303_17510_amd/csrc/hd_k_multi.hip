@@ -8,9 +8,10 @@ namespace hd {
 // centered row with tneg blocks left of index 0 the signed block tau - p once
 // tau >= p - tneg (the p-point DFT is periodic in the block index).
 __device__ __forceinline__ int signed_block(int tau, int p, int tneg) { return tau < p - tneg ? tau : tau - p; }
-// zeta_q^{v t} index for a signed block t (|v t| < q)
+// zeta_q^{v t} index for a signed block t, -p <= t < p: v < n and q = n p,
+// so |v t| < q and one conditional add reduces it (no division).
 __device__ __forceinline__ int zq_index(int v, int t, int q) {
-  const int k = (v * t) % q;
+  const int k = v * t;
   return k < 0 ? k + q : k;
 }
 
@@ -34,7 +35,7 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
     for (int e = 0; e < E; ++e) {
       const int tau = g + G * e;
       if constexpr (FOLD) {
-        y[n][e] = cmul(x[e], a.zq[(v * tau) % q]) + cmul(x1[FOLD ? e : 0], a.zq[zq_index(v, tau - p, q)]);
+        y[n][e] = cmul(x[e], a.zq[v * tau]) + cmul(x1[FOLD ? e : 0], a.zq[zq_index(v, tau - p, q)]);
       } else {
         y[n][e] = cmul(x[e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
       }
@@ -72,13 +73,17 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int tau = g + G * e;
+    // position i of the row (Hermitian rows: the signed index i - H of the
+    // stored half, mirrored)
+    auto ld = [&](int64_t i) -> cpx<T> {
+      if (i < 0 || i >= L) return czero<T>();
+      return a.herm ? herm_value(src, i - H) : src[i];
+    };
     if constexpr (FOLD) {
-      const int64_t i0 = (int64_t)tau * m + s + H, i1 = (int64_t)(tau - a.p) * m + s + H;
-      x[e] = i0 < L ? src[i0] : czero<T>();
-      x1[FOLD ? e : 0] = (i1 >= 0 && i1 < L) ? src[i1] : czero<T>();
+      x[e] = ld((int64_t)tau * m + s + H);
+      x1[FOLD ? e : 0] = ld((int64_t)(tau - a.p) * m + s + H);
     } else {
-      const int64_t i = (int64_t)signed_block(tau, a.p, tneg) * m + s + H;
-      x[e] = (i >= 0 && i < L) ? src[i] : czero<T>();
+      x[e] = ld((int64_t)signed_block(tau, a.p, tneg) * m + s + H);
     }
   }
   __syncthreads();
@@ -104,11 +109,11 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   const bool valid = R2 < a.nrows;
   const int u = (int)(R2 % p);
   const int dv = (int)((R2 / p) % a.D);
-  const uint64_t qm = (uint64_t)a.qm;
-  // twiddle exponent r s mod qm for s = g + G e: start and step
-  const uint64_t r = (uint64_t)u * a.n + a.v0 + dv;
-  const uint32_t ex0 = (uint32_t)((r * (uint32_t)g) % qm);
-  const uint32_t st = (uint32_t)((r * (uint32_t)G) % qm);
+  // twiddle exponent r s for s = g + G e: start and step; r < q and g, G < m,
+  // so both stay below q m without reduction
+  const uint32_t r = (uint32_t)u * (uint32_t)a.n + (uint32_t)(a.v0 + dv);
+  const uint32_t ex0 = r * (uint32_t)g;
+  const uint32_t st = r * (uint32_t)G;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
 
@@ -167,7 +172,7 @@ __device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T>
     for (int e = 0; e < E; ++e) {
       const int tau = g + G * e;
       if constexpr (FOLD) {
-        acc[e] = acc[e] + cmulc(y[n][e], a.zq[(v * tau) % q]);
+        acc[e] = acc[e] + cmulc(y[n][e], a.zq[v * tau]);
         acc1[FOLD ? e : 0] = acc1[FOLD ? e : 0] + cmulc(y[n][e], a.zq[zq_index(v, tau - p, q)]);
       } else {
         acc[e] = acc[e] + cmulc(y[n][e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
@@ -203,16 +208,19 @@ __global__ void __launch_bounds__(512) k_cols_bwd(ColBwdArgs<T> a) {
   if (dv < a.D) cols_bwd_residues<T, E, 1, FOLD>(a, acc, acc1, dv, g, s, row, tneg, tw, xb);
   cpx<T>* dst = a.tasks ? a.tasks[row].out : a.out + row * a.out_stride;
   double* acc64 = a.acc ? a.acc + 2 * row * a.out_stride : nullptr;
+  // Hermitian rows keep the outputs c = i - H >= 0, at c
+  const int64_t lo = a.herm ? H : 0, osh = a.herm ? H : 0;
+  auto put = [&](int64_t i, cpx<T> v) {
+    if (i >= lo && i < L) acc_store(dst, acc64, a.acc_mode, i - osh, v, a.scale);
+  };
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int tau = g + G * e;
     if constexpr (FOLD) {
-      const int64_t i0 = (int64_t)tau * m + s + H, i1 = (int64_t)(tau - a.p) * m + s + H;
-      if (i0 < L) acc_store(dst, acc64, a.acc_mode, i0, acc[e], a.scale);
-      if (i1 >= 0 && i1 < L) acc_store(dst, acc64, a.acc_mode, i1, acc1[FOLD ? e : 0], a.scale);
+      put((int64_t)tau * m + s + H, acc[e]);
+      put((int64_t)(tau - a.p) * m + s + H, acc1[FOLD ? e : 0]);
     } else {
-      const int64_t i = (int64_t)signed_block(tau, a.p, tneg) * m + s + H;
-      if (i >= 0 && i < L) acc_store(dst, acc64, a.acc_mode, i, acc[e], a.scale);
+      put((int64_t)signed_block(tau, a.p, tneg) * m + s + H, acc[e]);
     }
   }
 }

@@ -11,10 +11,25 @@ namespace hd {
 struct CtrShift {
   int64_t tneg, sh;
 };
+template <int P>
 __device__ __forceinline__ CtrShift ctr_shift(int ctr, int64_t L, int m) {
-  const int64_t H = ctr ? L / 2 : 0;
-  const int64_t tneg = (H + m - 1) / m;
+  // a centered dimension spans two blocks unless L = 1, so P = 1 never shifts
+  const int64_t H = (P == 2 && ctr) ? L / 2 : 0;
+  const int64_t tneg = H ? (H + m - 1) / m : 0;
   return CtrShift{tneg, tneg * m - H};
+}
+
+// Residue twiddle exponents of the direct form without division: for r < q
+// and g < G <= m, r g and r G stay below qm; block t starts at the signed
+// index (t - tneg) m + g, whose exponent is r g + m ((r (t - tneg)) mod q)
+// with t - tneg in {-1, 0, 1} (P <= 2).
+__device__ __forceinline__ uint32_t block_exp(uint32_t r, int t, int64_t tneg, uint32_t g, uint32_t m,
+                                              uint32_t qm) {
+  const int64_t d = t - tneg;
+  const uint32_t rm = r * m;
+  const uint32_t add = d == 0 ? 0u : (d > 0 ? rm : (rm ? qm - rm : 0u));
+  const uint32_t e = r * g + add;
+  return e >= qm ? e - qm : e;
 }
 
 // Outer dimension, direct form, forward: S adjacent columns per workgroup.
@@ -30,7 +45,7 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
   const cpx<T>* src = a.in[ai] + b * a.in_bstride + col;
-  const CtrShift cs = ctr_shift(a.ctr, a.L, m);
+  const CtrShift cs = ctr_shift<P>(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
@@ -45,18 +60,15 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
     }
   __syncthreads();
   for (int dr = 0; dr < a.D; ++dr) {
-    const int64_t r = a.r0 + dr;
-    // exponent r c = r j - r tneg m, kept in [0, qm)
-    const int64_t rneg = qm - (r * cs.tneg * m) % qm;
+    const int64_t r = a.r0 + dr;  // r < q
+    const uint32_t st = (uint32_t)r * (uint32_t)G;
     cpx<T> w[1][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)((r * (t * m + g) + rneg) % qm);
-      const uint32_t st = (uint32_t)((r * G) % qm);
-      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
-    }
+    for (int t = 0; t < P; ++t)
+      a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
+                            [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
     gfft_any<T, E, +1, 1, kCtOuter>(w, g, a.fd, tw, xb);
     if (valid) {
       cpx<T>* dst = a.out[ai] + ((b * a.D + dr) * m) * R + col;
@@ -77,7 +89,7 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
   const int64_t b = blockIdx.y;
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
-  const CtrShift cs = ctr_shift(a.ctr, a.L, m);
+  const CtrShift cs = ctr_shift<P>(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
@@ -89,19 +101,17 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
   for (int dr = 0; dr < a.D; ++dr) {
-    const int64_t r = a.r0 + dr;
+    const int64_t r = a.r0 + dr;  // r < q
+    const uint32_t st = (uint32_t)r * (uint32_t)G;
     const cpx<T>* src = a.y + ((b * a.D + dr) * m) * R + col;
     cpx<T> y[1][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) y[0][e] = valid ? src[(int64_t)(g + G * e) * R] : czero<T>();
     gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
-    const int64_t rneg = qm - (r * cs.tneg * m) % qm;
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      const uint32_t ex0 = (uint32_t)((r * (t * m + g) + rneg) % qm);
-      const uint32_t st = (uint32_t)((r * G) % qm);
-      a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
-    }
+    for (int t = 0; t < P; ++t)
+      a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
+                            [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
   }
   if (!valid) return;
   cpx<T>* dst = a.out + b * a.out_bstride + col;
@@ -130,8 +140,12 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
     const cpx<T>* src = a.src + ((i0 + o0) * Sx[1] + i1 + o1) * Sx[2] + o2;
     cpx<T>* dst = a.dst + row * D[2];
     for (int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i2 < D[2];
-         i2 += (int64_t)gridDim.x * blockDim.x)
-      dst[i2] = (in_src && i2 + o2 < Sx[2]) ? src[i2] : czero<T>();
+         i2 += (int64_t)gridDim.x * blockDim.x) {
+      if (a.herm && a.pad)  // 1D Hermitian padding: the centered array around hH
+        dst[i2] = i2 <= 2 * a.hH ? herm_value(a.src, i2 - a.hH) : czero<T>();
+      else
+        dst[i2] = (in_src && i2 + o2 < Sx[2]) ? src[i2] : czero<T>();
+    }
   }
 }
 

@@ -35,6 +35,17 @@ __host__ __device__ constexpr int xwords_rows(int m, int ps, int rows_per_block,
 }
 __host__ __device__ constexpr int xwords_cols(int p, int S, int nt) { return nt * p * S; }
 
+// Hermitian rows store f_0 .. f_{Lh-1} of a centered array with
+// f_{-c} = conj(f_c): the value at the signed index c (|c| < Lh), with the
+// centre taken real.
+template <typename T>
+__device__ __forceinline__ cpx<T> herm_value(const cpx<T>* src, int64_t c) {
+  cpx<T> v = src[c < 0 ? -c : c];
+  if (c < 0) v.y = -v.y;
+  if (c == 0) v.y = T(0);
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, int64_t i, cpx<T> v, T scale) {
   if (mode == ACC_WRITE) {

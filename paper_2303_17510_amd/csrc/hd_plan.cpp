@@ -381,7 +381,9 @@ static bool choose_dim_centered(int64_t L, int64_t M, int A, int tbytes, bool co
         if (p > kMaxColP) break;
         DimPlan c;
         if (!set_geom(&c, L, M, mm, p, VAR_MULTI, 1)) continue;
-        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 512)) ? 16 : 8;
+        // FP32 rows of 4096 points and more: 16 points per lane (measured
+        // faster from 384 rows on, the fewest a centered 2^20 plan has)
+        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 256)) ? 16 : 8;
         if (!finish_dim(&c, A, tbytes, &w)) continue;
         const double key = (double)(c.q * c.m) * 1e3 + std::fabs(std::log2((double)mm / 4096.0));
         if (!found || key < best_key) {

@@ -38,6 +38,8 @@ struct DimPlan {
   int rows_per_block = 0;     // rows per workgroup (fused / row kernels)
   int tw_pref = 0;            // twiddles: 0 choose, 1 two-level table, 2 per-stage tables
   int ctr = 0;                // 1: centered convolution (indices -H .. L-1-H, H = floor(L/2))
+  int herm = 0;               // 1: Hermitian rows: L = 2 Lh - 1 is the full centered length, the
+                              // arrays hold f_0 .. f_{Lh-1} (f_{-c} = conj f_c); implies ctr
 };
 
 // Blocks of m points a centered dimension spans (the centered transform of

@@ -58,6 +58,12 @@ def centered_min_padding(L: int, A: int = 2) -> int:
     return max(A * P + H, P + A * H) + 1
 
 
+def hermitian_min_padding(L: int, A: int = 2) -> int:
+    """Least M of a Hermitian dimension of nominal length L: the stored
+    ceil(L/2) entries stand for the centered length 2 ceil(L/2) - 1."""
+    return centered_min_padding(2 * ((L + 1) // 2) - 1, A)
+
+
 class Plan:
     """A planned convolution of ``A`` inputs of shape ``L`` padded to ``M``.
 
@@ -67,25 +73,32 @@ class Plan:
     ``centered``: arrays hold the indices -L//2 .. L-1-L//2 (index 0 at
     position L//2) and the result is the centered convolution; ``M`` then
     defaults to the centered minimum (3L/2 for A = 2, even L).
+    ``hermitian`` (1D): arrays hold the ``ceil(L/2)`` non-negative indices of
+    a Hermitian centered array (``f_{-c} = conj f_c``), and so does the
+    output; ``M`` defaults to the Hermitian minimum.
     """
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
-                 db_path: str | None = None, centered: bool = False):
+                 db_path: str | None = None, centered: bool = False, hermitian: bool = False):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
-            M = tuple(centered_min_padding(l, A) if centered else A * l for l in L)
+            M = tuple(hermitian_min_padding(l, A) if hermitian else
+                      (centered_min_padding(l, A) if centered else A * l) for l in L)
         M = (int(M),) if isinstance(M, int) else tuple(int(v) for v in M)
         self.L, self.M, self.A, self.B, self.dims = L, M, A, B, dims
         self.dtype_code = dtype_code(dtype)
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.method = _METHODS[method]
-        opt.flags = (_L.PLAN_HOST_ONLY if host_only else 0) | (_L.PLAN_CENTERED if centered else 0)
-        self.centered = bool(centered)
+        opt.flags = ((_L.PLAN_HOST_ONLY if host_only else 0) | (_L.PLAN_CENTERED if centered else 0) |
+                     (_L.PLAN_HERMITIAN if hermitian else 0))
+        self.centered, self.hermitian = bool(centered), bool(hermitian)
+        # shape of the arrays passed in and out
+        self.io_shape = tuple((l + 1) // 2 for l in L) if hermitian else L
         if dims > 3 or len(M) != dims:
             raise ValueError("L and M need 1 to 3 matching dimensions")
         for d, v in enumerate(_tup(m, dims)):
@@ -131,7 +144,7 @@ class Plan:
             dims.append({"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
                          "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p,
                          "S": di.S, "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p,
-                         "centered": bool(di.centered)})
+                         "centered": bool(di.centered), "hermitian": di.centered == 2})
         return {"dims": dims, "A": out.A, "B": out.B, "dtype": "c64" if out.dtype == 0 else "c128",
                 "method": {1: "hybrid", 2: "explicit"}.get(out.method, "auto"),
                 "npad": list(out.npad)[: out.dims], "workspace_bytes": out.workspace_bytes,
@@ -147,9 +160,9 @@ class Plan:
         want = torch.complex64 if self.dtype_code == _L.C64 else torch.complex128
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError("%s must be a CUDA (HIP) tensor" % name)
-        if t.dtype != want or tuple(t.shape) != self.L or not t.is_contiguous():
+        if t.dtype != want or tuple(t.shape) != self.io_shape or not t.is_contiguous():
             raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
-                             % (name, want, self.L, t.dtype, tuple(t.shape)))
+                             % (name, want, self.io_shape, t.dtype, tuple(t.shape)))
 
     def execute(self, inputs, out, stream=None):
         """Run asynchronously on ``stream`` (default: torch's current stream)."""
@@ -216,10 +229,11 @@ class BatchPlan:
 
     def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True,
                  tuner: str = "heuristic", model=None, tune_reps: int = 5, margin: float = 0.05,
-                 centered: bool = False):
+                 centered: bool = False, hermitian: bool = False):
         Ls = [int(v) for v in Ls]
         if Ms is None:
-            Ms = [centered_min_padding(v, A) if centered else A * v for v in Ls]
+            Ms = [hermitian_min_padding(v, A) if hermitian else
+                  (centered_min_padding(v, A) if centered else A * v) for v in Ls]
         Ms = [int(v) for v in Ms]
         if len(Ms) != len(Ls):
             raise ValueError("Ls and Ms differ in length")
@@ -227,8 +241,10 @@ class BatchPlan:
         self.dtype_code = dtype_code(dtype)
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
-        opt.flags = (0 if graph else _L.BATCH_NO_GRAPH) | (_L.PLAN_CENTERED if centered else 0)
-        self.centered = bool(centered)
+        opt.flags = ((0 if graph else _L.BATCH_NO_GRAPH) | (_L.PLAN_CENTERED if centered else 0) |
+                     (_L.PLAN_HERMITIAN if hermitian else 0))
+        self.centered, self.hermitian = bool(centered), bool(hermitian)
+        self.io_lengths = [(v + 1) // 2 for v in Ls] if hermitian else list(Ls)
         opt.tuner = {"heuristic": _L.TUNER_HEURISTIC, "exhaustive": _L.TUNER_EXHAUSTIVE,
                      "model": _L.TUNER_MODEL}[tuner]
         opt.tune_reps = int(tune_reps)
@@ -255,7 +271,7 @@ class BatchPlan:
         return [{"variant": _L.VARIANT_NAMES[arr[g].variant], "m": arr[g].m, "p": arr[g].p, "n": arr[g].n,
                  "q": arr[g].q, "E_m": arr[g].E_m, "E_p": arr[g].E_p, "S": arr[g].S,
                  "rows_per_block": arr[g].rows_per_block, "count": cnt[g], "Lmax": arr[g].L,
-                 "centered": bool(arr[g].centered)}
+                 "centered": bool(arr[g].centered), "hermitian": arr[g].centered == 2}
                 for g in range(min(ng.value, cap))]
 
     def bind(self, inputs, outputs) -> "BoundBatch":
@@ -272,9 +288,9 @@ class BatchPlan:
             if len(ins) != self.A:
                 raise ValueError("convolution %d needs %d inputs" % (i, self.A))
             for t in list(ins) + [outputs[i]]:
-                if not t.is_cuda or t.dtype != want or t.numel() != self.Ls[i] or not t.is_contiguous():
+                if not t.is_cuda or t.dtype != want or t.numel() != self.io_lengths[i] or not t.is_contiguous():
                     raise ValueError("convolution %d: tensors must be contiguous %s CUDA vectors of length %d"
-                                     % (i, want, self.Ls[i]))
+                                     % (i, want, self.io_lengths[i]))
             ptrs.extend(t.data_ptr() for t in ins)
         ins_c = (ctypes.c_void_p * len(ptrs))(*ptrs)
         outs_c = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outputs])

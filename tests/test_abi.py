@@ -241,3 +241,38 @@ def test_centered_multidim_and_explicit_plans():
             assert d["centered"] and d["q"] * d["m"] == 384
     with Plan((1024,), centered=True, method="explicit", host_only=True) as p:
         assert p.info()["npad"] == [1536]
+
+
+# ----------------------------------------------------- Hermitian plans ----
+@pytest.mark.parametrize("L,A", [(1, 2), (2, 2), (7, 2), (8, 2), (1024, 2), (1023, 3)])
+def test_hermitian_padding_rule(L, A):
+    Lh = (L + 1) // 2
+    Mh = (A + 1) * (Lh - 1) + 1  # the centered minimum of the full length 2 Lh - 1
+    with Plan((L,), (Mh,), A=A, hermitian=True, host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["hermitian"] and d["L"] == 2 * Lh - 1 and d["q"] * d["m"] >= Mh
+        assert p.io_shape == (Lh,)
+        # the stored halves are what the kernels read and write
+        assert p.info()["compulsory_bytes"] == (A + 1) * Lh * 8
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((L,), (Mh - 1,), A=A, hermitian=True, host_only=True)
+    assert ei.value.code == _lib.EINVAL
+
+
+def test_hermitian_is_one_dimensional():
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((16, 16), hermitian=True, host_only=True)
+    assert ei.value.code == _lib.EUNSUPPORTED
+    # the paper's Hermitian benchmark padding M = 3L/2 is accepted
+    with Plan((1 << 20,), (3 << 19,), hermitian=True, host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["q"] * d["m"] >= 3 << 19
+
+
+def test_explicit_c128_long_rows_split():
+    # one 8192-point complex128 row of A = 2 inputs does not fit LDS: the
+    # explicit method splits N' = p m instead of failing
+    for L, M in (((4097,), (8193,)), ((5000,), (9999,))):
+        with Plan(L, M, dtype="c128", method="explicit", host_only=True) as p:
+            d = p.info()["dims"][0]
+            assert d["variant"] == "multipass" and d["p"] * d["m"] == p.info()["npad"][0]
