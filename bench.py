@@ -61,6 +61,10 @@ def workload(name: str):
         return {"workload": "2D centered complex conv, A=2, B=1, 2048x2048, M=3072x3072, complex64, Gaussian, hybrid",
                 "L": [2048, 2048], "M": [3072, 3072], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss",
                 "centered": True}
+    if name == "c2_hermitian":
+        return {"workload": "1D Hermitian complex conv, A=2, B=1, L=2^20 (2^19 stored), M=3*2^19, complex64, "
+                            "unit disk, hybrid",
+                "L": [1 << 20], "M": [3 << 19], "A": 2, "dtype": "c64", "config_id": 1, "hermitian": True}
     raise SystemExit("unknown workload " + name)
 
 
@@ -69,7 +73,8 @@ def make_inputs(wl, dtype):
     import torch
     from paper_2303_17510_amd import synth
     npdt = np.complex64 if dtype == "c64" else np.complex128
-    xs = synth.inputs(wl["config_id"], wl["A"], tuple(wl["L"]), wl.get("dist", "disk"), dtype=npdt)
+    shape = tuple((l + 1) // 2 for l in wl["L"]) if wl.get("hermitian") else tuple(wl["L"])
+    xs = synth.inputs(wl["config_id"], wl["A"], shape, wl.get("dist", "disk"), dtype=npdt)
     return xs, [torch.from_numpy(x).cuda() for x in xs]
 
 
@@ -142,12 +147,14 @@ def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None, **plan_kw):
         kw["m"] = m
     if wl.get("centered"):
         kw["centered"] = True
+    if wl.get("hermitian"):
+        kw["hermitian"] = True
     with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method, tuner=tuner, **kw) as p:
         plan_s = time.perf_counter() - t0
         info = p.info()
         ms, stats, out = time_plan(p, dev, steps, warmup)
     name, avg_ms, bpl, agg = dominant(stats)
-    n_out = 1
+    n_out = 1  # outputs of the convolution (a Hermitian result of length L has L entries, half stored)
     for l in wl["L"]:
         n_out *= l
     r = {"stats": stats, "info": info, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
@@ -308,7 +315,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c2", "c2_1p5m", "c4", "c5_3d", "c2_centered",
-                                                         "c4_centered"])
+                                                         "c4_centered", "c2_hermitian"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-compare", action="store_true", help="skip explicit / FP64 / other-size legs")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -413,6 +420,12 @@ def main():
             put("centered_2048x2048_hybrid_c64", lambda: leg(wc4, "c64", "hybrid", 20, 3))
             put("centered_2048x2048_hybrid_c64_tuned", lambda: leg(wc4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
             put("centered_2048x2048_explicit_c64", lambda: leg(wc4, "c64", "explicit", 10, 2))
+            # Hermitian convolutions (half storage, M = 3L/2)
+            wh = workload("c2_hermitian")
+            for dt in ("c64", "c128"):
+                put("hermitian_1M_hybrid_%s" % dt, lambda: leg(wh, dt, "hybrid", sc, 5))
+                put("hermitian_1M_hybrid_%s_tuned" % dt, lambda: leg(wh, dt, "hybrid", sc, 5, tuner="exhaustive"))
+                put("hermitian_1M_explicit_%s" % dt, lambda: explicit_best(wh, dt, sc, 5))
         for v in compare.values():
             v.pop("stats", None)
             v.pop("info", None)
