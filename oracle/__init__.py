@@ -80,11 +80,13 @@ def _bind(path: str):
     lib.oracle_direct_centered.argtypes = [_dblp, _i64p, _i64p, _dblp, _i64p, _i64p, ctypes.c_int, _i64p, _i64p,
                                            _i64p, ctypes.c_int64, _dblp]
     lib.oracle_hermitian_expand.argtypes = [_dblp, ctypes.c_int64, _dblp]
+    lib.oracle_hermitian_expand_nd.argtypes = [_dblp, _i64p, ctypes.c_int64, _dblp]
     lib.oracle_padded_dft.argtypes = [_dblp, ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _dblp]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     for fn in ("oracle_direct2", "oracle_fft", "oracle_fft_nd", "oracle_explicit", "oracle_explicit_centered",
-               "oracle_direct_centered", "oracle_hermitian_expand", "oracle_padded_dft", "oracle_num_threads",
+               "oracle_direct_centered", "oracle_hermitian_expand", "oracle_hermitian_expand_nd",
+               "oracle_padded_dft", "oracle_num_threads",
                "oracle_set_num_threads"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
@@ -253,37 +255,67 @@ def conv_centered_explicit(inputs) -> np.ndarray:
 
 
 def hermitian_expand(f) -> np.ndarray:
-    """The centered array ``f_{-(Lh-1)} .. f_{Lh-1}`` (``f_{-j} = conj(f_j)``,
-    ``f_0`` real) that ``Lh`` stored entries ``f_0 .. f_{Lh-1}`` stand for."""
-    f = _c128(f).ravel()
-    out = np.empty(2 * f.size - 1, dtype=np.complex128)
-    rc = _load().oracle_hermitian_expand(_dp(f), f.size, _dp(out))
+    """The centered array that a stored Hermitian half stands for.
+
+    1D: ``Lh`` entries ``f_0 .. f_{Lh-1}`` give ``f_{-(Lh-1)} .. f_{Lh-1}``
+    with ``f_{-j} = conj(f_j)`` and ``f_0`` real.  2D/3D: a box whose last
+    axis holds ``c = 0 .. Lh-1`` and whose outer axes (odd extents) hold
+    centered signed indices gives the box with ``c = -(Lh-1) .. Lh-1``,
+    ``F(k, -c) = conj F(-k, c)`` and the ``c = 0`` plane replaced by its
+    Hermitian part."""
+    f = _c128(f)
+    if f.ndim <= 1:
+        f = f.ravel()
+        out = np.empty(2 * f.size - 1, dtype=np.complex128)
+        rc = _load().oracle_hermitian_expand(_dp(f), f.size, _dp(out))
+        if rc != 0:
+            raise ValueError("oracle_hermitian_expand failed (%d)" % rc)
+        return out
+    if f.ndim > 3:
+        raise ValueError("1 to 3 dimensions")
+    outer = list(f.shape[:-1])
+    n = np.array(([1] * (2 - len(outer))) + outer, dtype=np.int64)
+    Lh = f.shape[-1]
+    out = np.empty(tuple(outer) + (2 * Lh - 1,), dtype=np.complex128)
+    rc = _load().oracle_hermitian_expand_nd(_dp(f), _ip(n), Lh, _dp(out))
     if rc != 0:
-        raise ValueError("oracle_hermitian_expand failed (%d)" % rc)
+        raise ValueError("oracle_hermitian_expand_nd failed (%d): outer extents must be odd" % rc)
     return out
 
 
+def _herm_inputs(inputs):
+    ins = [_c128(x) for x in inputs]
+    if len(ins) not in (2, 3) or any(x.shape != ins[0].shape for x in ins):
+        raise ValueError("need 2 or 3 inputs of one shape")
+    return ins
+
+
 def conv_hermitian_direct(inputs, idx=None) -> np.ndarray:
-    """OH: Hermitian convolution of ``A`` (2 or 3) stored halves of one length
-    ``Lh`` (1D); returns ``h_0 .. h_{Lh-1}`` (or the entries ``idx``)."""
-    ins = [_c128(x).ravel() for x in inputs]
-    if len(ins) not in (2, 3) or any(x.size != ins[0].size for x in ins):
-        raise ValueError("need 2 or 3 inputs of one length")
-    Lh = ins[0].size
+    """OH: Hermitian convolution of ``A`` (2 or 3) stored halves of one shape
+    (1D, or 2D/3D with the Hermitian last axis); returns the stored half of
+    the result (or the flat entries ``idx`` of it)."""
+    ins = _herm_inputs(inputs)
+    shape = ins[0].shape if ins[0].ndim > 1 else (ins[0].size,)
+    Lh = shape[-1]
     full = [hermitian_expand(x) for x in ins]
-    pos = np.arange(Lh, dtype=np.int64) if idx is None else np.asarray(idx, dtype=np.int64).ravel()
-    if np.any(pos < 0) or np.any(pos >= Lh):
+    fshape = full[0].shape
+    n = int(np.prod(shape))
+    pos = np.arange(n, dtype=np.int64) if idx is None else np.asarray(idx, dtype=np.int64).ravel()
+    if np.any(pos < 0) or np.any(pos >= n):
         raise ValueError("idx out of range")
-    return conv_centered_direct(full, idx=pos + (Lh - 1))
+    # stored entry (outer..., c) is entry (outer..., c + Lh - 1) of the expanded box
+    outer, c = np.divmod(pos, Lh)
+    fpos = outer * fshape[-1] + c + (Lh - 1)
+    out = conv_centered_direct(full, idx=fpos)
+    return out if idx is not None else out.reshape(shape)
 
 
 def conv_hermitian_explicit(inputs) -> np.ndarray:
     """OH by explicit zero padding of the expanded arrays."""
-    ins = [_c128(x).ravel() for x in inputs]
-    if len(ins) not in (2, 3) or any(x.size != ins[0].size for x in ins):
-        raise ValueError("need 2 or 3 inputs of one length")
-    Lh = ins[0].size
-    return conv_centered_explicit([hermitian_expand(x) for x in ins])[Lh - 1:]
+    ins = _herm_inputs(inputs)
+    Lh = ins[0].shape[-1] if ins[0].ndim > 1 else ins[0].size
+    full = conv_centered_explicit([hermitian_expand(x) for x in ins])
+    return full[..., Lh - 1:]
 
 
 def padded_dft(f, N: int, ks) -> np.ndarray:

@@ -41,7 +41,8 @@
  *      array it stands for is the centered f_{-(Lh-1)} .. f_{Lh-1} with
  *      f_{-j} = conj(f_j) (f_0 taken real).  The result is the centered
  *      convolution of the expanded arrays at c = 0 .. Lh-1.  The expansion is
- *      here (oracle_hermitian_expand); the sums are OC's.
+ *      here (oracle_hermitian_expand, and oracle_hermitian_expand_nd for 2D/3D
+ *      arrays whose last axis is the Hermitian one); the sums are OC's.
  *
  *  PD  the padded DFT of Sec. 2, F_k = sum_{j<L} zeta_N^{kj} f_j with
  *      zeta_N = exp(+2 pi i / N), evaluated term by term at requested k with
@@ -402,6 +403,48 @@ int oracle_hermitian_expand(const double* f, int64_t Lh, double* out) {
     out[2 * (c + H)] = re;
     out[2 * (c + H) + 1] = im;
   }
+  return 0;
+}
+
+/* OH in 2D/3D: f holds the stored box n[0] x n[1] x Lh (leading extents 1
+ * below 3D; outer extents odd) of the array F(k, c), k the signed outer
+ * indices (centre (n-1)/2 per outer axis), c = 0 .. Lh-1 on the last axis;
+ * out (n[0] x n[1] x (2 Lh - 1)) receives F for c = -(Lh-1) .. Lh-1 with
+ *     F(k, -c) = conj F(-k, c)              (c > 0),
+ *     F(k, 0)  = (F(k, 0) + conj F(-k, 0)) / 2,
+ * the Hermitian symmetry F(-k, -c) = conj F(k, c) of a real function's
+ * coefficients (the c = 0 plane is replaced by its Hermitian part). */
+int oracle_hermitian_expand_nd(const double* f, const int64_t* n, int64_t Lh, double* out) {
+  if (Lh < 1 || n[0] < 1 || n[1] < 1 || n[0] % 2 == 0 || n[1] % 2 == 0) return -1;
+  const int64_t H = Lh - 1, W = 2 * Lh - 1;
+  for (int64_t i0 = 0; i0 < n[0]; ++i0)
+    for (int64_t i1 = 0; i1 < n[1]; ++i1) {
+      const int64_t r0 = n[0] - 1 - i0, r1 = n[1] - 1 - i1;  /* the reflected outer index -k */
+      for (int64_t c = -H; c <= H; ++c) {
+        const int64_t j = c < 0 ? -c : c;
+        const double* a = f + 2 * ((i0 * n[1] + i1) * Lh + j);
+        const double* b = f + 2 * ((r0 * n[1] + r1) * Lh + j);
+        double re, im;
+        if (c > 0) {
+          re = a[0];
+          im = a[1];
+        } else if (c < 0) {
+#if ORACLE_MUTANT == 10
+          re = b[0];
+          im = b[1];
+#else
+          re = b[0];
+          im = -b[1];
+#endif
+        } else {
+          re = 0.5 * (a[0] + b[0]);
+          im = 0.5 * (a[1] - b[1]);
+        }
+        double* o = out + 2 * ((i0 * n[1] + i1) * W + (c + H));
+        o[0] = re;
+        o[1] = im;
+      }
+    }
   return 0;
 }
 

@@ -394,3 +394,43 @@ def test_hermitian_delta_real_centre_and_sampling():
     # expansion: conjugate mirror around a real centre
     e = oracle.hermitian_expand(np.array([2 + 1j, 3 - 4j]))
     np.testing.assert_array_equal(e, np.array([3 + 4j, 2 + 0j, 3 - 4j]))
+
+
+@pytest.mark.parametrize("shape", [(5, 4), (3, 5, 3), (1, 6), (7, 1), (9, 7, 5)])
+def test_hermitian_nd_matches_real_function_product(shape):
+    # 2D/3D: the stored box (odd outer extents, last axis c = 0 .. Lh-1) is
+    # the half spectrum of a real function; numpy's inverse real FFT over all
+    # axes evaluates it (taking the Hermitian part of the c = 0 plane, as the
+    # definition does), the product of A such functions is sampled on a grid
+    # fine enough that no coefficient wraps, and numpy's real FFT reads the
+    # coefficients back at the signed outer indices.
+    outer, Lh = shape[:-1], shape[-1]
+    for A in (2, 3):
+        ins = [rnd(shape, 190 + k) for k in range(A)]
+        N = [A * (n - 1) + 1 for n in outer] + [2 * A * (Lh - 1) + 2]
+        prod = np.ones(N)
+        for x in ins:
+            spec = np.zeros(N[:-1] + [N[-1] // 2 + 1], complex)
+            pos = np.ix_(*[(np.arange(n) - (n - 1) // 2) % m for n, m in zip(outer, N[:-1])], np.arange(Lh))
+            spec[pos] = x
+            prod *= np.fft.irfftn(spec, s=N, axes=list(range(len(N)))) * np.prod(N)
+        coef = np.fft.rfftn(prod) / np.prod(N)
+        pos = np.ix_(*[(np.arange(n) - (n - 1) // 2) % m for n, m in zip(outer, N[:-1])], np.arange(Lh))
+        ref = coef[pos]
+        assert oracle.rel_l2(oracle.conv_hermitian_direct(ins), ref) < 1e-13
+        assert oracle.rel_l2(oracle.conv_hermitian_explicit(ins), ref) < 1e-13
+
+
+def test_hermitian_nd_delta_and_symmetric_plane():
+    g = rnd((5, 4), 195)
+    d = np.zeros((5, 4), complex)
+    d[2, 0] = 1.0  # outer index 0, c = 0
+    got = oracle.conv_hermitian_direct([d, g])
+    want = g.copy()
+    want[:, 0] = 0.5 * (g[:, 0] + np.conj(g[::-1, 0]))  # Hermitian part of the c = 0 column
+    np.testing.assert_allclose(got, want, atol=1e-15)
+    # a consistent c = 0 column is kept as it is
+    g[:, 0] = want[:, 0]
+    np.testing.assert_allclose(oracle.conv_hermitian_direct([d, g]), g, atol=1e-15)
+    with pytest.raises(ValueError):  # even outer extents have no symmetric range
+        oracle.hermitian_expand(np.zeros((4, 3), complex))
