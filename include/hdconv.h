@@ -64,7 +64,7 @@ enum {
   HDCONV_PLAN_HOST_ONLY = 1, /* plan geometry only: no device memory, cannot execute */
   HDCONV_BATCH_NO_GRAPH = 2, /* batched plans: launch eagerly on every execute      */
   HDCONV_PLAN_CENTERED = 4,  /* centered convolution (see below); plans and batches */
-  HDCONV_PLAN_HERMITIAN = 8  /* Hermitian convolution (see below); 1D plans and batches */
+  HDCONV_PLAN_HERMITIAN = 8  /* Hermitian convolution (see below); plans, 1D batches    */
 };
 
 /* Centered convolutions (the paper's section on centered convolutions in one
@@ -81,16 +81,20 @@ enum {
  * the arrays as they are and copies out entries (A-1)H .. (A-1)H+L-1.
  *
  * Hermitian convolutions (the paper's section on Hermitian symmetric
- * convolutions, eq. wHerDef and Alg. 2 with its Hermitian transforms), one
- * dimension.  With HDCONV_PLAN_HERMITIAN and nominal length L, each array
- * holds Lh = ceil(L/2) words f_0 .. f_{Lh-1} (the non-negative indices) of
- * the centered array f_{-(Lh-1)} .. f_{Lh-1} with f_{-c} = conj(f_c); the
- * imaginary part of f_0 is ignored (a Hermitian array has a real centre).  The
- * output holds h_0 .. h_{Lh-1} of the centered convolution of those arrays
- * (itself Hermitian).  Requires M >= (A+1)(Lh-1)+1 (3L/2 - 2 for A = 2 and
- * even L).  The kernels run the centered transforms of the full length
- * 2 Lh - 1, reading negative indices as conjugates of the stored half and
- * writing only the stored half. */
+ * convolutions, eq. wHerDef and Alg. 2 with its Hermitian transforms; Sec. 5
+ * with centered outer dimensions).  With HDCONV_PLAN_HERMITIAN and nominal
+ * length L of the last dimension, each array holds Lh = ceil(L/2) words
+ * f_0 .. f_{Lh-1} (the non-negative indices) of the centered array
+ * f_{-(Lh-1)} .. f_{Lh-1} with f_{-c} = conj(f_c); the imaginary part of f_0 is
+ * ignored (a Hermitian array has a real centre).  The output holds
+ * h_0 .. h_{Lh-1} of the centered convolution of those arrays (itself
+ * Hermitian).  Requires M >= (A+1)(Lh-1)+1 (3L/2 - 2 for A = 2 and even L).
+ * 2D/3D: the outer dimensions are centered (as HDCONV_PLAN_CENTERED) with odd
+ * extents, the stored box is L[0] x [L[1] x] Lh, and the array stands for
+ * F(k, -c) = conj F(-k, c) (k the signed outer indices), the c = 0 plane being
+ * taken as its Hermitian part.  The kernels run the centered transforms of the
+ * full length 2 Lh - 1, reading negative indices as conjugates of the stored
+ * half and writing only the stored half. */
 
 typedef struct hdconv_options {
   int method;        /* HDCONV_METHOD_*                                         */
@@ -126,10 +130,11 @@ typedef struct hdconv_dim_info {
   int S;             /* columns per workgroup (column / outer kernels)          */
   int rows_per_block;/* rows per workgroup (row kernels)                        */
   int tw_m, tw_p;    /* twiddle mode of the m- and p-point transforms (1 two-level, 2 per-stage) */
-  int centered;      /* 1: centered transforms (HDCONV_PLAN_CENTERED), 2: Hermitian
-                        (HDCONV_PLAN_HERMITIAN); shapes passed to
-                        hdconv_time_shape / hdconv_features take the flag from
-                        dimension 0's field                                    */
+  int centered;      /* 1: centered transforms (HDCONV_PLAN_CENTERED), 2: the
+                        Hermitian dimension (HDCONV_PLAN_HERMITIAN; its outer
+                        dimensions report 1); shapes passed to hdconv_time_shape /
+                        hdconv_features are Hermitian if the last dimension's
+                        field is 2, else centered if dimension 0's is 1        */
 } hdconv_dim_info_t;
 
 typedef struct hdconv_plan_info {
@@ -185,7 +190,7 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
 
 /* Run the convolution asynchronously on `stream` (a hipStream_t; NULL = the
  * null stream).  inputs: A device pointers, outputs: B device pointers, each
- * to prod(L) words of dtype (Hermitian plans: ceil(L/2) words).  outputs[0] may equal one of the inputs
+ * to prod(L) words of dtype (Hermitian plans: ceil(L/2) in the last dimension).  outputs[0] may equal one of the inputs
  * (in place, as in Algorithm 1); any other overlap is HDCONV_EINVAL.  The
  * inputs are not modified unless aliased by the output.  Returns the launch
  * status; no synchronisation is done. */

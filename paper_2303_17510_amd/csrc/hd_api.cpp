@@ -147,7 +147,9 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
                    P->method != HDCONV_METHOD_EXPLICIT) ? 1 : 0;
   for (int d = 0; d < P->dims; ++d) {
     const bool contiguous = (d == P->dims - 1);
-    int64_t Le = herm ? herm_full(P->L[d]) : P->L[d], Me = P->M[d];
+    // a Hermitian plan's last dimension runs at the full centered length
+    const int hd = herm && contiguous;
+    int64_t Le = hd ? herm_full(P->L[d]) : P->L[d], Me = P->M[d];
     if (P->method == HDCONV_METHOD_EXPLICIT) Le = Me = P->npad[d];
     DimPlan& dp = P->dp[d];
     std::string why;
@@ -206,7 +208,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
-      dp.herm = herm;
+      dp.herm = hd;
     } else {
       if (fv == HDCONV_VARIANT_AUTO) {
         Geometry g = geometry_c(Le, Me, fm ? fm : next_fft_size(Le), fp, false, ctr);
@@ -232,7 +234,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       dp.D = (opt && opt->D[d] > 0) ? std::min<int64_t>(opt->D[d], g.n) : g.n;
       dp.variant = fv;
       dp.ctr = ctr;
-      dp.herm = herm;
+      dp.herm = hd;
       if (opt) {
         dp.E_m = opt->E_m[d];
         dp.E_p = opt->E_p[d];
@@ -247,6 +249,10 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
   }
   return HDCONV_OK;
 }
+
+// Extent of dimension d as stored between passes: the engine length, or the
+// stored half of a Hermitian last dimension.
+static int64_t stored_extent(const DimPlan& dp) { return dp.herm ? herm_stored(dp.L) : dp.L; }
 
 // bytes moved by the kernels of one execute, by design (reads + writes)
 static double plan_traffic(const Plan* P, int* launches) {
@@ -270,7 +276,7 @@ static double plan_traffic(const Plan* P, int* launches) {
   for (int d = 0; d + 1 < P->dims; ++d) {
     const DimPlan& dp = P->dp[d];
     double rest = 1;
-    for (int e = d + 1; e < P->dims; ++e) rest *= (double)Le[e];
+    for (int e = d + 1; e < P->dims; ++e) rest *= (double)stored_extent(P->dp[e]);
     const double in_el = nb * Le[d] * rest, out_el = nb * dp.q * dp.m * rest;
     bytes += A * (in_el + out_el) * w + B * (out_el + in_el) * w;  // forward + backward
     nl += 2;
@@ -379,7 +385,7 @@ static int alloc_workspace(Plan* P) {
   size_t nb = (size_t)P->batch_rows;  // independent rows (batched groups), else 1
   for (int d = 0; d + 1 < P->dims; ++d) {
     size_t rest = 1;
-    for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)Le[e];
+    for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)stored_extent(P->dp[e]);
     nb *= (size_t)(P->dp[d].q * P->dp[d].m);
     for (int a = 0; a < P->A; ++a) want.push_back({&P->lvl[d][a], nb * rest * w});
   }
@@ -564,9 +570,9 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
         b.N[3 - P->dims + d] = P->npad[d];
       }
       b.pad = 1;
-      if (P->flags & HDCONV_PLAN_HERMITIAN) {  // 1D: the expanded centered array
+      if (P->flags & HDCONV_PLAN_HERMITIAN) {  // the expanded centered array
         b.herm = 1;
-        b.hH = P->Lio[0] - 1;
+        b.hH = P->Lio[P->dims - 1] - 1;
       }
       {
         double lt = 1, nt = 1;
@@ -589,7 +595,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
   for (int d = 0; d + 1 < P->dims; ++d) {
     const DimPlan& dp = P->dp[d];
     int64_t rest = 1;
-    for (int k = d + 1; k < P->dims; ++k) rest *= Le[k];
+    for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
     OuterFwdArgs<T> o{};
     for (int a = 0; a < A; ++a) {
       o.in[a] = cur[a];
@@ -627,7 +633,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     const DimPlan& dp = P->dp[d];
     nb /= dp.q * dp.m;
     int64_t rest = 1;
-    for (int k = d + 1; k < P->dims; ++k) rest *= Le[k];
+    for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
     OuterBwdArgs<T> o{};
     o.y = (const cpx<T>*)P->lvl[d][0];
     o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
@@ -665,8 +671,9 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
       // outputs -H .. L-1-H (the arrays were padded as they are, index c at
       // position c + H, so a product of A of them sits A H further on);
       // Hermitian: the outputs c >= 0 start at A H (H = Lh - 1)
-      if (P->flags & HDCONV_PLAN_HERMITIAN) b.off[3 - P->dims + d] = (int64_t)A * (P->Lio[d] - 1);
-      else if (P->flags & HDCONV_PLAN_CENTERED) b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
+      if ((P->flags & HDCONV_PLAN_HERMITIAN) && d == P->dims - 1) b.off[3 - P->dims + d] = (int64_t)A * (P->Lio[d] - 1);
+      else if (P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
+        b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
     }
     b.pad = 0;
     {
@@ -740,21 +747,25 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     return nullptr;
   }
   const bool herm = opt && (opt->flags & HDCONV_PLAN_HERMITIAN);
-  if (herm && dims != 1) {
-    set_err(HDCONV_EUNSUPPORTED, "Hermitian plans are one-dimensional in this build (got dims = %d)", dims);
-    return nullptr;
-  }
+  // 2D/3D Hermitian: the outer dimensions are centered with a symmetric index
+  // range, so their extents are odd
+  for (int d = 0; herm && d + 1 < dims; ++d)
+    if (L[d] % 2 == 0) {
+      set_err(HDCONV_EINVAL, "Hermitian plans need odd outer extents (L[%d] = %lld)", d, (long long)L[d]);
+      return nullptr;
+    }
   for (int d = 0; d < dims; ++d) {
     if (L[d] < 1 || L[d] > (int64_t(1) << 31)) {
       set_err(HDCONV_EINVAL, "L[%d] = %lld out of range", d, (long long)L[d]);
       return nullptr;
     }
     const bool ctr = opt && (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN));
-    const int64_t Mmin = herm ? centered_min_padding(herm_full(L[d]), A)
-                              : (ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1);
+    const bool hd = herm && d == dims - 1;
+    const int64_t Mmin = hd ? centered_min_padding(herm_full(L[d]), A)
+                            : (ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1);
     if (M[d] < Mmin) {
       set_err(HDCONV_EINVAL, "M[%d] = %lld is below %s = %lld, so the product would alias", d, (long long)M[d],
-              herm ? "the Hermitian minimum (A+1)(ceil(L/2)-1)+1"
+              hd ? "the Hermitian minimum (A+1)(ceil(L/2)-1)+1"
                    : (ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1"),
               (long long)Mmin);
       return nullptr;
@@ -792,7 +803,7 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
   for (int d = 0; d < dims; ++d) {
     P->L[d] = L[d];
-    P->Lio[d] = herm ? herm_stored(L[d]) : L[d];
+    P->Lio[d] = (herm && d == dims - 1) ? herm_stored(L[d]) : L[d];
     P->M[d] = M[d];
     if (P->method == HDCONV_METHOD_EXPLICIT) P->npad[d] = std::max<int64_t>(8, next_fft_size(M[d]));
   }
@@ -861,7 +872,9 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
     di.rows_per_block = dp.rows_per_block;
     di.tw_m = dp.fd_m.N ? dp.fd_m.twmode + 1 : 0;
     di.tw_p = dp.fd_p.N ? dp.fd_p.twmode + 1 : 0;
-    di.centered = (P->flags & HDCONV_PLAN_HERMITIAN) ? 2 : ((P->flags & HDCONV_PLAN_CENTERED) ? 1 : 0);
+    di.centered = ((P->flags & HDCONV_PLAN_HERMITIAN) && d == P->dims - 1)
+                      ? 2
+                      : ((P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) ? 1 : 0);
   }
   out->workspace_bytes = P->work_bytes;
   out->table_bytes = P->table_bytes;
@@ -993,8 +1006,8 @@ static hdconv_options opts_from_shape(const hdconv_dim_info_t* shp, int dims) {
   hdconv_options o;
   memset(&o, 0, sizeof(o));
   o.method = HDCONV_METHOD_HYBRID;
-  if (shp[0].centered == 1) o.flags |= HDCONV_PLAN_CENTERED;
-  if (shp[0].centered == 2) o.flags |= HDCONV_PLAN_HERMITIAN;
+  if (shp[dims - 1].centered == 2) o.flags |= HDCONV_PLAN_HERMITIAN;
+  else if (shp[0].centered == 1) o.flags |= HDCONV_PLAN_CENTERED;
   for (int d = 0; d < dims; ++d) {
     o.m[d] = shp[d].m;
     o.p[d] = shp[d].p;
@@ -1120,12 +1133,12 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
   // candidates are shapes of the engine's lengths (Hermitian: the full centered length)
   const bool herm = (opt->flags & HDCONV_PLAN_HERMITIAN) != 0;
   int64_t Lc[3];
-  for (int d = 0; d < dims; ++d) Lc[d] = herm ? herm_full(L[d]) : L[d];
+  for (int d = 0; d < dims; ++d) Lc[d] = (herm && d == dims - 1) ? herm_full(L[d]) : L[d];
   int rc = list_candidates(Lc, M, A, dims, dtype,
                            (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) ? 1 : 0, &cand, &varied);
   if (rc != HDCONV_OK) return rc;
-  if (herm)
-    for (auto& c : cand) c.centered = 2;
+  if (herm)  // the last dimension of every candidate is the Hermitian one
+    for (size_t k = 0; k < cand.size(); k += dims) cand[k + dims - 1].centered = 2;
   const int nc = (int)varied.size();
   *ncand = nc;
   *ntimed = 0;

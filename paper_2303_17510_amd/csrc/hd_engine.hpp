@@ -174,8 +174,8 @@ struct BoxCopyArgs {
   int64_t L[3], N[3];  // leading unused extents are 1
   int64_t off[3];      // truncation: dst[i] = src[i + off] (0, or the centered window start)
   int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
-  int herm;            // padding of a 1D Hermitian array: dst[c + hH] = f_c for |c| <= hH,
-  int64_t hH;          // with f_{-c} = conj f_c read from the L = hH + 1 stored entries
+  int herm;            // padding of a Hermitian array (stored box L, last axis c = 0 .. hH):
+  int64_t hH;          // the expanded centered box, F(k, -c) = conj F(-k, c)
 };
 
 // Launchers (return the launch status).  E, P and A select the template

@@ -141,9 +141,19 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
     cpx<T>* dst = a.dst + row * D[2];
     for (int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i2 < D[2];
          i2 += (int64_t)gridDim.x * blockDim.x) {
-      if (a.herm && a.pad)  // 1D Hermitian padding: the centered array around hH
-        dst[i2] = i2 <= 2 * a.hH ? herm_value(a.src, i2 - a.hH) : czero<T>();
-      else
+      if (a.herm && a.pad) {
+        // Hermitian padding: the expanded centered box, last-axis index
+        // c = i2 - hH; c < 0 reads the conjugate at the reflected outer
+        // position, c = 0 the Hermitian part of the stored plane
+        cpx<T> v = czero<T>();
+        if (i0 < a.L[0] && i1 < a.L[1] && i2 <= 2 * a.hH) {
+          const int64_t c = i2 - a.hH, j = c < 0 ? -c : c;
+          const cpx<T> f = a.src[(i0 * a.L[1] + i1) * a.L[2] + j];
+          const cpx<T> g = a.src[((a.L[0] - 1 - i0) * a.L[1] + (a.L[1] - 1 - i1)) * a.L[2] + j];
+          v = c > 0 ? f : (c < 0 ? mk(g.x, -g.y) : mk(T(0.5) * (f.x + g.x), T(0.5) * (f.y - g.y)));
+        }
+        dst[i2] = v;
+      } else
         dst[i2] = (in_src && i2 + o2 < Sx[2]) ? src[i2] : czero<T>();
     }
   }

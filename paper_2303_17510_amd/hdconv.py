@@ -73,9 +73,10 @@ class Plan:
     ``centered``: arrays hold the indices -L//2 .. L-1-L//2 (index 0 at
     position L//2) and the result is the centered convolution; ``M`` then
     defaults to the centered minimum (3L/2 for A = 2, even L).
-    ``hermitian`` (1D): arrays hold the ``ceil(L/2)`` non-negative indices of
-    a Hermitian centered array (``f_{-c} = conj f_c``), and so does the
-    output; ``M`` defaults to the Hermitian minimum.
+    ``hermitian``: the last dimension holds the ``ceil(L/2)`` non-negative
+    indices of a Hermitian centered array (``f_{-c} = conj f_c``; 2D/3D:
+    ``F(k, -c) = conj F(-k, c)`` with centered outer dimensions of odd
+    extent), and so does the output; ``M`` defaults to the minimum padding.
     """
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
@@ -86,8 +87,8 @@ class Plan:
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
-            M = tuple(hermitian_min_padding(l, A) if hermitian else
-                      (centered_min_padding(l, A) if centered else A * l) for l in L)
+            M = tuple(hermitian_min_padding(l, A) if (hermitian and d == dims - 1) else
+                      (centered_min_padding(l, A) if (centered or hermitian) else A * l) for d, l in enumerate(L))
         M = (int(M),) if isinstance(M, int) else tuple(int(v) for v in M)
         self.L, self.M, self.A, self.B, self.dims = L, M, A, B, dims
         self.dtype_code = dtype_code(dtype)
@@ -98,7 +99,7 @@ class Plan:
                      (_L.PLAN_HERMITIAN if hermitian else 0))
         self.centered, self.hermitian = bool(centered), bool(hermitian)
         # shape of the arrays passed in and out
-        self.io_shape = tuple((l + 1) // 2 for l in L) if hermitian else L
+        self.io_shape = L[:-1] + ((L[-1] + 1) // 2,) if hermitian else L
         if dims > 3 or len(M) != dims:
             raise ValueError("L and M need 1 to 3 matching dimensions")
         for d, v in enumerate(_tup(m, dims)):

@@ -259,10 +259,18 @@ def test_hermitian_padding_rule(L, A):
     assert ei.value.code == _lib.EINVAL
 
 
-def test_hermitian_is_one_dimensional():
+def test_hermitian_multidim_shapes():
+    # outer dimensions are centered with a symmetric (odd) range
     with pytest.raises(_lib.HdconvError) as ei:
         Plan((16, 16), hermitian=True, host_only=True)
-    assert ei.value.code == _lib.EUNSUPPORTED
+    assert ei.value.code == _lib.EINVAL
+    with Plan((33, 64), hermitian=True, host_only=True) as p:
+        assert p.io_shape == (33, 32)
+        dims = p.info()["dims"]
+        assert [d["hermitian"] for d in dims] == [False, True] and all(d["centered"] for d in dims)
+        assert dims[0]["q"] * dims[0]["m"] >= 49 and dims[1]["L"] == 63
+    with Plan((9, 11, 20), hermitian=True, method="explicit", host_only=True) as p:
+        assert p.io_shape == (9, 11, 10) and p.info()["npad"] == [16, 16, 32]
     # the paper's Hermitian benchmark padding M = 3L/2 is accepted
     with Plan((1 << 20,), (3 << 19,), hermitian=True, host_only=True) as p:
         d = p.info()["dims"][0]

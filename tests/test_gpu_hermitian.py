@@ -163,3 +163,38 @@ def test_hermitian_batched(gpu, dtype):
             for i, L in enumerate(Ls):
                 err = oracle.rel_l2(outs[i].cpu().numpy(), wants[i])
                 assert err <= TOL[dtype], (i, L, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape,kw", [
+    ((1, 5), {}), ((33, 64), {}), ((33, 63), {}), ((255, 512), {}), ((7, 3000), {"m": (0, 64), "variant": ("outer", "multipass")}),
+    ((9, 11, 20), {}), ((31, 31, 31), {}),
+    ((33, 64), {"method": "explicit"}), ((9, 11, 20), {"method": "explicit"}),
+])
+def test_hermitian_multidim(gpu, dtype, shape, kw):
+    # outer dimensions centered (odd extents), the last one Hermitian
+    import torch
+    say("hermitian nd case", shape, dtype, kw)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    with Plan(shape, dtype=dtype, hermitian=True, **kw) as p:
+        io = p.io_shape
+        xs = [synth.unit_disk(io, 7400 + a).astype(npdt) for a in range(2)]
+        dev = [torch.from_numpy(x).cuda() for x in xs]
+        info = p.info()
+        got = run(p, dev)
+    ins = [synth.as_oracle(x) for x in xs]
+    want = oracle.conv_hermitian_direct(ins) if np.prod(io) <= 6000 else oracle.conv_hermitian_explicit(ins)
+    err = oracle.rel_l2(got, want)
+    say("   ->", [(d["variant"], d["m"], d["p"], d["q"]) for d in info["dims"]], "err=%.3e" % err)
+    assert got.shape == io and err <= TOL[dtype]
+
+
+def test_hermitian_2d_tuned(gpu):
+    import torch
+    shape = (65, 128)
+    with Plan(shape, dtype="c64", hermitian=True, tuner="exhaustive", tune_reps=2) as p:
+        xs = [synth.unit_disk(p.io_shape, 7500 + a).astype(np.complex64) for a in range(2)]
+        got = run(p, [torch.from_numpy(x).cuda() for x in xs])
+        assert p.info()["timed_candidates"] > 1
+    want = oracle.conv_hermitian_explicit([synth.as_oracle(x) for x in xs])
+    assert oracle.rel_l2(got, want) <= TOL["c64"]
