@@ -65,6 +65,11 @@ def workload(name: str):
         return {"workload": "1D Hermitian complex conv, A=2, B=1, L=2^20 (2^19 stored), M=3*2^19, complex64, "
                             "unit disk, hybrid",
                 "L": [1 << 20], "M": [3 << 19], "A": 2, "dtype": "c64", "config_id": 1, "hermitian": True}
+    if name == "c4_hermitian":
+        return {"workload": "2D Hermitian complex conv, A=2, B=1, 2047x2048 (2047x1024 stored), M=3072x3072, "
+                            "complex64, Gaussian, hybrid",
+                "L": [2047, 2048], "M": [3072, 3072], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss",
+                "hermitian": True}
     raise SystemExit("unknown workload " + name)
 
 
@@ -73,7 +78,7 @@ def make_inputs(wl, dtype):
     import torch
     from paper_2303_17510_amd import synth
     npdt = np.complex64 if dtype == "c64" else np.complex128
-    shape = tuple((l + 1) // 2 for l in wl["L"]) if wl.get("hermitian") else tuple(wl["L"])
+    shape = tuple(wl["L"][:-1]) + ((wl["L"][-1] + 1) // 2,) if wl.get("hermitian") else tuple(wl["L"])
     xs = synth.inputs(wl["config_id"], wl["A"], shape, wl.get("dist", "disk"), dtype=npdt)
     return xs, [torch.from_numpy(x).cuda() for x in xs]
 
@@ -315,7 +320,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c2", "c2_1p5m", "c4", "c5_3d", "c2_centered",
-                                                         "c4_centered", "c2_hermitian"])
+                                                         "c4_centered", "c2_hermitian", "c4_hermitian"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-compare", action="store_true", help="skip explicit / FP64 / other-size legs")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -426,6 +431,10 @@ def main():
                 put("hermitian_1M_hybrid_%s" % dt, lambda: leg(wh, dt, "hybrid", sc, 5))
                 put("hermitian_1M_hybrid_%s_tuned" % dt, lambda: leg(wh, dt, "hybrid", sc, 5, tuner="exhaustive"))
                 put("hermitian_1M_explicit_%s" % dt, lambda: explicit_best(wh, dt, sc, 5))
+            wh4 = workload("c4_hermitian")
+            put("hermitian_2047x2048_hybrid_c64", lambda: leg(wh4, "c64", "hybrid", 20, 3))
+            put("hermitian_2047x2048_hybrid_c64_tuned", lambda: leg(wh4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
+            put("hermitian_2047x2048_explicit_c64", lambda: leg(wh4, "c64", "explicit", 10, 2))
         for v in compare.values():
             v.pop("stats", None)
             v.pop("info", None)

@@ -69,6 +69,7 @@ struct FusedArgs {
   int rows_per_block;
   int ctr;   // 1: centered rows (H = floor(L/2) of each row's own L)
   int herm;  // 1: Hermitian rows (half storage, see above)
+  int pair;  // 1: Hermitian rows transform two residues per complex transform
   T scale;  // 1/(q m)
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -104,6 +105,7 @@ struct RowConvArgs {
   int64_t nrows;  // rows of the work buffer (= batch * D * p)
   int m, p, n, v0, D;
   int rows_per_block;
+  int herm;  // 1: Hermitian plan transforming two (real-output) rows per slot
   int64_t qm;
   FftDesc fd;  // m points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)

@@ -79,46 +79,97 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   // (r < q, g < G <= m).  Block t starts at the signed index
   // c = (t - tneg) m + g, whose exponent is r g + m ((r (t - tneg)) mod q),
   // with t - tneg in {-1, 0, 1} (P <= 2).
-  for (int r = 0; r < a.q; ++r) {
-    const uint32_t eg = (uint32_t)r * (uint32_t)g, st = (uint32_t)r * (uint32_t)G;
-    auto ex_of = [&](int t) -> uint32_t {
-      const int d = t - (int)tneg;
-      const uint32_t rm = (uint32_t)r * (uint32_t)m;
-      const uint32_t add = d == 0 ? 0u : (d > 0 ? rm : (r ? qm - rm : 0u));
-      const uint32_t e = eg + add;
-      return e >= qm ? e - qm : e;
-    };
+  auto ex_of = [&](int r, int t) -> uint32_t {
+    const int d = t - (int)tneg;
+    const uint32_t rm = (uint32_t)r * (uint32_t)m;
+    const uint32_t add = d == 0 ? 0u : (d > 0 ? rm : (r ? qm - rm : 0u));
+    const uint32_t e = (uint32_t)r * (uint32_t)g + add;
+    return e >= qm ? e - qm : e;
+  };
+  // Hermitian rows: every residue transform is real (the paper's
+  // complex-to-real residue DFTs), so two residues r, r+1 share one complex
+  // transform per input: z = W_r + i W_{r+1} gives F_r = Re Z and
+  // F_{r+1} = Im Z; the products go back packed as P_r + i P_{r+1}, whose
+  // inverse Y splits by conjugate symmetry, y_r(s) = (Y(s) + conj Y(-s)) / 2
+  // and y_{r+1}(s) = (Y(s) - conj Y(-s)) / (2i).  Half the transforms.
+  for (int r = 0; r < a.q;) {
+    const bool pair = HERM && a.pair && r + 1 < a.q;  // uniform
     cpx<T> w[A][E];
 #pragma unroll
     for (int ai = 0; ai < A; ++ai)
 #pragma unroll
       for (int e = 0; e < E; ++e) w[ai][e] = czero<T>();
+    auto gather = [&](int rr, bool times_i) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      a.zqm.template run<E>(ex_of(t), st, [&](int e, cpx<T> z) {
+      for (int t = 0; t < P; ++t) {
+        a.zqm.template run<E>(ex_of(rr, t), (uint32_t)rr * (uint32_t)G, [&](int e, cpx<T> z) {
 #pragma unroll
-        for (int ai = 0; ai < A; ++ai) {
-          cpx<T> xv;
-          if constexpr (kKeep) xv = x[ai][t][e];
-          else xv = load(ai, t, e);
-          w[ai][e] = w[ai][e] + cmul(xv, z);
-        }
-      });
-    }
+          for (int ai = 0; ai < A; ++ai) {
+            cpx<T> xv;
+            if constexpr (kKeep) xv = x[ai][t][e];
+            else xv = load(ai, t, e);
+            const cpx<T> v = cmul(xv, z);
+            w[ai][e] = w[ai][e] + (times_i ? mk(-v.y, v.x) : v);
+          }
+        });
+      }
+    };
+    gather(r, false);
+    if constexpr (HERM)
+      if (pair) gather(r + 1, true);
     gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
     cpx<T> prod[1][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       cpx<T> pr = w[0][e];
+      if (HERM && pair) {
+        T pa = w[0][e].x, pb = w[0][e].y;
 #pragma unroll
-      for (int ai = 1; ai < A; ++ai) pr = cmul(pr, w[ai][e]);
+        for (int ai = 1; ai < A; ++ai) {
+          pa *= w[ai][e].x;
+          pb *= w[ai][e].y;
+        }
+        pr = mk(pa, pb);
+      } else {
+#pragma unroll
+        for (int ai = 1; ai < A; ++ai) pr = cmul(pr, w[ai][e]);
+      }
       prod[0][e] = pr;
     }
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
+    if constexpr (HERM) {
+      if (pair) {
+        // Y(-s) from the lane that holds it, through LDS
+        __syncthreads();
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      a.zqm.template run<E>(ex_of(t), st, [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
+        for (int e = 0; e < E; ++e) xb.at(0, g + G * e) = prod[0][e];
+        __syncthreads();
+        cpx<T> ym[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int sidx = g + G * e;
+          ym[e] = xb.at(0, sidx ? m - sidx : 0);
+        }
+        __syncthreads();
+        cpx<T> y1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const cpx<T> yv = prod[0][e];
+          // y_r = (Y + conj Ym) / 2,  y_{r+1} = -i (Y - conj Ym) / 2
+          prod[0][e] = mk(T(0.5) * (yv.x + ym[e].x), T(0.5) * (yv.y - ym[e].y));
+          y1[e] = mk(T(0.5) * (yv.y + ym[e].y), T(0.5) * (ym[e].x - yv.x));
+        }
+#pragma unroll
+        for (int t = 0; t < P; ++t)
+          a.zqm.template run<E>(ex_of(r + 1, t), (uint32_t)(r + 1) * (uint32_t)G,
+                                [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y1[e], z); });
+      }
     }
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+      a.zqm.template run<E>(ex_of(r, t), (uint32_t)r * (uint32_t)G,
+                            [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(prod[0][e], z); });
+    r += pair ? 2 : 1;
   }
   if (valid) {
     cpx<T>* dst = tk ? tk->out : a.out + row * a.out_stride;

@@ -99,21 +99,29 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
 // Inner form, pass 2: m-point convolution rows.  The A rows are loaded
 // together and transformed together.  The twiddles zeta_{qm}^{r s} are looked
 // up again for the post-multiplication rather than kept in registers across
-// the transforms.
-template <typename T, int E, int A>
+// the transforms.  Hermitian plans (HERM): every row's transform is real, so
+// a slot takes two rows a, b and packs them as x_a + i x_b into one
+// transform per input (F_a = Re, F_b = Im), the products go back packed as
+// P_a + i P_b, and the inverse Y splits by conjugate symmetry:
+// y_a(s) = (Y(s) + conj Y(-s)) / 2, y_b(s) = (Y(s) - conj Y(-s)) / (2i).
+template <typename T, int E, int A, bool HERM>
 __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   const int G = a.fd.G, m = a.m, p = a.p;
   const int slot = threadIdx.x / G;
   const int g = threadIdx.x - slot * G;
-  const int64_t R2 = (int64_t)blockIdx.x * a.rows_per_block + slot;
+  const int64_t R2 = HERM ? 2 * ((int64_t)blockIdx.x * a.rows_per_block + slot)
+                          : (int64_t)blockIdx.x * a.rows_per_block + slot;
   const bool valid = R2 < a.nrows;
-  const int u = (int)(R2 % p);
-  const int dv = (int)((R2 / p) % a.D);
+  const bool valid_b = HERM && R2 + 1 < a.nrows;
   // twiddle exponent r s for s = g + G e: start and step; r < q and g, G < m,
   // so both stay below q m without reduction
-  const uint32_t r = (uint32_t)u * (uint32_t)a.n + (uint32_t)(a.v0 + dv);
-  const uint32_t ex0 = r * (uint32_t)g;
-  const uint32_t st = r * (uint32_t)G;
+  auto residue = [&](int64_t row) -> uint32_t {
+    const int u = (int)(row % p);
+    const int dv = (int)((row / p) % a.D);
+    return (uint32_t)u * (uint32_t)a.n + (uint32_t)(a.v0 + dv);
+  };
+  const uint32_t r = residue(R2);
+  const uint32_t rb = HERM ? residue(R2 + 1) : 0u;
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + (size_t)slot * A * row_pad(m, a.fd.ps), 1, a.fd.ps, row_pad(m, a.fd.ps)};
 
@@ -125,30 +133,71 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
     for (int e = 0; e < E; ++e) x[ai][e] = valid ? ld_at(src, (uint32_t)(g + G * e)) : czero<T>();
   }
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_rows(m, a.fd.ps, a.rows_per_block, A));
-  a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) {
+  a.zqm.template run<E>(r * (uint32_t)g, r * (uint32_t)G, [&](int e, cpx<T> z) {
 #pragma unroll
     for (int ai = 0; ai < A; ++ai) x[ai][e] = cmul(x[ai][e], z);
   });
+  if constexpr (HERM) {
+    // the second row enters as i times its twiddled values
+    a.zqm.template run<E>(rb * (uint32_t)g, rb * (uint32_t)G, [&](int e, cpx<T> z) {
+#pragma unroll
+      for (int ai = 0; ai < A; ++ai) {
+        const cpx<T> v = valid_b ? cmul(ld_at(a.work[ai] + (R2 + 1) * m, (uint32_t)(g + G * e)), z) : czero<T>();
+        x[ai][e] = x[ai][e] + mk(-v.y, v.x);
+      }
+    });
+  }
   __syncthreads();
   gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
   cpx<T> prod[1][E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     cpx<T> pr = x[0][e];
+    if constexpr (HERM) {
+      T pa = x[0][e].x, pb = x[0][e].y;
 #pragma unroll
-    for (int ai = 1; ai < A; ++ai) pr = cmul(pr, x[ai][e]);
+      for (int ai = 1; ai < A; ++ai) {
+        pa *= x[ai][e].x;
+        pb *= x[ai][e].y;
+      }
+      pr = mk(pa, pb);
+    } else {
+#pragma unroll
+      for (int ai = 1; ai < A; ++ai) pr = cmul(pr, x[ai][e]);
+    }
     prod[0][e] = pr;
   }
   gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
+  if constexpr (HERM) {
+    // Y(-s) from the lane that holds it, through LDS
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xb.at(0, g + G * e) = prod[0][e];
+    __syncthreads();
+    cpx<T> ym[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int sidx = g + G * e;
+      ym[e] = xb.at(0, sidx ? m - sidx : 0);
+    }
+    if (valid_b) {
+      cpx<T>* dstb = a.work[0] + (R2 + 1) * m;
+      a.zqm.template run<E>(rb * (uint32_t)g, rb * (uint32_t)G, [&](int e, cpx<T> z) {
+        const cpx<T> yv = prod[0][e];  // y_b = -i (Y - conj Ym) / 2
+        st_at(dstb, (uint32_t)(g + G * e), cmulc(mk(T(0.5) * (yv.y + ym[e].y), T(0.5) * (ym[e].x - yv.x)), z));
+      });
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)  // y_a = (Y + conj Ym) / 2
+      prod[0][e] = mk(T(0.5) * (prod[0][e].x + ym[e].x), T(0.5) * (prod[0][e].y - ym[e].y));
+  }
   if (valid) {
     cpx<T>* dst = a.work[0] + R2 * m;
-    a.zqm.template run<E>(ex0, st, [&](int e, cpx<T> z) {
+    a.zqm.template run<E>(r * (uint32_t)g, r * (uint32_t)G, [&](int e, cpx<T> z) {
       st_at(dst, (uint32_t)(g + G * e), cmulc(prod[0][e], z));
     });
   }
 }
-
-
 
 // Inner form, pass 3 (eq. invInner): columns back to the p x m view.  With
 // FOLD the value at position tau also feeds the negative block tau - p (acc1).
@@ -246,10 +295,14 @@ template <typename T>
 hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s) {
   const int nt = a.fd.G * a.rows_per_block;
   if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N) return HD_BAD;
-  dim3 grid((unsigned)((a.nrows + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
+  // Hermitian plans: a slot takes two rows
+  const int64_t slots = a.herm ? (a.nrows + 1) / 2 : a.nrows;
+  dim3 grid((unsigned)((slots + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
   const size_t lds = lds_rows(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
-#define R1(EE, AA) \
-  if (E == EE && A == AA) return go(k_rows_conv<T, EE, AA>, grid, block, lds, s, a);
+#define R1(EE, AA)                                                                \
+  if (E == EE && A == AA)                                                         \
+    return a.herm ? go(k_rows_conv<T, EE, AA, true>, grid, block, lds, s, a)      \
+                  : go(k_rows_conv<T, EE, AA, false>, grid, block, lds, s, a);
   R1(4, 2) R1(4, 3) R1(8, 2) R1(8, 3) R1(12, 2) R1(12, 3) R1(16, 2) R1(16, 3)
 #undef R1
   return HD_BAD;

@@ -169,6 +169,8 @@ def test_hermitian_batched(gpu, dtype):
 @pytest.mark.parametrize("shape,kw", [
     ((1, 5), {}), ((33, 64), {}), ((33, 63), {}), ((255, 512), {}), ((7, 3000), {"m": (0, 64), "variant": ("outer", "multipass")}),
     ((9, 11, 20), {}), ((31, 31, 31), {}),
+    # 128 outer lines x 96 rows per line: the FP32 row pass pairs its rows too
+    ((65, 4000), {"m": (0, 64), "variant": ("outer", "multipass")}),
     ((33, 64), {"method": "explicit"}), ((9, 11, 20), {"method": "explicit"}),
 ])
 def test_hermitian_multidim(gpu, dtype, shape, kw):
