@@ -114,6 +114,9 @@ typedef struct hdconv_options {
                         log-time gap between the best two is below this (0: 0.05) */
   void* model;       /* model tuner: a cost model from hdconv_model_create      */
   const char* db_path; /* timed tuners: append every timing to this CSV (NULL: none) */
+  int64_t copies;    /* C independent copies of the problem per execute (0: 1)  */
+  int64_t dist;      /* words between the starts of consecutive copies, inputs
+                        and output alike (0: the dense extent of one copy)     */
   int reserved[8];   /* zero                                                    */
 } hdconv_options;
 
@@ -188,9 +191,18 @@ void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, in
 void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                      const hdconv_options* opt);
 
-/* Run the convolution asynchronously on `stream` (a hipStream_t; NULL = the
+/* Copies (the paper's problem descriptor carries C copies with a stride):
+ * with options.copies = C > 1 every input and the output hold C copies of
+ * the problem, copy c starting options.dist words (default: one copy's dense
+ * extent) after copy c-1; each copy is convolved independently, all in the
+ * same launches (the copies multiply the rows / planes of every pass).  dist
+ * must be at least one copy's extent; words between copies are not touched.
+ * The explicit method runs the copies one after another.
+ *
+ * Run the convolution asynchronously on `stream` (a hipStream_t; NULL = the
  * null stream).  inputs: A device pointers, outputs: B device pointers, each
- * to prod(L) words of dtype (Hermitian plans: ceil(L/2) in the last dimension).  outputs[0] may equal one of the inputs
+ * to prod(L) words of dtype (Hermitian plans: ceil(L/2) in the last
+ * dimension; with copies, (C-1) dist + that many).  outputs[0] may equal one of the inputs
  * (in place, as in Algorithm 1); any other overlap is HDCONV_EINVAL.  The
  * inputs are not modified unless aliased by the output.  Returns the launch
  * status; no synchronisation is done. */

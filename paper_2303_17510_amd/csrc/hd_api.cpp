@@ -73,6 +73,7 @@ struct Plan {
   void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
   double* acc64 = nullptr;                            // multi-block accumulator
   int64_t batch_rows = 1;                             // rows of a batched group
+  int64_t copies = 1, dist = 0;                       // copies per execute, words between them
   int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
   double tuned_ms = 0;
   int launches = 0;
@@ -135,7 +136,7 @@ static int64_t lines_of_shape(const int64_t* L, int dims, int d) {
   return n;
 }
 static int64_t lines_of(const Plan* P, int d) {
-  return P->batch_rows > 1 ? P->batch_rows : lines_of_shape(P->L, P->dims, d);
+  return P->batch_rows > 1 ? P->batch_rows : P->copies * lines_of_shape(P->L, P->dims, d);
 }
 
 static int build_dims(Plan* P, const hdconv_options* opt) {
@@ -297,8 +298,8 @@ static double plan_traffic(const Plan* P, int* launches) {
     if (blocks > 1) bytes += (2.0 * blocks - 2) * rows * B * Lr * 16.0;  // FP64 accumulator round trips
     nl += 3 * (int)blocks;
   }
-  if (launches) *launches = nl;
-  return bytes;
+  if (launches) *launches = P->method == HDCONV_METHOD_EXPLICIT ? nl * (int)P->copies : nl;
+  return bytes * (double)P->copies;
 }
 
 template <typename T>
@@ -382,7 +383,9 @@ static int alloc_workspace(Plan* P) {
     for (int d = 0; d < P->dims; ++d) n *= (size_t)P->npad[d];
     for (int a = 0; a < P->A; ++a) want.push_back({&P->pad_in[a], n * w});
   }
-  size_t nb = (size_t)P->batch_rows;  // independent rows (batched groups), else 1
+  // independent rows (batched groups) or copies, else 1 (the explicit method
+  // runs copies one at a time)
+  size_t nb = (size_t)(P->method == HDCONV_METHOD_EXPLICIT ? 1 : P->batch_rows * P->copies);
   for (int d = 0; d + 1 < P->dims; ++d) {
     size_t rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)stored_extent(P->dp[e]);
@@ -393,7 +396,13 @@ static int alloc_workspace(Plan* P) {
   if (dl.variant == VAR_MULTI) {
     const size_t rowsz = nb * (size_t)(dl.D * dl.p * dl.m);
     for (int a = 0; a < P->A; ++a) want.push_back({&P->rowwork[a], rowsz * w});
-    if (dl.D < dl.n) want.push_back({(void**)&P->acc64, nb * (size_t)Le[P->dims - 1] * 16});
+    // the FP64 accumulator is laid out like the rows' output (1D copies: dist apart)
+    size_t acc_rows = nb, acc_len = (size_t)Le[P->dims - 1];
+    if (P->dims == 1 && P->copies > 1 && P->method != HDCONV_METHOD_EXPLICIT) {
+      acc_rows = (size_t)P->copies;
+      acc_len = (size_t)P->dist;
+    }
+    if (dl.D < dl.n) want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
   }
   size_t total = 0;
   for (auto& x : want) total += align256(x.second);
@@ -437,17 +446,19 @@ static RootTable<T> rtab(const Plan* P, int d) {
 // or (tasks != NULL) nrows independent rows described by a device task table
 template <typename T>
 static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s,
-                    const RowTask<T>* tasks = nullptr) {
+                    const RowTask<T>* tasks = nullptr, int64_t row_stride = 0) {
   const int d = P->dims - 1;
   const DimPlan& dp = P->dp[d];
   const int A = P->A;
+  // words between consecutive rows of the inputs and the output (default: dense)
+  const int64_t rs = row_stride ? row_stride : stored_extent(dp);
   hipError_t e;
   if (dp.variant == VAR_FUSED) {
     FusedArgs<T> a{};
     a.tasks = tasks;
     for (int i = 0; i < A; ++i) a.in[i] = in ? in[i] : nullptr;
     a.out = out;
-    a.in_stride = a.out_stride = dp.herm ? herm_stored(dp.L) : dp.L;
+    a.in_stride = a.out_stride = rs;
     a.nrows = nrows;
     a.L = dp.L;
     a.m = (int)dp.m;
@@ -463,7 +474,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
     a.zqm = rtab<T>(P, d);
     const double wb = 2.0 * sizeof(T);
-    ProfScope ps(P, s, "fused1d", (double)nrows * (A + 1) * dp.L * wb);
+    ProfScope ps(P, s, "fused1d", (double)nrows * (A + 1) * (double)stored_extent(dp) * wb);
     e = launch_fused1d<T>(a, dp.E_m, (int)dp.p, A, s);
     if (e != hipSuccess) return hip_err(e, "fused1d launch");
     return HDCONV_OK;
@@ -479,7 +490,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
       k1.in[i] = in ? in[i] : nullptr;
       k1.work[i] = (cpx<T>*)P->rowwork[i];
     }
-    k1.in_stride = dp.herm ? herm_stored(dp.L) : dp.L;
+    k1.in_stride = rs;
     k1.nrows = nrows;
     k1.L = dp.L;
     k1.m = (int)dp.m;
@@ -496,7 +507,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k1.zq = (const cpx<T>*)P->dd[d].zq;
     const double wb = 2.0 * sizeof(T);
     {
-      ProfScope ps(P, s, "cols_fwd", (double)nrows * A * ((double)dp.L + (double)D * dp.p * dp.m) * wb);
+      ProfScope ps(P, s, "cols_fwd", (double)nrows * A * ((double)stored_extent(dp) + (double)D * dp.p * dp.m) * wb);
       e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
     }
     if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
@@ -530,7 +541,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.out = out;
     k3.acc = P->acc64;
     k3.acc_mode = nblk == 1 ? ACC_WRITE : (blk == 0 ? ACC_FIRST : (blk == nblk - 1 ? ACC_LAST : ACC_ADD));
-    k3.out_stride = dp.herm ? herm_stored(dp.L) : dp.L;
+    k3.out_stride = rs;
     k3.nrows = nrows;
     k3.L = dp.L;
     k3.m = (int)dp.m;
@@ -547,9 +558,10 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k3.zq = (const cpx<T>*)P->dd[d].zq;
     {
-      const double accb = k3.acc_mode == ACC_WRITE ? (double)dp.L * wb
-                          : (k3.acc_mode == ACC_FIRST ? 16.0 * dp.L
-                                                      : (k3.acc_mode == ACC_ADD ? 32.0 * dp.L : 16.0 * dp.L + dp.L * wb));
+      const double Lw = (double)stored_extent(dp);
+      const double accb = k3.acc_mode == ACC_WRITE ? Lw * wb
+                          : (k3.acc_mode == ACC_FIRST ? 16.0 * Lw
+                                                      : (k3.acc_mode == ACC_ADD ? 32.0 * Lw : 16.0 * Lw + Lw * wb));
       ProfScope ps(P, s, "cols_bwd", (double)nrows * ((double)D * dp.p * dp.m * wb + accb));
       e = launch_cols_bwd<T>(k3, dp.E_pb, s);
     }
@@ -558,12 +570,20 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
   return HDCONV_OK;
 }
 
+// One execute.  Hybrid plans take all copies in the same launches (the
+// copies are the first level's planes, or the rows of a 1D plan); `nc` is
+// the number of copies this call covers (the explicit method calls it once
+// per copy with nc = 1).
 template <typename T>
-static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t s) {
+static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream_t s, int64_t nc) {
   const int A = P->A;
   hipError_t e;
   int64_t Le[3];
   for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
+  // words between copies in the user's arrays (dense: one copy's extent)
+  int64_t one = 1;
+  for (int d = 0; d < P->dims; ++d) one *= P->Lio[d];
+  const int64_t dist = nc > 1 ? P->dist : one;
   const cpx<T>* cur[kMaxA];
   cpx<T>* final_out = (cpx<T>*)out_v;
   if (P->method == HDCONV_METHOD_EXPLICIT) {
@@ -598,7 +618,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)inputs[a];
   }
   // outer dimensions, forward
-  int64_t nb = 1;
+  int64_t nb = nc;
   for (int d = 0; d + 1 < P->dims; ++d) {
     const DimPlan& dp = P->dp[d];
     int64_t rest = 1;
@@ -609,7 +629,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
       o.out[a] = (cpx<T>*)P->lvl[d][a];
     }
     o.nb = nb;
-    o.in_bstride = Le[d] * rest;
+    o.in_bstride = d == 0 ? dist : Le[d] * rest;  // the user's copies are dist apart
     o.R = rest;
     o.L = Le[d];
     o.m = (int)dp.m;
@@ -632,7 +652,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
   // innermost rows
   {
     cpx<T>* rows_out = P->dims == 1 ? final_out : (cpx<T>*)P->lvl[P->dims - 2][0];
-    int rc = run_rows<T>(P, cur, rows_out, nb, s);
+    int rc = run_rows<T>(P, cur, rows_out, nb, s, nullptr, P->dims == 1 ? dist : 0);
     if (rc != HDCONV_OK) return rc;
   }
   // outer dimensions, backward
@@ -647,7 +667,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
     o.acc = nullptr;
     o.acc_mode = ACC_WRITE;
     o.nb = nb;
-    o.out_bstride = Le[d] * rest;
+    o.out_bstride = d == 0 ? dist : Le[d] * rest;
     o.R = rest;
     o.L = Le[d];
     o.m = (int)dp.m;
@@ -690,6 +710,19 @@ static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t
       e = launch_box_copy<T>(b, s);
     }
     if (e != hipSuccess) return hip_err(e, "truncate launch");
+  }
+  return HDCONV_OK;
+}
+
+template <typename T>
+static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t s) {
+  if (P->method != HDCONV_METHOD_EXPLICIT || P->copies == 1) return run_copies<T>(P, inputs, out_v, s, P->copies);
+  // the explicit baseline pads one copy at a time into its work buffers
+  for (int64_t c = 0; c < P->copies; ++c) {
+    const void* in_c[kMaxA];
+    for (int a = 0; a < P->A; ++a) in_c[a] = (const cpx<T>*)inputs[a] + c * P->dist;
+    int rc = run_copies<T>(P, in_c, (cpx<T>*)out_v + c * P->dist, s, 1);
+    if (rc != HDCONV_OK) return rc;
   }
   return HDCONV_OK;
 }
@@ -787,6 +820,8 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     if (tune_shapes(L, M, A, B, dims, dtype, opt, shp, &nc, &nt, &ms) != HDCONV_OK) return nullptr;
     hdconv_options o = opts_from_shape(shp, dims);
     o.flags = opt->flags;
+    o.copies = opt->copies;
+    o.dist = opt->dist;
     Plan* T = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
     if (T) {
       T->tuner = opt->tuner;
@@ -808,6 +843,18 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->method = (opt && opt->method == HDCONV_METHOD_EXPLICIT) ? HDCONV_METHOD_EXPLICIT : HDCONV_METHOD_HYBRID;
   P->flags = opt ? opt->flags : 0;
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
+  {
+    int64_t one = 1;
+    for (int d = 0; d < dims; ++d) one *= (herm && d == dims - 1) ? (L[d] + 1) / 2 : L[d];
+    P->copies = (opt && opt->copies > 0) ? opt->copies : 1;
+    P->dist = (opt && opt->dist > 0) ? opt->dist : one;
+    if (P->dist < one || P->copies > (int64_t(1) << 31)) {
+      set_err(HDCONV_EINVAL, "copies must be dist >= %lld words apart (got dist = %lld, copies = %lld)",
+              (long long)one, (long long)P->dist, (long long)P->copies);
+      free_plan(P);
+      return nullptr;
+    }
+  }
   for (int d = 0; d < dims; ++d) {
     P->L[d] = L[d];
     P->Lio[d] = (herm && d == dims - 1) ? herm_stored(L[d]) : L[d];
@@ -899,8 +946,10 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
   if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
   Plan* P = (Plan*)plan;
   if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
-  size_t bytes = 2 * (size_t)tbytes_of(P->dtype);
-  for (int d = 0; d < P->dims; ++d) bytes *= (size_t)P->Lio[d];
+  // span of one array: (C-1) dist + one copy's extent
+  size_t one = 1;
+  for (int d = 0; d < P->dims; ++d) one *= (size_t)P->Lio[d];
+  const size_t bytes = 2 * (size_t)tbytes_of(P->dtype) * ((size_t)(P->copies - 1) * (size_t)P->dist + one);
   for (int a = 0; a < P->A; ++a)
     if (!inputs[a]) return set_err(HDCONV_EINVAL, "inputs[%d] is NULL", a);
   if (!outputs[0]) return set_err(HDCONV_EINVAL, "outputs[0] is NULL");

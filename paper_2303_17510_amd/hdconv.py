@@ -73,6 +73,9 @@ class Plan:
     ``centered``: arrays hold the indices -L//2 .. L-1-L//2 (index 0 at
     position L//2) and the result is the centered convolution; ``M`` then
     defaults to the centered minimum (3L/2 for A = 2, even L).
+    ``copies`` (C) and ``dist``: each array holds C copies of the problem,
+    ``dist`` words apart (default: dense, tensors of shape ``(C, *shape)``;
+    with ``dist`` a flat tensor of at least ``(C-1) dist + n`` words).
     ``hermitian``: the last dimension holds the ``ceil(L/2)`` non-negative
     indices of a Hermitian centered array (``f_{-c} = conj f_c``; 2D/3D:
     ``F(k, -c) = conj F(-k, c)`` with centered outer dimensions of odd
@@ -83,7 +86,8 @@ class Plan:
                  dtype="c64", method: str = "hybrid", m=None, p=None, D=None, variant=None,
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
-                 db_path: str | None = None, centered: bool = False, hermitian: bool = False):
+                 db_path: str | None = None, centered: bool = False, hermitian: bool = False,
+                 copies: int = 1, dist: int = 0):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
@@ -100,6 +104,9 @@ class Plan:
         self.centered, self.hermitian = bool(centered), bool(hermitian)
         # shape of the arrays passed in and out
         self.io_shape = L[:-1] + ((L[-1] + 1) // 2,) if hermitian else L
+        self.copies, self.dist = int(copies), int(dist)
+        opt.copies = self.copies
+        opt.dist = self.dist
         if dims > 3 or len(M) != dims:
             raise ValueError("L and M need 1 to 3 matching dimensions")
         for d, v in enumerate(_tup(m, dims)):
@@ -161,9 +168,18 @@ class Plan:
         want = torch.complex64 if self.dtype_code == _L.C64 else torch.complex128
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError("%s must be a CUDA (HIP) tensor" % name)
-        if t.dtype != want or tuple(t.shape) != self.io_shape or not t.is_contiguous():
+        if self.copies > 1 and self.dist:
+            n = 1
+            for v in self.io_shape:
+                n *= v
+            need = (self.copies - 1) * self.dist + n
+            if t.dtype != want or t.dim() != 1 or t.numel() < need or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous flat %s tensor of at least %d words" % (name, want, need))
+            return
+        shape = ((self.copies,) + self.io_shape) if self.copies > 1 else self.io_shape
+        if t.dtype != want or tuple(t.shape) != shape or not t.is_contiguous():
             raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
-                             % (name, want, self.io_shape, t.dtype, tuple(t.shape)))
+                             % (name, want, shape, t.dtype, tuple(t.shape)))
 
     def execute(self, inputs, out, stream=None):
         """Run asynchronously on ``stream`` (default: torch's current stream)."""

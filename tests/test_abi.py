@@ -284,3 +284,15 @@ def test_explicit_c128_long_rows_split():
         with Plan(L, M, dtype="c128", method="explicit", host_only=True) as p:
             d = p.info()["dims"][0]
             assert d["variant"] == "multipass" and d["p"] * d["m"] == p.info()["npad"][0]
+
+
+def test_copies_validation_and_accounting():
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), copies=2, dist=50, host_only=True)
+    assert ei.value.code == _lib.EINVAL
+    with Plan((1024,), copies=1, host_only=True) as p1, Plan((1024,), copies=8, host_only=True) as p8:
+        # copies share the launches and multiply the designed traffic
+        assert p8.info()["launches"] == p1.info()["launches"]
+        assert p8.info()["traffic_bytes"] == pytest.approx(8 * p1.info()["traffic_bytes"])
+    with Plan((1000,), copies=5, method="explicit", host_only=True) as p:
+        assert p.info()["launches"] == 5 * 4  # pads, transform, truncation per copy
