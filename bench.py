@@ -431,6 +431,19 @@ def main():
                 put("hermitian_1M_hybrid_%s" % dt, lambda: leg(wh, dt, "hybrid", sc, 5))
                 put("hermitian_1M_hybrid_%s_tuned" % dt, lambda: leg(wh, dt, "hybrid", sc, 5, tuner="exhaustive"))
                 put("hermitian_1M_explicit_%s" % dt, lambda: explicit_best(wh, dt, sc, 5))
+            # 3D cubes of incremental, mostly non-power-of-two extents (M = 2L):
+            # hybrid against explicit padding to the next supported size
+            sweep = {}
+            for n in (96, 100, 127, 150, 181, 200, 229, 256):
+                w3 = {"workload": "3D sweep", "L": [n] * 3, "M": [2 * n] * 3, "A": 2, "dtype": "c64",
+                      "config_id": 4}
+                h = run("sweep3d_%d" % n, lambda: leg(w3, "c64", "hybrid", 5, 2))
+                x = run("sweep3d_%d_explicit" % n, lambda: leg(w3, "c64", "explicit", 3, 1))
+                if h and x:
+                    sweep[str(n)] = {"hybrid_ms": h[0]["ms"], "explicit_ms": x[0]["ms"],
+                                     "speedup": x[0]["ms"] / h[0]["ms"],
+                                     "ns_per_NlogN_hybrid": h[0]["ns_per_NlogN"]}
+            compare["sweep3d_c64"] = sweep
             wh4 = workload("c4_hermitian")
             put("hermitian_2047x2048_hybrid_c64", lambda: leg(wh4, "c64", "hybrid", 20, 3))
             put("hermitian_2047x2048_hybrid_c64_tuned", lambda: leg(wh4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
@@ -439,7 +452,7 @@ def main():
             v.pop("stats", None)
             v.pop("info", None)
         for k, v in compare.items():
-            if "error" in v:
+            if "error" in v or "ms" not in v:
                 continue
             dom = v.get("dominant", {"kernel": "-", "frac": float("nan")})
             log("%-22s %.4f ms  %.3e outputs/s  dominant %s %.3f" % (k, v["ms"], v["outputs_per_s"],
