@@ -423,7 +423,31 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // residues looped (q = 2 for M = 2L), half the transform work.  Powers
     // of two only: sizes with a factor 3 measured slower at equal padding.
     const int64_t m = std::max<int64_t>(8, pow2_ceil(lines <= 1 ? M : L));
-    if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_FUSED) && finish_dim(dp, A, tbytes, &w)) return true;
+    // a size 3 * 2^k whose padding q m is at least 20 % smaller (lengths well
+    // below a power of two; measured on 3D cubes: L = 150 1.75 -> 1.40 ms,
+    // L = 181 2.04 -> 1.65 ms)
+    if (m <= 4096) {
+      const DimPlan base_try = [&] {
+        DimPlan t;
+        std::string w2;
+        if (!set_geom(&t, L, M, m, 0, VAR_FUSED) || !finish_dim(&t, A, tbytes, &w2)) t.m = 0;
+        return t;
+      }();
+      const int64_t m3 = std::max<int64_t>(24, next_fft_size(lines <= 1 ? M : L));
+      if (m3 < m && m3 % 3 == 0) {
+        DimPlan t;
+        std::string w2;
+        if (set_geom(&t, L, M, m3, 0, VAR_FUSED) && finish_dim(&t, A, tbytes, &w2) &&
+            (base_try.m == 0 || 5 * t.q * t.m <= 4 * base_try.q * base_try.m)) {
+          *dp = t;
+          return true;
+        }
+      }
+      if (base_try.m) {
+        *dp = base_try;
+        return true;
+      }
+    }
     // Inner form: the least padding q m over m = 1024 .. 8192 and p a power
     // of two, or 3 * 2^k from 96 up (small column transforms with a factor 3
     // measured slow; FP64 ones spill, so powers of two there).  Among equal
@@ -474,6 +498,11 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
   // ties to p = 2 once the p = 1 transform would exceed 1024 points.
   {
     const int64_t m1 = std::max<int64_t>(8, pow2_ceil(M));
+    // (as for rows: a 3 * 2^k transform when it pads at least 20 % less)
+    const int64_t m13 = std::max<int64_t>(24, next_fft_size(M));
+    if (m13 < m1 && m13 % 3 == 0 && 5 * m13 <= 4 * m1 && m13 <= 1536 && set_geom(dp, L, M, m13, 0, VAR_OUTER) &&
+        finish_dim(dp, A, tbytes, &w))
+      return true;
     if (m1 <= 1024 && set_geom(dp, L, M, m1, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
     DimPlan a, b;
     const int64_t ma = std::max<int64_t>(8, pow2_ceil(L)), mb = std::max<int64_t>(8, pow2_ceil(cdiv(L, 2)));
