@@ -200,3 +200,29 @@ def test_hermitian_2d_tuned(gpu):
         assert p.info()["timed_candidates"] > 1
     want = oracle.conv_hermitian_explicit([synth.as_oracle(x) for x in xs])
     assert oracle.rel_l2(got, want) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("tuner", ["exhaustive", "model"])
+def test_hermitian_and_centered_tuned_batches(gpu, tuner):
+    # batched plans tune per size bucket with the centered / Hermitian flag
+    import torch
+    rng = np.random.default_rng(29)
+    Ls = [int(v) for v in rng.integers(50, 5000, 24)]
+    for flag in ("centered", "hermitian"):
+        io = [((L + 1) // 2 if flag == "hermitian" else L) for L in Ls]
+        xs = [[synth.unit_disk((n,), 8700 + 2 * i + a).astype(np.complex64) for a in range(2)]
+              for i, n in enumerate(io)]
+        ins = [[torch.from_numpy(x).cuda() for x in pair] for pair in xs]
+        outs = [torch.empty_like(pair[0]) for pair in ins]
+        with BatchPlan(Ls, dtype="c64", tuner=tuner, tune_reps=2, **{flag: True}) as bp:
+            bp.execute(ins, outs)
+            torch.cuda.synchronize()
+        for i in range(len(Ls)):
+            o = [synth.as_oracle(x) for x in xs[i]]
+            want = oracle.conv_hermitian_direct(o) if flag == "hermitian" else oracle.conv_centered_direct(o)
+            assert oracle.rel_l2(outs[i].cpu().numpy(), want) <= TOL["c64"], (flag, i)
+
+
+def test_hermitian_model_tuned_plan(gpu):
+    _, info = check(1 << 16, "c64", tuner="model")
+    assert info["tuner"] == "model"
