@@ -15,6 +15,38 @@ __device__ __forceinline__ int zq_index(int v, int t, int q) {
   return k < 0 ? k + q : k;
 }
 
+// Calls f(e, zeta_q^{v (g + G e)}) for e = 0 .. E-1 (v < n, so v (g + G e) <
+// q): the powers are composed from three table lookups, zeta_q^{v g},
+// w = zeta_q^{v G} and w^4, as z = base w^{e mod 4} (w^4)^{e div 4}, instead
+// of one lookup per point.
+template <int E, typename T, typename F>
+__device__ __forceinline__ void zq_run(const cpx<T>* zq, int v, int g, int G, int q, F&& f) {
+  static_assert(E <= 16, "at most 16 powers per run");
+  const cpx<T> base = zq[v * g];
+  cpx<T> p0[4], p1[4];
+  p0[0] = p1[0] = mk(T(1), T(0));
+  if constexpr (E > 1) {
+    const int st = v * G;  // < q
+    p0[1] = zq[st];
+    p0[2] = cmul(p0[1], p0[1]);
+    p0[3] = cmul(p0[2], p0[1]);
+    if constexpr (E > 4) {
+      int s4 = 4 * st;
+      while (s4 >= q) s4 -= q;
+      p1[1] = zq[s4];
+      p1[2] = cmul(p1[1], p1[1]);
+      p1[3] = cmul(p1[2], p1[1]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cpx<T> z = base;
+    if (e & 3) z = cmul(z, p0[e & 3]);
+    if (e >> 2) z = cmul(z, p1[e >> 2]);
+    f(e, z);
+  }
+}
+
 // Inner form, pass 1 (Sec. 6.1, forward): columns s of the p x m view.  For
 // each residue v the column is scaled by zeta_q^{vt} and p-point transformed;
 // residues are taken two at a time (shared twiddles and barriers).  Centered
@@ -31,14 +63,17 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int v = a.v0 + dv0 + n;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int tau = g + G * e;
-      if constexpr (FOLD) {
-        y[n][e] = cmul(x[e], a.zq[v * tau]) + cmul(x1[FOLD ? e : 0], a.zq[zq_index(v, tau - p, q)]);
-      } else {
-        y[n][e] = cmul(x[e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
-      }
+    // the negative block t - p carries zeta_q^{v (t - p)} = zeta_q^{v t} c
+    const cpx<T> zc = a.zq[v * p ? q - v * p : 0];
+    if constexpr (FOLD) {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) { y[n][e] = cmul(z, x[e] + cmul(zc, x1[FOLD ? e : 0])); });
+    } else if (tneg == 0) {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) { y[n][e] = cmul(x[e], z); });
+    } else {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) {
+        const cpx<T> xe = g + G * e >= p - tneg ? cmul(x[e], zc) : x[e];
+        y[n][e] = cmul(xe, z);
+      });
     }
   }
   gfft_any<T, E, +1, NT, (sizeof(T) == 4 ? kCtCols : 0u)>(y, g, a.fd, tw, xb);
@@ -217,15 +252,21 @@ __device__ __forceinline__ void cols_bwd_residues(const ColBwdArgs<T>& a, cpx<T>
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int v = a.v0 + dv0 + n;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int tau = g + G * e;
-      if constexpr (FOLD) {
-        acc[e] = acc[e] + cmulc(y[n][e], a.zq[v * tau]);
-        acc1[FOLD ? e : 0] = acc1[FOLD ? e : 0] + cmulc(y[n][e], a.zq[zq_index(v, tau - p, q)]);
-      } else {
-        acc[e] = acc[e] + cmulc(y[n][e], a.zq[zq_index(v, signed_block(tau, p, tneg), q)]);
-      }
+    // the negative block t - p takes conj(zeta_q^{v (t - p)}) = conj(zeta_q^{v t} c)
+    const cpx<T> zc = a.zq[v * p ? q - v * p : 0];
+    if constexpr (FOLD) {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) {
+        const cpx<T> t = cmulc(y[n][e], z);
+        acc[e] = acc[e] + t;
+        acc1[FOLD ? e : 0] = acc1[FOLD ? e : 0] + cmulc(t, zc);
+      });
+    } else if (tneg == 0) {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) { acc[e] = acc[e] + cmulc(y[n][e], z); });
+    } else {
+      zq_run<E>(a.zq, v, g, G, q, [&](int e, cpx<T> z) {
+        const cpx<T> t = cmulc(y[n][e], z);
+        acc[e] = acc[e] + (g + G * e >= p - tneg ? cmulc(t, zc) : t);
+      });
     }
   }
 }
