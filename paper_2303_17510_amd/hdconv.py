@@ -350,8 +350,16 @@ class BoundBatch:
 
 
 def convolve(*inputs, M=None, **kw):
-    """One-shot convolution of equal-shape complex CUDA tensors (first L outputs)."""
+    """One-shot convolution of equal-shape complex CUDA tensors (first L
+    outputs; with ``centered`` / ``hermitian`` the centered or Hermitian
+    convolution, the tensors then holding the stored halves; with ``copies``
+    the leading dimension counts the copies)."""
     L = tuple(inputs[0].shape)
+    if kw.get("copies", 1) > 1:
+        L = L[1:]
+    if kw.get("hermitian"):
+        # stored halves of Lh entries stand for the odd length 2 Lh - 1
+        L = L[:-1] + (2 * L[-1] - 1,)
     with Plan(L, M, A=len(inputs), dtype=inputs[0].dtype, **kw) as p:
         out = p(*inputs)
         import torch

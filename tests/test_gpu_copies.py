@@ -102,3 +102,14 @@ def test_copies_explicit(gpu, dtype, shape, dist):
 def test_copies_three_inputs_and_in_place(gpu):
     check((500,), "c128", 4, A=3)
     check((2000,), "c128", 3, dist=2100, in_place=True, m=32, variant="multipass")
+
+
+def test_convolve_helper_flags(gpu):
+    import torch
+    from paper_2303_17510_amd import convolve
+    f, g = (synth.unit_disk((3, 40), 7700 + a) for a in range(2))
+    out = convolve(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), copies=3, centered=True)
+    for c in range(3):
+        assert oracle.rel_l2(out[c].cpu().numpy(), oracle.conv_centered_direct([f[c], g[c]])) <= 1e-12
+    h = convolve(torch.from_numpy(f[0]).cuda(), torch.from_numpy(g[0]).cuda(), hermitian=True)
+    assert oracle.rel_l2(h.cpu().numpy(), oracle.conv_hermitian_direct([f[0], g[0]])) <= 1e-12
