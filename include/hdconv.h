@@ -116,7 +116,11 @@ typedef struct hdconv_options {
   const char* db_path; /* timed tuners: append every timing to this CSV (NULL: none) */
   int64_t copies;    /* C independent copies of the problem per execute (0: 1)  */
   int64_t dist;      /* words between the starts of consecutive copies, inputs
-                        and output alike (0: the dense extent of one copy)     */
+                        and output alike (0: one copy's extent)                */
+  int64_t stride[2]; /* 2D/3D: element strides of dimensions 0 and 1 (the last
+                        dimension is contiguous), inputs and output alike; 0:
+                        dense.  2D uses stride[0] >= L[1] (stored extent);
+                        3D stride[1] >= L[2], stride[0] >= L[1] stride[1]     */
   int reserved[8];   /* zero                                                    */
 } hdconv_options;
 
@@ -197,7 +201,10 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
  * extent) after copy c-1; each copy is convolved independently, all in the
  * same launches (the copies multiply the rows / planes of every pass).  dist
  * must be at least one copy's extent; words between copies are not touched.
- * The explicit method runs the copies one after another.
+ * The explicit method runs the copies one after another.  With
+ * options.stride a copy is strided (padded rows, as in the paper's benchmark
+ * layouts): element (i0, i1[, i2]) at i0 stride[0] + i1 [stride[1] + i2]; one
+ * copy's extent is then L[0] stride[0], and the padding words are not touched.
  *
  * Run the convolution asynchronously on `stream` (a hipStream_t; NULL = the
  * null stream).  inputs: A device pointers, outputs: B device pointers, each

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ("variant", ctypes.c_int * 3), ("E_m", ctypes.c_int * 3), ("E_p", ctypes.c_int * 3),
                 ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("twiddles", ctypes.c_int * 3),
                 ("tuner", ctypes.c_int), ("tune_reps", ctypes.c_int), ("margin", ctypes.c_double),
-                ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("copies", _i64), ("dist", _i64),
+                ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("copies", _i64), ("dist", _i64), ("stride", _i64 * 2),
                 ("reserved", ctypes.c_int * 8)]
 
 

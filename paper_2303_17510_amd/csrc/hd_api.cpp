@@ -74,6 +74,8 @@ struct Plan {
   double* acc64 = nullptr;                            // multi-block accumulator
   int64_t batch_rows = 1;                             // rows of a batched group
   int64_t copies = 1, dist = 0;                       // copies per execute, words between them
+  int64_t stride[2] = {0, 0};                         // element strides of dims 0, 1 (0: dense)
+  int64_t span = 0;                                   // words one copy of an array spans
   int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
   double tuned_ms = 0;
   int launches = 0;
@@ -580,10 +582,19 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
   hipError_t e;
   int64_t Le[3];
   for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
-  // words between copies in the user's arrays (dense: one copy's extent)
-  int64_t one = 1;
-  for (int d = 0; d < P->dims; ++d) one *= P->Lio[d];
-  const int64_t dist = nc > 1 ? P->dist : one;
+  // words between copies in the user's arrays (default: one copy's extent)
+  const int64_t dist = nc > 1 ? P->dist : (P->span ? P->span : 1);
+  // the user's layout in the first outer pass (strided 2D/3D arrays; the
+  // explicit method reads and writes the user's arrays in its copies only)
+  ColLayout user{};
+  if (P->dims >= 2 && (P->stride[0] || P->stride[1]) && P->method != HDCONV_METHOD_EXPLICIT) {
+    const int64_t s1 = P->dims == 3 ? (P->stride[1] ? P->stride[1] : P->Lio[2]) : 1;
+    user.jstride = P->stride[0] ? P->stride[0] : P->Lio[1] * s1;
+    if (P->dims == 3) {
+      user.cgrp = P->Lio[2];
+      user.cgstride = s1;
+    }
+  }
   const cpx<T>* cur[kMaxA];
   cpx<T>* final_out = (cpx<T>*)out_v;
   if (P->method == HDCONV_METHOD_EXPLICIT) {
@@ -597,6 +608,10 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
         b.N[3 - P->dims + d] = P->npad[d];
       }
       b.pad = 1;
+      if (P->dims >= 2) {  // the user's strides (0: dense)
+        b.ls[3 - P->dims] = P->stride[0];
+        if (P->dims == 3) b.ls[1] = P->stride[1];
+      }
       if (P->flags & HDCONV_PLAN_HERMITIAN) {  // the expanded centered array
         b.herm = 1;
         b.hH = P->Lio[P->dims - 1] - 1;
@@ -630,6 +645,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
     }
     o.nb = nb;
     o.in_bstride = d == 0 ? dist : Le[d] * rest;  // the user's copies are dist apart
+    if (d == 0) o.lay = user;
     o.R = rest;
     o.L = Le[d];
     o.m = (int)dp.m;
@@ -668,6 +684,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
     o.acc_mode = ACC_WRITE;
     o.nb = nb;
     o.out_bstride = d == 0 ? dist : Le[d] * rest;
+    if (d == 0) o.lay = user;
     o.R = rest;
     o.L = Le[d];
     o.m = (int)dp.m;
@@ -703,6 +720,10 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
         b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
     }
     b.pad = 0;
+    if (P->dims >= 2) {
+      b.ls[3 - P->dims] = P->stride[0];
+      if (P->dims == 3) b.ls[1] = P->stride[1];
+    }
     {
       double lt = 1;
       for (int d = 0; d < P->dims; ++d) lt *= (double)P->Lio[d];
@@ -822,6 +843,8 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     o.flags = opt->flags;
     o.copies = opt->copies;
     o.dist = opt->dist;
+    o.stride[0] = opt->stride[0];
+    o.stride[1] = opt->stride[1];
     Plan* T = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
     if (T) {
       T->tuner = opt->tuner;
@@ -844,8 +867,30 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->flags = opt ? opt->flags : 0;
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
   {
-    int64_t one = 1;
-    for (int d = 0; d < dims; ++d) one *= (herm && d == dims - 1) ? (L[d] + 1) / 2 : L[d];
+    int64_t ext[3];
+    for (int d = 0; d < dims; ++d) ext[d] = (herm && d == dims - 1) ? (L[d] + 1) / 2 : L[d];
+    // element strides of the outer dimensions (dense unless given)
+    int64_t st[3] = {0, 0, 1};
+    st[dims - 1] = 1;
+    for (int d = dims - 2; d >= 0; --d) {
+      const int64_t dense = ext[d + 1] * st[d + 1];
+      const int64_t want = (opt && opt->stride[d] > 0) ? opt->stride[d] : dense;
+      if (want < dense) {
+        set_err(HDCONV_EINVAL, "stride[%d] = %lld is below %lld (rows would overlap)", d, (long long)want,
+                (long long)dense);
+        free_plan(P);
+        return nullptr;
+      }
+      st[d] = want;
+      if (want != dense || (opt && opt->stride[d] > 0)) P->stride[d] = want;
+    }
+    if (opt && dims == 1 && (opt->stride[0] > 0 || opt->stride[1] > 0)) {
+      set_err(HDCONV_EINVAL, "strides apply to the outer dimensions of 2D/3D plans");
+      free_plan(P);
+      return nullptr;
+    }
+    const int64_t one = ext[0] * st[0];  // one copy's extent (its last row padded too)
+    P->span = one;
     P->copies = (opt && opt->copies > 0) ? opt->copies : 1;
     P->dist = (opt && opt->dist > 0) ? opt->dist : one;
     if (P->dist < one || P->copies > (int64_t(1) << 31)) {
@@ -947,9 +992,8 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
   Plan* P = (Plan*)plan;
   if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
   // span of one array: (C-1) dist + one copy's extent
-  size_t one = 1;
-  for (int d = 0; d < P->dims; ++d) one *= (size_t)P->Lio[d];
-  const size_t bytes = 2 * (size_t)tbytes_of(P->dtype) * ((size_t)(P->copies - 1) * (size_t)P->dist + one);
+  const size_t bytes =
+      2 * (size_t)tbytes_of(P->dtype) * ((size_t)(P->copies - 1) * (size_t)P->dist + (size_t)P->span);
   for (int a = 0; a < P->A; ++a)
     if (!inputs[a]) return set_err(HDCONV_EINVAL, "inputs[%d] is NULL", a);
   if (!outputs[0]) return set_err(HDCONV_EINVAL, "outputs[0] is NULL");

@@ -138,10 +138,18 @@ struct ColBwdArgs {
 // Outer dimension of a multidimensional convolution (Sec. 5), direct form:
 // data viewed as [nb][L][R] (R contiguous columns).  Forward writes, for
 // residues r0 .. r0+D-1, out[a][((b D + dr) m + l) R + c].
+// Layout of the user's array in the first outer pass: element (j, col) of a
+// plane is at j jstride + (col / cgrp) cgstride + col % cgrp (all zero: dense,
+// j R + col).  Strided 2D/3D layouts set it; the level buffers are dense.
+struct ColLayout {
+  int64_t jstride, cgrp, cgstride;
+};
+
 template <typename T>
 struct OuterFwdArgs {
   const cpx<T>* in[kMaxA];
   cpx<T>* out[kMaxA];
+  ColLayout lay;  // of in
   int64_t nb, in_bstride, R;
   int64_t L;
   int m, q, r0, D, S;
@@ -154,7 +162,8 @@ struct OuterFwdArgs {
 template <typename T>
 struct OuterBwdArgs {
   const cpx<T>* y;  // [nb][D][m][R]
-  cpx<T>* out;      // out[b * out_bstride + x R + c], x < L
+  cpx<T>* out;      // out[b * out_bstride + x R + c], x < L (or as lay says)
+  ColLayout lay;    // of out
   double* acc;
   int acc_mode;
   int64_t nb, out_bstride, R;
@@ -174,6 +183,7 @@ struct BoxCopyArgs {
   const cpx<T>* src;
   cpx<T>* dst;
   int64_t L[3], N[3];  // leading unused extents are 1
+  int64_t ls[2];       // element strides of the L box's first two axes (0: dense)
   int64_t off[3];      // truncation: dst[i] = src[i + off] (0, or the centered window start)
   int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
   int herm;            // padding of a Hermitian array (stored box L, last axis c = 0 .. hH):

@@ -32,6 +32,12 @@ __device__ __forceinline__ uint32_t block_exp(uint32_t r, int t, int64_t tneg, u
   return e >= qm ? e - qm : e;
 }
 
+// Offset of column col and the stride between rows j, for a layout (dense
+// when all fields are zero).
+__device__ __forceinline__ int64_t col_offset(const ColLayout& l, int64_t col) {
+  return l.cgrp ? (col / l.cgrp) * l.cgstride + col % l.cgrp : col;
+}
+
 // Outer dimension, direct form, forward: S adjacent columns per workgroup.
 template <typename T, int E, int P>
 __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
@@ -44,7 +50,8 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
   const int ai = blockIdx.z;
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
-  const cpx<T>* src = a.in[ai] + b * a.in_bstride + col;
+  const cpx<T>* src = a.in[ai] + b * a.in_bstride + (valid ? col_offset(a.lay, col) : 0);
+  const int64_t js = a.lay.jstride ? a.lay.jstride : R;
   const CtrShift cs = ctr_shift<P>(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
@@ -56,7 +63,7 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
-      x[t][e] = (valid && i >= 0 && i < a.L) ? src[i * R] : czero<T>();
+      x[t][e] = (valid && i >= 0 && i < a.L) ? src[i * js] : czero<T>();
     }
   __syncthreads();
   for (int dr = 0; dr < a.D; ++dr) {
@@ -114,14 +121,15 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
                             [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
   }
   if (!valid) return;
-  cpx<T>* dst = a.out + b * a.out_bstride + col;
-  double* acc64 = a.acc ? a.acc + 2 * (b * a.out_bstride + col) : nullptr;
+  const int64_t coff = col_offset(a.lay, col), js = a.lay.jstride ? a.lay.jstride : R;
+  cpx<T>* dst = a.out + b * a.out_bstride + coff;
+  double* acc64 = a.acc ? a.acc + 2 * (b * a.out_bstride + coff) : nullptr;
 #pragma unroll
   for (int t = 0; t < P; ++t)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
-      if (i >= 0 && i < a.L) acc_store(dst, acc64, a.acc_mode, i * R, acc[t][e], a.scale);
+      if (i >= 0 && i < a.L) acc_store(dst, acc64, a.acc_mode, i * js, acc[t][e], a.scale);
     }
 }
 
@@ -133,12 +141,17 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
   const int64_t* Sx = a.pad ? a.L : a.N;
   // source offsets (truncation only: the window of the padded result)
   const int64_t o0 = a.pad ? 0 : a.off[0], o1 = a.pad ? 0 : a.off[1], o2 = a.pad ? 0 : a.off[2];
+  // element strides of the L box (the user's array, possibly strided) and of
+  // the N box (dense)
+  const int64_t l1 = a.ls[1] ? a.ls[1] : a.L[2], l0 = a.ls[0] ? a.ls[0] : a.L[1] * l1;
+  const int64_t s1 = a.pad ? l1 : Sx[2], s0 = a.pad ? l0 : Sx[1] * Sx[2];
+  const int64_t d1 = a.pad ? D[2] : l1, d0 = a.pad ? D[1] * D[2] : l0;
   const int64_t rows = D[0] * D[1];
   for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
     const int64_t i1 = row % D[1], i0 = row / D[1];
     const bool in_src = i0 + o0 < Sx[0] && i1 + o1 < Sx[1];
-    const cpx<T>* src = a.src + ((i0 + o0) * Sx[1] + i1 + o1) * Sx[2] + o2;
-    cpx<T>* dst = a.dst + row * D[2];
+    const cpx<T>* src = a.src + (i0 + o0) * s0 + (i1 + o1) * s1 + o2;
+    cpx<T>* dst = a.dst + i0 * d0 + i1 * d1;
     for (int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i2 < D[2];
          i2 += (int64_t)gridDim.x * blockDim.x) {
       if (a.herm && a.pad) {
@@ -148,8 +161,8 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
         cpx<T> v = czero<T>();
         if (i0 < a.L[0] && i1 < a.L[1] && i2 <= 2 * a.hH) {
           const int64_t c = i2 - a.hH, j = c < 0 ? -c : c;
-          const cpx<T> f = a.src[(i0 * a.L[1] + i1) * a.L[2] + j];
-          const cpx<T> g = a.src[((a.L[0] - 1 - i0) * a.L[1] + (a.L[1] - 1 - i1)) * a.L[2] + j];
+          const cpx<T> f = a.src[i0 * l0 + i1 * l1 + j];
+          const cpx<T> g = a.src[(a.L[0] - 1 - i0) * l0 + (a.L[1] - 1 - i1) * l1 + j];
           v = c > 0 ? f : (c < 0 ? mk(g.x, -g.y) : mk(T(0.5) * (f.x + g.x), T(0.5) * (f.y - g.y)));
         }
         dst[i2] = v;

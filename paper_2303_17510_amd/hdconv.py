@@ -76,6 +76,9 @@ class Plan:
     ``copies`` (C) and ``dist``: each array holds C copies of the problem,
     ``dist`` words apart (default: dense, tensors of shape ``(C, *shape)``;
     with ``dist`` a flat tensor of at least ``(C-1) dist + n`` words).
+    ``strides`` (2D/3D): element strides of the outer dimensions (padded
+    rows); the tensors are then flat, of at least ``(C-1) dist + L[0]
+    strides[0]`` words.
     ``hermitian``: the last dimension holds the ``ceil(L/2)`` non-negative
     indices of a Hermitian centered array (``f_{-c} = conj f_c``; 2D/3D:
     ``F(k, -c) = conj F(-k, c)`` with centered outer dimensions of odd
@@ -87,7 +90,7 @@ class Plan:
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
                  db_path: str | None = None, centered: bool = False, hermitian: bool = False,
-                 copies: int = 1, dist: int = 0):
+                 copies: int = 1, dist: int = 0, strides=None):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if M is None:
@@ -107,6 +110,16 @@ class Plan:
         self.copies, self.dist = int(copies), int(dist)
         opt.copies = self.copies
         opt.dist = self.dist
+        self.strides = tuple(int(v) for v in strides) if strides else ()
+        for d, v in enumerate(self.strides[:2]):
+            opt.stride[d] = v
+        # words one copy spans (strided: the first dimension's stride times its extent)
+        if self.strides:
+            self.span = self.io_shape[0] * self.strides[0]
+        else:
+            self.span = 1
+            for v in self.io_shape:
+                self.span *= v
         if dims > 3 or len(M) != dims:
             raise ValueError("L and M need 1 to 3 matching dimensions")
         for d, v in enumerate(_tup(m, dims)):
@@ -168,11 +181,8 @@ class Plan:
         want = torch.complex64 if self.dtype_code == _L.C64 else torch.complex128
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError("%s must be a CUDA (HIP) tensor" % name)
-        if self.copies > 1 and self.dist:
-            n = 1
-            for v in self.io_shape:
-                n *= v
-            need = (self.copies - 1) * self.dist + n
+        if (self.copies > 1 and self.dist) or self.strides:
+            need = (self.copies - 1) * (self.dist or self.span) + self.span
             if t.dtype != want or t.dim() != 1 or t.numel() < need or not t.is_contiguous():
                 raise ValueError("%s must be a contiguous flat %s tensor of at least %d words" % (name, want, need))
             return

@@ -296,3 +296,12 @@ def test_copies_validation_and_accounting():
         assert p8.info()["traffic_bytes"] == pytest.approx(8 * p1.info()["traffic_bytes"])
     with Plan((1000,), copies=5, method="explicit", host_only=True) as p:
         assert p.info()["launches"] == 5 * 4  # pads, transform, truncation per copy
+
+
+def test_strides_validation():
+    with Plan((20, 30), strides=(40,), host_only=True) as p:
+        assert p.span == 800
+    for L, st in (((20, 30), (29,)), ((5, 6, 7), (50, 10)), ((100,), (200,))):
+        with pytest.raises(_lib.HdconvError) as ei:
+            Plan(L, strides=st, host_only=True)
+        assert ei.value.code == _lib.EINVAL

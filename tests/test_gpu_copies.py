@@ -113,3 +113,53 @@ def test_convolve_helper_flags(gpu):
         assert oracle.rel_l2(out[c].cpu().numpy(), oracle.conv_centered_direct([f[c], g[c]])) <= 1e-12
     h = convolve(torch.from_numpy(f[0]).cuda(), torch.from_numpy(g[0]).cuda(), hermitian=True)
     assert oracle.rel_l2(h.cpu().numpy(), oracle.conv_hermitian_direct([f[0], g[0]])) <= 1e-12
+
+
+def _positions(io, strides):
+    """Flat positions of a strided copy's elements (row-major over io)."""
+    st = list(strides) + [1]
+    if len(io) == 3 and len(strides) == 1:
+        st = [strides[0], io[2], 1]
+    grids = np.meshgrid(*[np.arange(n) * s for n, s in zip(io, st)], indexing="ij")
+    return sum(grids).ravel()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape,strides,copies,dist,kind,kw", [
+    ((20, 30), (40,), 1, 0, "plain", {}),
+    ((20, 30), (33,), 3, 700, "plain", {}),
+    ((6, 7, 9), (120, 12), 2, 0, "plain", {}),
+    ((6, 7, 9), (80,), 1, 0, "plain", {}),
+    ((33, 40), (48,), 2, 0, "centered", {}),
+    ((21, 64), (40,), 2, 0, "hermitian", {}),
+    ((20, 30), (40,), 2, 0, "plain", {"method": "explicit"}),
+    ((6, 7, 9), (120, 12), 1, 0, "plain", {"method": "explicit"}),
+    ((21, 64), (40,), 1, 0, "hermitian", {"method": "explicit"}),
+])
+def test_strided_layouts(gpu, dtype, shape, strides, copies, dist, kind, kw):
+    import torch
+    say("strided case", shape, strides, copies, dist, kind, dtype, kw)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    flags = {"centered": kind == "centered", "hermitian": kind == "hermitian"}
+    with Plan(shape, dtype=dtype, copies=copies, dist=dist, strides=strides, **flags, **kw) as p:
+        io, span = p.io_shape, p.span
+        step = dist or span
+        pos = _positions(io, strides)
+        total = (copies - 1) * step + span
+        xs = [[synth.unit_disk(io, 7800 + 10 * c + a).astype(npdt) for a in range(2)] for c in range(copies)]
+        bufs = []
+        for a in range(2):
+            b = np.full(total, SENTINEL, dtype=npdt)
+            for c in range(copies):
+                b[c * step + pos] = xs[c][a].ravel()
+            bufs.append(torch.from_numpy(b).cuda())
+        out = torch.full_like(bufs[0], SENTINEL)
+        p.execute(bufs, out)
+        torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    touched = np.zeros(total, bool)
+    for c in range(copies):
+        want = reference(kind, [synth.as_oracle(x) for x in xs[c]])
+        assert oracle.rel_l2(got[c * step + pos], want.ravel()) <= TOL[dtype], c
+        touched[c * step + pos] = True
+    assert np.all(got[~touched] == npdt(SENTINEL))  # padding and gaps untouched
