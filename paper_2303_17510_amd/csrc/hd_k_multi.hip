@@ -1,4 +1,6 @@
-// hd_k_multi.hip -- the three passes of the inner-loop form (Sec. 6.1).
+// hd_k_multi.hip -- the three passes of the inner-loop form (Sec. 6.1), with
+// the centered (signed block, folded) and Hermitian (mirrored half, paired
+// real rows) variants.
 #include "hd_kcommon.hpp"
 
 namespace hd {
@@ -8,12 +10,6 @@ namespace hd {
 // centered row with tneg blocks left of index 0 the signed block tau - p once
 // tau >= p - tneg (the p-point DFT is periodic in the block index).
 __device__ __forceinline__ int signed_block(int tau, int p, int tneg) { return tau < p - tneg ? tau : tau - p; }
-// zeta_q^{v t} index for a signed block t, -p <= t < p: v < n and q = n p,
-// so |v t| < q and one conditional add reduces it (no division).
-__device__ __forceinline__ int zq_index(int v, int t, int q) {
-  const int k = v * t;
-  return k < 0 ? k + q : k;
-}
 
 // Calls f(e, zeta_q^{v (g + G e)}) for e = 0 .. E-1 (v < n, so v (g + G e) <
 // q): the powers are composed from three table lookups, zeta_q^{v g},
