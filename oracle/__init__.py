@@ -29,6 +29,9 @@ Functions (Murasko & Bowman, arXiv 2303.17510):
   f_{Lh-1}`` of the centered Hermitian array ``f_{-j} = conj(f_j)`` (``f_0``
   taken real); the result is the centered convolution of the expanded arrays
   at ``c = 0 .. Lh-1`` (:func:`hermitian_expand` does the expansion).
+* :func:`conv_quadratic` -- general convolutions whose multiplication
+  operator is a quadratic form per output (``B`` outputs), through the
+  pairwise convolutions above (linearity of the DFT).
 * :func:`padded_dft` -- the padded DFT of Sec. 2,
   ``F_k = sum_{j<L} zeta_N^{kj} f_j`` with ``zeta_N = exp(+2 pi i/N)``.
 * :func:`fft` / :func:`fft_nd` -- the unnormalised transform
@@ -316,6 +319,33 @@ def conv_hermitian_explicit(inputs) -> np.ndarray:
     Lh = ins[0].shape[-1] if ins[0].ndim > 1 else ins[0].size
     full = conv_centered_explicit([hermitian_expand(x) for x in ins])
     return full[..., Lh - 1:]
+
+
+def conv_quadratic(inputs, coef, kind="plain") -> list:
+    """General convolution with a quadratic multiplication operator (Sec. 2:
+    ``mult`` maps the ``A`` transforms to ``B`` outputs pointwise): output b
+    has transform ``sum_{i <= j} coef[b][i][j] F_i F_j``, so by linearity of
+    the DFT it is ``sum_{i <= j} coef[b][i][j] (f_i * f_j)`` with ``*`` the
+    convolution of ``kind`` ("plain": first L outputs, "centered",
+    "hermitian").  ``coef`` is B x A x A (entries below the diagonal unused)."""
+    ins = [_c128(x) for x in inputs]
+    A = len(ins)
+    c = np.asarray(coef, dtype=np.float64)
+    if c.ndim != 3 or c.shape[1:] != (A, A):
+        raise ValueError("coef must be B x A x A")
+    pair = {"plain": conv_direct, "centered": conv_centered_direct, "hermitian": conv_hermitian_direct}[kind]
+    cache = {}
+    outs = []
+    for b in range(c.shape[0]):
+        acc = np.zeros(pair([ins[0], ins[0]]).shape, dtype=np.complex128)
+        for i in range(A):
+            for j in range(i, A):
+                if c[b, i, j] != 0:
+                    if (i, j) not in cache:
+                        cache[(i, j)] = pair([ins[i], ins[j]])
+                    acc += c[b, i, j] * cache[(i, j)]
+        outs.append(acc)
+    return outs
 
 
 def padded_dft(f, N: int, ks) -> np.ndarray:

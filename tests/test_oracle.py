@@ -434,3 +434,25 @@ def test_hermitian_nd_delta_and_symmetric_plane():
     np.testing.assert_allclose(oracle.conv_hermitian_direct([d, g]), g, atol=1e-15)
     with pytest.raises(ValueError):  # even outer extents have no symmetric range
         oracle.hermitian_expand(np.zeros((4, 3), complex))
+
+
+# ------------------------------------------- quadratic multiplication ----
+def test_quadratic_mult_basdevant_2d_form():
+    # two outputs u*u - v*v and u*v (the two-dimensional Basdevant products),
+    # checked against the DFT definition: pad, transform, combine pointwise,
+    # invert, keep the first L (numpy's FFT, independent of the oracle)
+    L = 37
+    u, v = rnd(L, 201), rnd(L, 202)
+    coef = [[[1, 0], [0, -1]], [[0, 1], [0, 0]]]
+    got = oracle.conv_quadratic([u, v], coef)
+    N = 2 * L - 1
+    U, V = np.fft.fft(u, N), np.fft.fft(v, N)
+    want = [np.fft.ifft(U * U - V * V)[:L], np.fft.ifft(U * V)[:L]]
+    for g_, w_ in zip(got, want):
+        assert oracle.rel_l2(g_, w_) < 1e-13
+    # centered and Hermitian kinds combine their own pairwise convolutions
+    c = oracle.conv_quadratic([u, v], coef, kind="centered")
+    assert oracle.rel_l2(c[1], oracle.conv_centered_direct([u, v])) < 1e-15
+    h = oracle.conv_quadratic([u, v], coef, kind="hermitian")
+    want_h = oracle.conv_hermitian_direct([u, u]) - oracle.conv_hermitian_direct([v, v])
+    assert oracle.rel_l2(h[0], want_h) < 1e-15
