@@ -70,7 +70,24 @@ def workload(name: str):
                             "complex64, Gaussian, hybrid",
                 "L": [2047, 2048], "M": [3072, 3072], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss",
                 "hermitian": True}
+    if name == "basdevant2d_hermitian":
+        return {"workload": "2D Hermitian quadratic conv (Basdevant: u^2-v^2, uv), A=2, B=2, 2047x2048 "
+                            "(2047x1024 stored), M=3072x3072, complex64, Gaussian, hybrid",
+                "L": [2047, 2048], "M": [3072, 3072], "A": 2, "dtype": "c64", "config_id": 3, "dist": "gauss",
+                "hermitian": True, "B": 2, "coef": BASDEVANT_2D}
+    if name == "basdevant3d":
+        return {"workload": "3D quadratic conv (Basdevant: u^2-w^2, v^2-w^2, uv, uw, vw), A=3, B=5, 256^3, "
+                            "M=512^3, complex64, unit disk, hybrid",
+                "L": [256] * 3, "M": [512] * 3, "A": 3, "dtype": "c64", "config_id": 4, "B": 5,
+                "coef": BASDEVANT_3D}
     raise SystemExit("unknown workload " + name)
+
+
+# Basdevant forms of the Navier-Stokes nonlinearity (coefficients c[b][i][j], i <= j)
+BASDEVANT_2D = [[[1, 0], [0, -1]], [[0, 1], [0, 0]]]
+BASDEVANT_3D = [[[1, 0, 0], [0, 0, 0], [0, 0, -1]], [[0, 0, 0], [0, 1, 0], [0, 0, -1]],
+                [[0, 1, 0], [0, 0, 0], [0, 0, 0]], [[0, 0, 1], [0, 0, 0], [0, 0, 0]],
+                [[0, 0, 0], [0, 0, 1], [0, 0, 0]]]
 
 
 def make_inputs(wl, dtype):
@@ -86,7 +103,7 @@ def make_inputs(wl, dtype):
 def time_plan(plan, dev, steps, warmup):
     """ms per execute over `steps` back-to-back executes, plus per-launch event stats."""
     import torch
-    out = torch.empty_like(dev[0])
+    out = torch.empty_like(dev[0]) if plan.B == 1 else [torch.empty_like(dev[0]) for _ in range(plan.B)]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.execute(dev, out)
@@ -154,12 +171,15 @@ def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None, **plan_kw):
         kw["centered"] = True
     if wl.get("hermitian"):
         kw["hermitian"] = True
+    if wl.get("B", 1) > 1:
+        kw.update(B=wl["B"], mult="quadratic", coef=wl["coef"])
     with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method, tuner=tuner, **kw) as p:
         plan_s = time.perf_counter() - t0
         info = p.info()
         ms, stats, out = time_plan(p, dev, steps, warmup)
     name, avg_ms, bpl, agg = dominant(stats)
-    n_out = 1  # outputs of the convolution (a Hermitian result of length L has L entries, half stored)
+    # outputs of the convolution (a Hermitian result of length L has L entries, half stored), all B arrays
+    n_out = wl.get("B", 1)
     for l in wl["L"]:
         n_out *= l
     r = {"stats": stats, "info": info, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
@@ -448,6 +468,16 @@ def main():
             put("hermitian_2047x2048_hybrid_c64", lambda: leg(wh4, "c64", "hybrid", 20, 3))
             put("hermitian_2047x2048_hybrid_c64_tuned", lambda: leg(wh4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
             put("hermitian_2047x2048_explicit_c64", lambda: leg(wh4, "c64", "explicit", 10, 2))
+            # quadratic operators (Basdevant forms): one plan for all outputs against the
+            # pairwise products it replaces (u^2, v^2, uv in 2D; six pairs in 3D)
+            for nm, wq, base, pairs in (("basdevant_2047x2048_hermitian_c64", workload("basdevant2d_hermitian"),
+                                         "hermitian_2047x2048_hybrid_c64", 3),
+                                        ("basdevant_256cube_c64", workload("basdevant3d"),
+                                         "C5_256cube_hybrid_c64", 6)):
+                r = put(nm, lambda: leg(wq, "c64", "hybrid", 10, 2))
+                if r and "ms" in compare.get(base, {}):
+                    compare[nm]["pairwise_products_ms"] = pairs * compare[base]["ms"]
+                    compare[nm]["speedup_vs_pairwise"] = pairs * compare[base]["ms"] / compare[nm]["ms"]
         for v in compare.values():
             v.pop("stats", None)
             v.pop("info", None)

@@ -21,6 +21,7 @@ PLAN_HOST_ONLY = 1
 BATCH_NO_GRAPH = 2
 PLAN_CENTERED = 4
 PLAN_HERMITIAN = 8
+MULT_PRODUCT, MULT_QUADRATIC = 0, 1
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
 NFEATURES = 44
 
@@ -36,7 +37,8 @@ class Options(ctypes.Structure):
                 ("variant", ctypes.c_int * 3), ("E_m", ctypes.c_int * 3), ("E_p", ctypes.c_int * 3),
                 ("S", ctypes.c_int * 3), ("rows_per_block", ctypes.c_int * 3), ("twiddles", ctypes.c_int * 3),
                 ("tuner", ctypes.c_int), ("tune_reps", ctypes.c_int), ("margin", ctypes.c_double),
-                ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("copies", _i64), ("dist", _i64), ("stride", _i64 * 2),
+                ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("copies", _i64), ("dist", _i64),
+                ("mult", ctypes.c_int), ("mult_coef", ctypes.POINTER(ctypes.c_double)), ("stride", _i64 * 2),
                 ("reserved", ctypes.c_int * 8)]
 
 

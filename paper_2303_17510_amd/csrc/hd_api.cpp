@@ -75,6 +75,11 @@ struct Plan {
   int64_t batch_rows = 1;                             // rows of a batched group
   int64_t copies = 1, dist = 0;                       // copies per execute, words between them
   int64_t stride[2] = {0, 0};                         // element strides of dims 0, 1 (0: dense)
+  int quad = 0;                                       // quadratic multiplication operator, B outputs
+  double coef[kMaxB][6] = {};                         // its coefficients per output (pair slots)
+  void* rowout = nullptr;                             // quadratic: result rows of the row pass
+  void* outbuf = nullptr;                             // quadratic 2D/3D: the innermost level's result
+  void* padout = nullptr;                             // quadratic explicit method: padded result
   int64_t span = 0;                                   // words one copy of an array spans
   int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
   double tuned_ms = 0;
@@ -253,6 +258,14 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
   return HDCONV_OK;
 }
 
+template <typename T>
+static QuadMult<T> quad_of(const Plan* P, int b) {
+  QuadMult<T> q{};
+  q.on = P->quad;
+  for (int k = 0; k < 6; ++k) q.c[k] = P->quad ? (T)P->coef[b][k] : T(0);
+  return q;
+}
+
 // Extent of dimension d as stored between passes: the engine length, or the
 // stored half of a Hermitian last dimension.
 static int64_t stored_extent(const DimPlan& dp) { return dp.herm ? herm_stored(dp.L) : dp.L; }
@@ -260,7 +273,8 @@ static int64_t stored_extent(const DimPlan& dp) { return dp.herm ? herm_stored(d
 // bytes moved by the kernels of one execute, by design (reads + writes)
 static double plan_traffic(const Plan* P, int* launches) {
   const double w = 2.0 * tbytes_of(P->dtype);
-  const int A = P->A, B = P->B;
+  const int A = P->A;
+  const int nout = P->quad ? P->B : 1;  // outputs, each through the row pass and the inverse passes
   double bytes = 0;
   int nl = 0;
   int64_t Le[3];
@@ -271,9 +285,9 @@ static double plan_traffic(const Plan* P, int* launches) {
     etot *= (double)Le[d];
   }
   if (P->method == HDCONV_METHOD_EXPLICIT) {
-    bytes += A * (ltot + etot) * w;  // padding copies
-    bytes += B * (etot + ltot) * w;  // truncating copy
-    nl += A + 1;
+    bytes += A * (ltot + etot) * w;     // padding copies
+    bytes += nout * (etot + ltot) * w;  // truncating copies
+    nl += A + nout;
   }
   double nb = 1;  // planes entering the current level
   for (int d = 0; d + 1 < P->dims; ++d) {
@@ -281,24 +295,26 @@ static double plan_traffic(const Plan* P, int* launches) {
     double rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (double)stored_extent(P->dp[e]);
     const double in_el = nb * Le[d] * rest, out_el = nb * dp.q * dp.m * rest;
-    bytes += A * (in_el + out_el) * w + B * (out_el + in_el) * w;  // forward + backward
-    nl += 2;
+    bytes += A * (in_el + out_el) * w + nout * (out_el + in_el) * w;  // forward + backward
+    nl += 1 + nout;
     nb *= (double)(dp.q * dp.m);
   }
   const DimPlan& dl = P->dp[P->dims - 1];
   // words each row reads per input and writes (Hermitian rows: the stored half)
   const double rows = nb, Lr = (double)(dl.herm ? P->Lio[P->dims - 1] : Le[P->dims - 1]);
   if (dl.variant == VAR_FUSED) {
-    bytes += rows * (A + B) * Lr * w;
-    nl += 1;
+    bytes += nout * rows * (A + 1) * Lr * w;
+    nl += nout;
   } else {
     const int64_t blocks = cdiv(dl.n, dl.D);
     const double wk = rows * (double)dl.q * dl.m;  // all residues' rows
-    bytes += blocks * rows * A * Lr * w + A * wk * w;  // K1: read inputs per block, write work
-    bytes += (A + B) * wk * w;                         // K2
-    bytes += B * wk * w + rows * B * Lr * w;           // K3
-    if (blocks > 1) bytes += (2.0 * blocks - 2) * rows * B * Lr * 16.0;  // FP64 accumulator round trips
-    nl += 3 * (int)blocks;
+    // K1 (read inputs per block, write work) once, or per output with blocks
+    const int k1_runs = blocks > 1 ? nout : 1;
+    bytes += k1_runs * (blocks * rows * A * Lr * w + A * wk * w);
+    bytes += nout * (A + 1) * wk * w;             // K2
+    bytes += nout * (wk * w + rows * Lr * w);     // K3
+    if (blocks > 1) bytes += nout * (2.0 * blocks - 2) * rows * Lr * 16.0;  // FP64 accumulator round trips
+    nl += k1_runs * (int)blocks + nout * 2 * (int)blocks;
   }
   if (launches) *launches = P->method == HDCONV_METHOD_EXPLICIT ? nl * (int)P->copies : nl;
   return bytes * (double)P->copies;
@@ -395,9 +411,19 @@ static int alloc_workspace(Plan* P) {
     for (int a = 0; a < P->A; ++a) want.push_back({&P->lvl[d][a], nb * rest * w});
   }
   const DimPlan& dl = P->dp[P->dims - 1];
+  if (P->quad && P->method == HDCONV_METHOD_EXPLICIT) {  // padded result of one output
+    size_t n = 1;
+    for (int d = 0; d < P->dims; ++d) n *= (size_t)P->npad[d];
+    want.push_back({&P->padout, n * w});
+  }
+  if (P->quad && P->dims > 1) {  // the innermost level's result of one output
+    size_t last = nb;
+    want.push_back({&P->outbuf, last * (size_t)stored_extent(P->dp[P->dims - 1]) * w});
+  }
   if (dl.variant == VAR_MULTI) {
     const size_t rowsz = nb * (size_t)(dl.D * dl.p * dl.m);
     for (int a = 0; a < P->A; ++a) want.push_back({&P->rowwork[a], rowsz * w});
+    if (P->quad) want.push_back({&P->rowout, rowsz * w});
     // the FP64 accumulator is laid out like the rows' output (1D copies: dist apart)
     size_t acc_rows = nb, acc_len = (size_t)Le[P->dims - 1];
     if (P->dims == 1 && P->copies > 1 && P->method != HDCONV_METHOD_EXPLICIT) {
@@ -446,9 +472,11 @@ static RootTable<T> rtab(const Plan* P, int d) {
 
 // rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L,
 // or (tasks != NULL) nrows independent rows described by a device task table
+// `b` selects the output of a quadratic multiplication operator; `skip_fwd`
+// reuses the column pass of the previous output (one residue block only).
 template <typename T>
 static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s,
-                    const RowTask<T>* tasks = nullptr, int64_t row_stride = 0) {
+                    const RowTask<T>* tasks = nullptr, int64_t row_stride = 0, int b = 0, bool skip_fwd = false) {
   const int d = P->dims - 1;
   const DimPlan& dp = P->dp[d];
   const int A = P->A;
@@ -471,6 +499,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     // paired real residue transforms (measured: 2047 x 2048 FP32 inner rows
     // 160 -> 134 us, L = 4096 42 -> 34 us)
     a.pair = dp.herm;
+    a.quad = quad_of<T>(P, b);
     a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
     a.fd = dp.fd_m;
     a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
@@ -508,14 +537,17 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
     k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
     k1.zq = (const cpx<T>*)P->dd[d].zq;
     const double wb = 2.0 * sizeof(T);
-    {
+    if (!skip_fwd) {
       ProfScope ps(P, s, "cols_fwd", (double)nrows * A * ((double)stored_extent(dp) + (double)D * dp.p * dp.m) * wb);
       e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
+      if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
     }
-    if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
 
     RowConvArgs<T> k2{};
     for (int i = 0; i < A; ++i) k2.work[i] = (cpx<T>*)P->rowwork[i];
+    // quadratic operators keep the transformed inputs for the other outputs
+    k2.out = P->quad ? (cpx<T>*)P->rowout : nullptr;
+    k2.quad = quad_of<T>(P, b);
     k2.nrows = nrows * D * dp.p;
     k2.m = (int)dp.m;
     k2.p = (int)dp.p;
@@ -539,7 +571,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
 
     ColBwdArgs<T> k3{};
     k3.tasks = tasks;
-    k3.work = (const cpx<T>*)P->rowwork[0];
+    k3.work = (const cpx<T>*)(P->quad ? P->rowout : P->rowwork[0]);
     k3.out = out;
     k3.acc = P->acc64;
     k3.acc_mode = nblk == 1 ? ACC_WRITE : (blk == 0 ? ACC_FIRST : (blk == nblk - 1 ? ACC_LAST : ACC_ADD));
@@ -577,8 +609,12 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
 // the number of copies this call covers (the explicit method calls it once
 // per copy with nc = 1).
 template <typename T>
-static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream_t s, int64_t nc) {
+static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, hipStream_t s, int64_t nc) {
   const int A = P->A;
+  // outputs computed one after another (quadratic operators), each through
+  // the row pass and the outer inverse passes; the forward passes run once
+  const int nout = P->quad ? P->B : 1;
+  const int Aeff = P->quad ? 2 : A;  // factors per product (window offsets)
   hipError_t e;
   int64_t Le[3];
   for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
@@ -596,7 +632,12 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
     }
   }
   const cpx<T>* cur[kMaxA];
-  cpx<T>* final_out = (cpx<T>*)out_v;
+  // where the engine leaves output b: the user's array, or for the explicit
+  // method its padded buffer (in place over the first input for products)
+  auto engine_out = [&](int b) -> cpx<T>* {
+    if (P->method != HDCONV_METHOD_EXPLICIT) return (cpx<T>*)outputs[b];
+    return (cpx<T>*)(P->quad ? P->padout : P->pad_in[0]);
+  };
   if (P->method == HDCONV_METHOD_EXPLICIT) {
     for (int a = 0; a < A; ++a) {
       BoxCopyArgs<T> b{};
@@ -628,7 +669,6 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
       if (e != hipSuccess) return hip_err(e, "pad launch");
       cur[a] = (const cpx<T>*)P->pad_in[a];
     }
-    final_out = (cpx<T>*)P->pad_in[0];
   } else {
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)inputs[a];
   }
@@ -665,84 +705,98 @@ static int run_copies(Plan* P, const void* const* inputs, void* out_v, hipStream
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
     nb *= dp.q * dp.m;
   }
-  // innermost rows
-  {
-    cpx<T>* rows_out = P->dims == 1 ? final_out : (cpx<T>*)P->lvl[P->dims - 2][0];
-    int rc = run_rows<T>(P, cur, rows_out, nb, s, nullptr, P->dims == 1 ? dist : 0);
-    if (rc != HDCONV_OK) return rc;
-  }
-  // outer dimensions, backward
-  for (int d = P->dims - 2; d >= 0; --d) {
-    const DimPlan& dp = P->dp[d];
-    nb /= dp.q * dp.m;
-    int64_t rest = 1;
-    for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
-    OuterBwdArgs<T> o{};
-    o.y = (const cpx<T>*)P->lvl[d][0];
-    o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
-    o.acc = nullptr;
-    o.acc_mode = ACC_WRITE;
-    o.nb = nb;
-    o.out_bstride = d == 0 ? dist : Le[d] * rest;
-    if (d == 0) o.lay = user;
-    o.R = rest;
-    o.L = Le[d];
-    o.m = (int)dp.m;
-    o.q = (int)dp.q;
-    o.r0 = 0;
-    o.D = (int)dp.q;
-    o.S = dp.S;
-    o.ctr = dp.ctr;
-    o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
-    o.fd = dp.fd_m;
-    o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
-    o.zqm = rtab<T>(P, d);
+  const int64_t nb_rows = nb;
+  for (int ob = 0; ob < nout; ++ob) {
+    nb = nb_rows;
+    cpx<T>* final_out = engine_out(ob);
+    // innermost rows (products: in place over the first input's level)
+    cpx<T>* rows_out = P->dims == 1 ? final_out
+                                    : (cpx<T>*)(P->quad ? P->outbuf : P->lvl[P->dims - 2][0]);
     {
-      ProfScope ps(P, s, "outer_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
-      e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
+      const bool one_block = P->dp[P->dims - 1].variant != VAR_MULTI ||
+                             P->dp[P->dims - 1].D >= P->dp[P->dims - 1].n;
+      int rc = run_rows<T>(P, cur, rows_out, nb, s, nullptr, P->dims == 1 ? dist : 0, ob, ob > 0 && one_block);
+      if (rc != HDCONV_OK) return rc;
     }
-    if (e != hipSuccess) return hip_err(e, "outer_bwd launch");
-  }
-  if (P->method == HDCONV_METHOD_EXPLICIT) {
-    BoxCopyArgs<T> b{};
-    b.src = (const cpx<T>*)P->pad_in[0];
-    b.dst = (cpx<T>*)out_v;
-    for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
-    for (int d = 0; d < P->dims; ++d) {
-      b.L[3 - P->dims + d] = P->Lio[d];
-      b.N[3 - P->dims + d] = P->npad[d];
-      // centered: entries (A-1)H .. (A-1)H+L-1 of the padded product are the
-      // outputs -H .. L-1-H (the arrays were padded as they are, index c at
-      // position c + H, so a product of A of them sits A H further on);
-      // Hermitian: the outputs c >= 0 start at A H (H = Lh - 1)
-      if ((P->flags & HDCONV_PLAN_HERMITIAN) && d == P->dims - 1) b.off[3 - P->dims + d] = (int64_t)A * (P->Lio[d] - 1);
-      else if (P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
-        b.off[3 - P->dims + d] = (int64_t)(A - 1) * (P->L[d] / 2);
+    // outer dimensions, backward (the first level's transformed inputs are
+    // free by now and carry the intermediate levels of every output)
+    const cpx<T>* yl = rows_out;
+    for (int d = P->dims - 2; d >= 0; --d) {
+      const DimPlan& dp = P->dp[d];
+      nb /= dp.q * dp.m;
+      int64_t rest = 1;
+      for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
+      OuterBwdArgs<T> o{};
+      o.y = yl;
+      o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
+      o.acc = nullptr;
+      o.acc_mode = ACC_WRITE;
+      o.nb = nb;
+      o.out_bstride = d == 0 ? dist : Le[d] * rest;
+      if (d == 0) o.lay = user;
+      o.R = rest;
+      o.L = Le[d];
+      o.m = (int)dp.m;
+      o.q = (int)dp.q;
+      o.r0 = 0;
+      o.D = (int)dp.q;
+      o.S = dp.S;
+      o.ctr = dp.ctr;
+      o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+      o.fd = dp.fd_m;
+      o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+      o.zqm = rtab<T>(P, d);
+      {
+        ProfScope ps(P, s, "outer_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+        e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "outer_bwd launch");
+      yl = o.out;
     }
-    b.pad = 0;
-    if (P->dims >= 2) {
-      b.ls[3 - P->dims] = P->stride[0];
-      if (P->dims == 3) b.ls[1] = P->stride[1];
+    if (P->method == HDCONV_METHOD_EXPLICIT) {
+      BoxCopyArgs<T> b{};
+      b.src = final_out;
+      b.dst = (cpx<T>*)outputs[ob];
+      for (int k = 0; k < 3; ++k) b.L[k] = b.N[k] = 1;
+      for (int d = 0; d < P->dims; ++d) {
+        b.L[3 - P->dims + d] = P->Lio[d];
+        b.N[3 - P->dims + d] = P->npad[d];
+        // centered: entries (F-1)H .. (F-1)H+L-1 of the padded product of F
+        // factors are the outputs -H .. L-1-H (the arrays were padded as they
+        // are, index c at position c + H, so a product of F of them sits F H
+        // further on); Hermitian: the outputs c >= 0 start at F H (H = Lh - 1)
+        if ((P->flags & HDCONV_PLAN_HERMITIAN) && d == P->dims - 1)
+          b.off[3 - P->dims + d] = (int64_t)Aeff * (P->Lio[d] - 1);
+        else if (P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
+          b.off[3 - P->dims + d] = (int64_t)(Aeff - 1) * (P->L[d] / 2);
+      }
+      b.pad = 0;
+      if (P->dims >= 2) {
+        b.ls[3 - P->dims] = P->stride[0];
+        if (P->dims == 3) b.ls[1] = P->stride[1];
+      }
+      {
+        double lt = 1;
+        for (int d = 0; d < P->dims; ++d) lt *= (double)P->Lio[d];
+        ProfScope ps(P, s, "truncate", 2.0 * lt * 2.0 * sizeof(T));
+        e = launch_box_copy<T>(b, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "truncate launch");
     }
-    {
-      double lt = 1;
-      for (int d = 0; d < P->dims; ++d) lt *= (double)P->Lio[d];
-      ProfScope ps(P, s, "truncate", 2.0 * lt * 2.0 * sizeof(T));
-      e = launch_box_copy<T>(b, s);
-    }
-    if (e != hipSuccess) return hip_err(e, "truncate launch");
   }
   return HDCONV_OK;
 }
 
 template <typename T>
-static int run_plan(Plan* P, const void* const* inputs, void* out_v, hipStream_t s) {
-  if (P->method != HDCONV_METHOD_EXPLICIT || P->copies == 1) return run_copies<T>(P, inputs, out_v, s, P->copies);
+static int run_plan(Plan* P, const void* const* inputs, void* const* outputs, hipStream_t s) {
+  if (P->method != HDCONV_METHOD_EXPLICIT || P->copies == 1) return run_copies<T>(P, inputs, outputs, s, P->copies);
   // the explicit baseline pads one copy at a time into its work buffers
   for (int64_t c = 0; c < P->copies; ++c) {
     const void* in_c[kMaxA];
+    void* out_c[kMaxB];
     for (int a = 0; a < P->A; ++a) in_c[a] = (const cpx<T>*)inputs[a] + c * P->dist;
-    int rc = run_copies<T>(P, in_c, (cpx<T>*)out_v + c * P->dist, s, 1);
+    for (int b = 0; b < P->B; ++b) out_c[b] = (cpx<T>*)outputs[b] + c * P->dist;
+    int rc = run_copies<T>(P, in_c, out_c, s, 1);
     if (rc != HDCONV_OK) return rc;
   }
   return HDCONV_OK;
@@ -799,8 +853,21 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     set_err(HDCONV_EUNSUPPORTED, "A must be 2 or 3 (got %d)", A);
     return nullptr;
   }
-  if (B != 1) {
-    set_err(HDCONV_EUNSUPPORTED, "only B = 1 (product of the inputs) is supported (got %d)", B);
+  const bool quad = opt && opt->mult == HDCONV_MULT_QUADRATIC;
+  if (opt && opt->mult != HDCONV_MULT_PRODUCT && !quad) {
+    set_err(HDCONV_EINVAL, "unknown multiplication operator %d", opt->mult);
+    return nullptr;
+  }
+  if (!quad && B != 1) {
+    set_err(HDCONV_EUNSUPPORTED, "the product operator has B = 1 output (got %d); use HDCONV_MULT_QUADRATIC", B);
+    return nullptr;
+  }
+  if (quad && (B < 1 || B > kMaxB || !opt->mult_coef)) {
+    set_err(HDCONV_EINVAL, "a quadratic operator needs 1 <= B <= %d and its coefficients (got B = %d)", kMaxB, B);
+    return nullptr;
+  }
+  if (quad && opt->tuner != HDCONV_TUNER_HEURISTIC) {
+    set_err(HDCONV_EUNSUPPORTED, "quadratic operators use the heuristic planner");
     return nullptr;
   }
   if (dtype != HDCONV_C64 && dtype != HDCONV_C128) {
@@ -822,12 +889,14 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     }
     const bool ctr = opt && (opt->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN));
     const bool hd = herm && d == dims - 1;
-    const int64_t Mmin = hd ? centered_min_padding(herm_full(L[d]), A)
-                            : (ctr ? centered_min_padding(L[d], A) : (int64_t)A * (L[d] - 1) + 1);
+    const int F = quad ? 2 : A;  // factors per product
+    const int64_t Mmin = hd ? centered_min_padding(herm_full(L[d]), F)
+                            : (ctr ? centered_min_padding(L[d], F) : (int64_t)F * (L[d] - 1) + 1);
     if (M[d] < Mmin) {
       set_err(HDCONV_EINVAL, "M[%d] = %lld is below %s = %lld, so the product would alias", d, (long long)M[d],
-              hd ? "the Hermitian minimum (A+1)(ceil(L/2)-1)+1"
-                   : (ctr ? "the centered minimum max(A(L-1-H)+H, L-1-H+AH)+1" : "A(L-1)+1"),
+              hd ? "the Hermitian minimum (F+1)(ceil(L/2)-1)+1 (F factors per product)"
+                 : (ctr ? "the centered minimum max(F(L-1-H)+H, L-1-H+FH)+1 (F factors per product)"
+                        : "F(L-1)+1 (F factors per product)"),
               (long long)Mmin);
       return nullptr;
     }
@@ -866,6 +935,13 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->method = (opt && opt->method == HDCONV_METHOD_EXPLICIT) ? HDCONV_METHOD_EXPLICIT : HDCONV_METHOD_HYBRID;
   P->flags = opt ? opt->flags : 0;
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
+  if (quad) {
+    // coef is B x A x A (row-major); the pair (i, j), i <= j, weighs F_i F_j
+    P->quad = 1;
+    for (int b = 0; b < B; ++b)
+      for (int i = 0; i < A; ++i)
+        for (int j = i; j < A; ++j) P->coef[b][pair_slot(i, j)] = opt->mult_coef[(b * A + i) * A + j];
+  }
   {
     int64_t ext[3];
     for (int d = 0; d < dims; ++d) ext[d] = (herm && d == dims - 1) ? (L[d] + 1) / 2 : L[d];
@@ -996,20 +1072,30 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
       2 * (size_t)tbytes_of(P->dtype) * ((size_t)(P->copies - 1) * (size_t)P->dist + (size_t)P->span);
   for (int a = 0; a < P->A; ++a)
     if (!inputs[a]) return set_err(HDCONV_EINVAL, "inputs[%d] is NULL", a);
-  if (!outputs[0]) return set_err(HDCONV_EINVAL, "outputs[0] is NULL");
+  for (int b = 0; b < P->B; ++b)
+    if (!outputs[b]) return set_err(HDCONV_EINVAL, "outputs[%d] is NULL", b);
+  auto overlap = [&](const char* x, const char* y) { return x < y + bytes && y < x + bytes; };
   const char* o = (const char*)outputs[0];
   for (int a = 0; a < P->A; ++a) {
     const char* i = (const char*)inputs[a];
-    if (i != o && i < o + bytes && o < i + bytes)
+    if (P->B == 1 && i != o && overlap(i, o))
       return set_err(HDCONV_EINVAL, "outputs[0] partially overlaps inputs[%d]", a);
+    // several outputs are written one after another: none may touch an input
+    for (int b = 0; P->B > 1 && b < P->B; ++b)
+      if (overlap(i, (const char*)outputs[b]))
+        return set_err(HDCONV_EINVAL, "outputs[%d] overlaps inputs[%d] (B > 1 runs out of place)", b, a);
   }
+  for (int b = 0; b < P->B; ++b)
+    for (int c = b + 1; c < P->B; ++c)
+      if (overlap((const char*)outputs[b], (const char*)outputs[c]))
+        return set_err(HDCONV_EINVAL, "outputs[%d] and outputs[%d] overlap", b, c);
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (cur != P->device) return set_err(HDCONV_EINVAL, "plan belongs to device %d, current device is %d", P->device, cur);
   hipStream_t s = (hipStream_t)stream;
   P->prof.slot = 0;
-  int rc = P->dtype == HDCONV_C64 ? run_plan<float>(P, inputs, outputs[0], s)
-                                  : run_plan<double>(P, inputs, outputs[0], s);
+  int rc = P->dtype == HDCONV_C64 ? run_plan<float>(P, inputs, outputs, s)
+                                  : run_plan<double>(P, inputs, outputs, s);
   if (P->prof.on && P->prof.used < P->prof.max_exec) P->prof.used++;
   return rc;
 }

@@ -35,6 +35,17 @@
 namespace hd {
 
 constexpr int kMaxA = 3;
+constexpr int kMaxB = 6;  // outputs of a quadratic multiplication operator
+
+// Quadratic multiplication operator (Sec. 2: mult maps the A transforms to B
+// outputs pointwise): one output's H = sum_{i <= j} c_ij F_i F_j, the pairs
+// (0,0), (0,1), (0,2), (1,1), (1,2), (2,2) in slots 0 .. 5 (unused: 0).
+template <typename T>
+struct QuadMult {
+  int on;     // 0: the product of the A transforms (B = 1)
+  T c[6];
+};
+__host__ __device__ constexpr int pair_slot(int i, int j) { return i == 0 ? j : (i == 1 ? 2 + j : 5); }
 
 // Accumulation of one residue block into the output (blocks of D residues):
 //   ACC_WRITE : out  = sum * scale              (single block)
@@ -70,6 +81,7 @@ struct FusedArgs {
   int ctr;   // 1: centered rows (H = floor(L/2) of each row's own L)
   int herm;  // 1: Hermitian rows (half storage, see above)
   int pair;  // 1: Hermitian rows transform two residues per complex transform
+  QuadMult<T> quad;  // multiplication operator of the output this launch computes
   T scale;  // 1/(q m)
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
@@ -102,6 +114,8 @@ struct ColFwdArgs {
 template <typename T>
 struct RowConvArgs {
   cpx<T>* work[kMaxA];
+  cpx<T>* out;  // result rows (nullptr: in place, over work[0])
+  QuadMult<T> quad;
   int64_t nrows;  // rows of the work buffer (= batch * D * p)
   int m, p, n, v0, D;
   int rows_per_block;

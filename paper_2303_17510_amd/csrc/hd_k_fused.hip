@@ -120,22 +120,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
     gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
     cpx<T> prod[1][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      cpx<T> pr = w[0][e];
-      if (HERM && pair) {
-        T pa = w[0][e].x, pb = w[0][e].y;
-#pragma unroll
-        for (int ai = 1; ai < A; ++ai) {
-          pa *= w[ai][e].x;
-          pb *= w[ai][e].y;
-        }
-        pr = mk(pa, pb);
-      } else {
-#pragma unroll
-        for (int ai = 1; ai < A; ++ai) pr = cmul(pr, w[ai][e]);
-      }
-      prod[0][e] = pr;
-    }
+    for (int e = 0; e < E; ++e) prod[0][e] = (HERM && pair) ? mult_at_real_pair(w, e, a.quad) : mult_at(w, e, a.quad);
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
     if constexpr (HERM) {
       if (pair) {

@@ -182,22 +182,7 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
   cpx<T> prod[1][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    cpx<T> pr = x[0][e];
-    if constexpr (HERM) {
-      T pa = x[0][e].x, pb = x[0][e].y;
-#pragma unroll
-      for (int ai = 1; ai < A; ++ai) {
-        pa *= x[ai][e].x;
-        pb *= x[ai][e].y;
-      }
-      pr = mk(pa, pb);
-    } else {
-#pragma unroll
-      for (int ai = 1; ai < A; ++ai) pr = cmul(pr, x[ai][e]);
-    }
-    prod[0][e] = pr;
-  }
+  for (int e = 0; e < E; ++e) prod[0][e] = HERM ? mult_at_real_pair(x, e, a.quad) : mult_at(x, e, a.quad);
   gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
   if constexpr (HERM) {
     // Y(-s) from the lane that holds it, through LDS
@@ -212,7 +197,7 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
       ym[e] = xb.at(0, sidx ? m - sidx : 0);
     }
     if (valid_b) {
-      cpx<T>* dstb = a.work[0] + (R2 + 1) * m;
+      cpx<T>* dstb = (a.out ? a.out : a.work[0]) + (R2 + 1) * m;
       a.zqm.template run<E>(rb * (uint32_t)g, rb * (uint32_t)G, [&](int e, cpx<T> z) {
         const cpx<T> yv = prod[0][e];  // y_b = -i (Y - conj Ym) / 2
         st_at(dstb, (uint32_t)(g + G * e), cmulc(mk(T(0.5) * (yv.y + ym[e].y), T(0.5) * (ym[e].x - yv.x)), z));
@@ -223,7 +208,7 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
       prod[0][e] = mk(T(0.5) * (prod[0][e].x + ym[e].x), T(0.5) * (prod[0][e].y - ym[e].y));
   }
   if (valid) {
-    cpx<T>* dst = a.work[0] + R2 * m;
+    cpx<T>* dst = (a.out ? a.out : a.work[0]) + R2 * m;
     a.zqm.template run<E>(r * (uint32_t)g, r * (uint32_t)G, [&](int e, cpx<T> z) {
       st_at(dst, (uint32_t)(g + G * e), cmulc(prod[0][e], z));
     });

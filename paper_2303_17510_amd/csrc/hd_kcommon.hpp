@@ -46,6 +46,49 @@ __device__ __forceinline__ cpx<T> herm_value(const cpx<T>* src, int64_t c) {
   return v;
 }
 
+// The pointwise multiplication operator at point e: the product of the A
+// transforms, or the quadratic form sum_{i <= j} c_ij F_i F_j.
+template <typename T, int A, int E>
+__device__ __forceinline__ cpx<T> mult_at(const cpx<T> (&w)[A][E], int e, const QuadMult<T>& q) {
+  cpx<T> pr = w[0][e];
+  if (!q.on) {
+#pragma unroll
+    for (int ai = 1; ai < A; ++ai) pr = cmul(pr, w[ai][e]);
+    return pr;
+  }
+  pr = czero<T>();
+#pragma unroll
+  for (int i = 0; i < A; ++i)
+#pragma unroll
+    for (int j = i; j < A; ++j) pr = pr + cscale(cmul(w[i][e], w[j][e]), q.c[pair_slot(i, j)]);
+  return pr;
+}
+// The same for two packed real transforms (Hermitian pairs): x parts and y
+// parts separately.
+template <typename T, int A, int E>
+__device__ __forceinline__ cpx<T> mult_at_real_pair(const cpx<T> (&w)[A][E], int e, const QuadMult<T>& q) {
+  T pa = w[0][e].x, pb = w[0][e].y;
+  if (!q.on) {
+#pragma unroll
+    for (int ai = 1; ai < A; ++ai) {
+      pa *= w[ai][e].x;
+      pb *= w[ai][e].y;
+    }
+    return mk(pa, pb);
+  }
+  pa = T(0);
+  pb = T(0);
+#pragma unroll
+  for (int i = 0; i < A; ++i)
+#pragma unroll
+    for (int j = i; j < A; ++j) {
+      const T c = q.c[pair_slot(i, j)];
+      pa += c * w[i][e].x * w[j][e].x;
+      pb += c * w[i][e].y * w[j][e].y;
+    }
+  return mk(pa, pb);
+}
+
 template <typename T>
 __device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, int64_t i, cpx<T> v, T scale) {
   if (mode == ACC_WRITE) {

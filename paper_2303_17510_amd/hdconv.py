@@ -83,6 +83,10 @@ class Plan:
     indices of a Hermitian centered array (``f_{-c} = conj f_c``; 2D/3D:
     ``F(k, -c) = conj F(-k, c)`` with centered outer dimensions of odd
     extent), and so does the output; ``M`` defaults to the minimum padding.
+    ``mult="quadratic"`` with real coefficients ``coef`` of shape
+    ``(B, A, A)``: B outputs, output b = sum_{i <= j} coef[b][i][j] F_i F_j
+    pointwise in transform space (entries below the diagonal unused); the
+    padding rule is that of two factors.
     """
 
     def __init__(self, L: Sequence[int], M: Sequence[int] | None = None, A: int = 2, B: int = 1,
@@ -90,12 +94,15 @@ class Plan:
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
                  db_path: str | None = None, centered: bool = False, hermitian: bool = False,
-                 copies: int = 1, dist: int = 0, strides=None):
+                 copies: int = 1, dist: int = 0, strides=None, mult: str = "product", coef=None):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
+        if mult not in ("product", "quadratic"):
+            raise ValueError("mult must be 'product' or 'quadratic'")
+        F = 2 if mult == "quadratic" else A  # factors per output term
         if M is None:
-            M = tuple(hermitian_min_padding(l, A) if (hermitian and d == dims - 1) else
-                      (centered_min_padding(l, A) if (centered or hermitian) else A * l) for d, l in enumerate(L))
+            M = tuple(hermitian_min_padding(l, F) if (hermitian and d == dims - 1) else
+                      (centered_min_padding(l, F) if (centered or hermitian) else F * l) for d, l in enumerate(L))
         M = (int(M),) if isinstance(M, int) else tuple(int(v) for v in M)
         self.L, self.M, self.A, self.B, self.dims = L, M, A, B, dims
         self.dtype_code = dtype_code(dtype)
@@ -110,6 +117,15 @@ class Plan:
         self.copies, self.dist = int(copies), int(dist)
         opt.copies = self.copies
         opt.dist = self.dist
+        self.mult = mult
+        self._coef = None
+        if mult == "quadratic":
+            if coef is None:
+                raise ValueError("a quadratic operator needs coef of shape (B, A, A)")
+            flat = [float(coef[b][i][j]) for b in range(B) for i in range(A) for j in range(A)]
+            self._coef = (ctypes.c_double * len(flat))(*flat)
+            opt.mult = _L.MULT_QUADRATIC
+            opt.mult_coef = ctypes.cast(self._coef, ctypes.POINTER(ctypes.c_double))
         self.strides = tuple(int(v) for v in strides) if strides else ()
         for d, v in enumerate(self.strides[:2]):
             opt.stride[d] = v
@@ -192,17 +208,22 @@ class Plan:
                              % (name, want, shape, t.dtype, tuple(t.shape)))
 
     def execute(self, inputs, out, stream=None):
-        """Run asynchronously on ``stream`` (default: torch's current stream)."""
+        """Run asynchronously on ``stream`` (default: torch's current stream).
+        ``out``: one tensor, or a sequence of B tensors (B > 1)."""
         torch = _torch()
         if len(inputs) != self.A:
             raise ValueError("expected %d inputs" % self.A)
         for i, t in enumerate(inputs):
             self._check_tensor(t, "inputs[%d]" % i)
-        self._check_tensor(out, "out")
+        outs_t = list(out) if isinstance(out, (list, tuple)) else [out]
+        if len(outs_t) != self.B:
+            raise ValueError("expected %d outputs" % self.B)
+        for b, t in enumerate(outs_t):
+            self._check_tensor(t, "out[%d]" % b)
         if stream is None:
-            stream = torch.cuda.current_stream(out.device)
+            stream = torch.cuda.current_stream(outs_t[0].device)
         ins = (ctypes.c_void_p * self.A)(*[t.data_ptr() for t in inputs])
-        outs = (ctypes.c_void_p * 1)(out.data_ptr())
+        outs = (ctypes.c_void_p * self.B)(*[t.data_ptr() for t in outs_t])
         _L.check(_L.lib().hdconv_execute(self._h, ins, outs, ctypes.c_void_p(stream.cuda_stream)))
         return out
 
@@ -226,8 +247,9 @@ class Plan:
 
     def __call__(self, *inputs):
         torch = _torch()
-        out = torch.empty_like(inputs[0])
-        return self.execute(inputs, out)
+        if self.B == 1:
+            return self.execute(inputs, torch.empty_like(inputs[0]))
+        return self.execute(inputs, [torch.empty_like(inputs[0]) for _ in range(self.B)])
 
     def close(self):
         h, self._h = getattr(self, "_h", None), None
@@ -363,7 +385,8 @@ def convolve(*inputs, M=None, **kw):
     """One-shot convolution of equal-shape complex CUDA tensors (first L
     outputs; with ``centered`` / ``hermitian`` the centered or Hermitian
     convolution, the tensors then holding the stored halves; with ``copies``
-    the leading dimension counts the copies)."""
+    the leading dimension counts the copies; with ``mult="quadratic"``,
+    ``B`` and ``coef``, the list of B outputs)."""
     L = tuple(inputs[0].shape)
     if kw.get("copies", 1) > 1:
         L = L[1:]
@@ -373,5 +396,5 @@ def convolve(*inputs, M=None, **kw):
     with Plan(L, M, A=len(inputs), dtype=inputs[0].dtype, **kw) as p:
         out = p(*inputs)
         import torch
-        torch.cuda.current_stream(out.device).synchronize()
+        torch.cuda.current_stream(inputs[0].device).synchronize()
     return out

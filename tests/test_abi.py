@@ -305,3 +305,40 @@ def test_strides_validation():
         with pytest.raises(_lib.HdconvError) as ei:
             Plan(L, strides=st, host_only=True)
         assert ei.value.code == _lib.EINVAL
+
+
+def test_quadratic_operator_validation_and_accounting():
+    basdevant = [[[1, 0], [0, -1]], [[0, 1], [0, 0]]]  # B = 2 outputs of A = 2 inputs
+    # two factors per term: A = 3 inputs pad like A = 2
+    coef3 = [[[1 if (i, j) == (0, 1) else 0 for j in range(3)] for i in range(3)]]
+    with Plan((100,), (199,), A=3, B=1, mult="quadratic", coef=coef3, host_only=True) as p:
+        assert p.info()["B"] == 1
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), (198,), A=3, B=1, mult="quadratic", coef=coef3, host_only=True)
+    assert ei.value.code == _lib.EINVAL
+    # default M follows the two-factor rule too
+    with Plan((100,), A=3, B=1, mult="quadratic", coef=coef3, host_only=True) as p:
+        assert p.M == (200,)
+    with pytest.raises(ValueError):
+        Plan((100,), B=2, mult="quadratic", host_only=True)  # no coefficients
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), B=7, mult="quadratic", coef=[basdevant[0]] * 7, host_only=True)
+    assert ei.value.code == _lib.EINVAL
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), B=2, mult="quadratic", coef=basdevant, tuner="exhaustive")
+    assert ei.value.code == _lib.EUNSUPPORTED
+    # launches: the forward passes once, the row pass and inverse passes per output
+    with Plan((4096,), B=2, mult="quadratic", coef=basdevant, variant="fused", host_only=True) as p:
+        assert p.info()["launches"] == 2
+    with Plan((256, 256), B=2, mult="quadratic", coef=basdevant, host_only=True) as p, \
+            Plan((256, 256), host_only=True) as p1:
+        assert p1.info()["launches"] == 3 and p.info()["launches"] == 5
+        assert p.info()["traffic_bytes"] > p1.info()["traffic_bytes"]
+    with Plan((1 << 20,), B=2, mult="quadratic", coef=basdevant, host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["variant"] == "multipass" and d["D"] >= d["n"]
+        assert p.info()["launches"] == 1 + 2 * 2
+    with Plan((1 << 20,), B=2, mult="quadratic", coef=basdevant, m=d["m"], D=1,
+              variant="multipass", host_only=True) as p:
+        assert p.info()["dims"][0]["D"] == 1 and p.info()["dims"][0]["n"] == 2
+        assert p.info()["launches"] == 2 * 3 * 2

@@ -456,3 +456,23 @@ def test_quadratic_mult_basdevant_2d_form():
     h = oracle.conv_quadratic([u, v], coef, kind="hermitian")
     want_h = oracle.conv_hermitian_direct([u, u]) - oracle.conv_hermitian_direct([v, v])
     assert oracle.rel_l2(h[0], want_h) < 1e-15
+
+
+def test_quadratic_mult_three_inputs_random_coefficients():
+    # every pair (i, j), i <= j, of three inputs with its own weight, in 2D,
+    # against the DFT definition (numpy's FFT); weights below the diagonal
+    # must be ignored
+    rng = np.random.default_rng(203)
+    shape = (5, 6)
+    f = [rnd(shape, 204 + a) for a in range(3)]
+    coef = rng.uniform(-1, 1, size=(2, 3, 3))
+    got = oracle.conv_quadratic(f, coef)
+    N = tuple(2 * s - 1 for s in shape)
+    F = [np.fft.fftn(x, N) for x in f]
+    for b in range(2):
+        H = sum(coef[b, i, j] * F[i] * F[j] for i in range(3) for j in range(i, 3))
+        want = np.fft.ifftn(H)[: shape[0], : shape[1]]
+        assert oracle.rel_l2(got[b], want) < 1e-13
+    lower = coef + np.tril(rng.uniform(-1, 1, size=(3, 3)), -1)[None]
+    for g_, w_ in zip(oracle.conv_quadratic(f, lower), got):
+        assert np.array_equal(g_, w_)
