@@ -213,7 +213,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
         }
         if (!finish_dim(&dp, P->A, tb, &why))
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
-      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr)) {
+      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr, P->dims)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
       dp.herm = hd;
@@ -1216,7 +1216,7 @@ static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, 
   std::vector<DimPlan> base(dims);
   for (int d = 0; d < dims; ++d) {
     std::string why;
-    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, lines_of_shape(L, dims, d), &base[d], &why, ctr))
+    if (!choose_dim(L[d], M[d], A, tb, d == dims - 1, lines_of_shape(L, dims, d), &base[d], &why, ctr, dims))
       return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
   }
   auto push = [&](const std::vector<DimPlan>& s, int v) {

@@ -119,8 +119,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       if (pair) gather(r + 1, true);
     gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
     cpx<T> prod[1][E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) prod[0][e] = (HERM && pair) ? mult_at_real_pair(w, e, a.quad) : mult_at(w, e, a.quad);
+    mult_all(w, prod, a.quad, HERM && pair);
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
     if constexpr (HERM) {
       if (pair) {

@@ -181,8 +181,7 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   __syncthreads();
   gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
   cpx<T> prod[1][E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) prod[0][e] = HERM ? mult_at_real_pair(x, e, a.quad) : mult_at(x, e, a.quad);
+  mult_all(x, prod, a.quad, HERM);
   gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
   if constexpr (HERM) {
     // Y(-s) from the lane that holds it, through LDS

@@ -89,6 +89,31 @@ __device__ __forceinline__ cpx<T> mult_at_real_pair(const cpx<T> (&w)[A][E], int
   return mk(pa, pb);
 }
 
+// The operator at every point of a lane, with the operator's branch taken
+// once (uniform) rather than per point.
+template <typename T, int A, int E>
+__device__ __forceinline__ void mult_all(const cpx<T> (&w)[A][E], cpx<T> (&out)[1][E], const QuadMult<T>& q,
+                                         bool real_pair) {
+  if (!q.on) {
+    constexpr QuadMult<T> none{};
+    if (real_pair) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[0][e] = mult_at_real_pair(w, e, none);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[0][e] = mult_at(w, e, none);
+    }
+    return;
+  }
+  if (real_pair) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[0][e] = mult_at_real_pair(w, e, q);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[0][e] = mult_at(w, e, q);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, int64_t i, cpx<T> v, T scale) {
   if (mode == ACC_WRITE) {

@@ -363,7 +363,10 @@ static bool choose_dim_centered(int64_t L, int64_t M, int A, int tbytes, bool co
   };
   if (contiguous) {
     if (lines <= 1) {
-      const int64_t m = std::max<int64_t>(8, next_fft_size(M));
+      // a power of two (a lone row of 3 * 2^k points measured ~2x slower),
+      // else 3 * 2^k when only that stays within 4096 points
+      int64_t m = std::max<int64_t>(8, pow2_ceil(M));
+      if (m > 4096) m = std::max<int64_t>(8, next_fft_size(M));
       if (m <= 4096 && set_geom(dp, L, M, m, 0, VAR_FUSED, 1) && finish_dim(dp, A, tbytes, &w)) return true;
     }
     if (pick(VAR_FUSED, 4096, false)) return true;
@@ -413,7 +416,7 @@ static bool choose_dim_centered(int64_t L, int64_t M, int A, int tbytes, bool co
 }
 
 bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
-                std::string* why, int ctr) {
+                std::string* why, int ctr, int dims) {
   if (ctr) return choose_dim_centered(L, M, A, tbytes, contiguous, lines, dp, why);
   std::string w;
   if (contiguous) {
@@ -423,9 +426,8 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // residues looped (q = 2 for M = 2L), half the transform work.  Powers
     // of two only: sizes with a factor 3 measured slower at equal padding.
     const int64_t m = std::max<int64_t>(8, pow2_ceil(lines <= 1 ? M : L));
-    // a size 3 * 2^k whose padding q m is at least 20 % smaller (lengths well
-    // below a power of two; measured on 3D cubes: L = 150 1.75 -> 1.40 ms,
-    // L = 181 2.04 -> 1.65 ms)
+    // (sizes 3 * 2^k, even with 25 % less padding, measured slower here:
+    // 1D single rows 1.9-2.1x, 2D rows 1.2-1.6x, 3D rows 1.1x)
     if (m <= 4096) {
       const DimPlan base_try = [&] {
         DimPlan t;
@@ -433,16 +435,6 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
         if (!set_geom(&t, L, M, m, 0, VAR_FUSED) || !finish_dim(&t, A, tbytes, &w2)) t.m = 0;
         return t;
       }();
-      const int64_t m3 = std::max<int64_t>(24, next_fft_size(lines <= 1 ? M : L));
-      if (m3 < m && m3 % 3 == 0) {
-        DimPlan t;
-        std::string w2;
-        if (set_geom(&t, L, M, m3, 0, VAR_FUSED) && finish_dim(&t, A, tbytes, &w2) &&
-            (base_try.m == 0 || 5 * t.q * t.m <= 4 * base_try.q * base_try.m)) {
-          *dp = t;
-          return true;
-        }
-      }
       if (base_try.m) {
         *dp = base_try;
         return true;
@@ -495,12 +487,20 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
   // the autotuner's 2D/3D timings): powers of two only; up to 1024 points one
   // transform of m >= M (q = 1); beyond, the direct form with p = 1 or p = 2
   // (half the length: twice the columns per workgroup) and the least padding,
-  // ties to p = 2 once the p = 1 transform would exceed 1024 points.
+  // ties to p = 2 once the p = 1 transform would exceed 1024 points.  In 3D
+  // plans, from 256 points on, two residues of half the length (q = 2,
+  // p = 1) instead of the one transform: the recorded 3D timings put them
+  // 6-45 % ahead per dimension (the 2D timings favour q = 1 at every size).
   {
     const int64_t m1 = std::max<int64_t>(8, pow2_ceil(M));
-    // (as for rows: a 3 * 2^k transform when it pads at least 20 % less)
-    const int64_t m13 = std::max<int64_t>(24, next_fft_size(M));
-    if (m13 < m1 && m13 % 3 == 0 && 5 * m13 <= 4 * m1 && m13 <= 1536 && set_geom(dp, L, M, m13, 0, VAR_OUTER) &&
+    // 3D plans: a transform of 3 * 2^k points (192 ... 768) when it pads at
+    // least 20 % less (3D cubes L = 150: 1.60 -> 1.22 ms; smaller and larger
+    // sizes, and 2D plans, measured slower)
+    const int64_t m13 = next_fft_size(M);
+    if (dims == 3 && m13 < m1 && m13 % 3 == 0 && 5 * m13 <= 4 * m1 && m13 >= 192 && m13 <= 768 &&
+        set_geom(dp, L, M, m13, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w))
+      return true;
+    if (dims == 3 && m1 >= 256 && m1 <= 1024 && set_geom(dp, L, M, m1 / 2, 0, VAR_OUTER) && dp->p == 1 &&
         finish_dim(dp, A, tbytes, &w))
       return true;
     if (m1 <= 1024 && set_geom(dp, L, M, m1, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;

@@ -95,9 +95,10 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why);
 // innermost dimension (rows), others are outer dimensions; `lines` is the
 // number of independent lines one launch of this dimension processes (1 for
 // a single 1D convolution: latency first; many: throughput first).
-// `ctr` selects the centered convolution.
+// `ctr` selects the centered convolution; `dims` is the plan's dimension
+// count (the outer-dimension rules differ between 2D and 3D).
 bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_t lines, DimPlan* dp,
-                std::string* why, int ctr = 0);
+                std::string* why, int ctr = 0, int dims = 1);
 
 // Candidates for the autotuner: every supported (m, variant) of a dimension.
 std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int ctr = 0);

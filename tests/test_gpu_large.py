@@ -113,8 +113,9 @@ def test_1d_maximum_length(gpu):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n", [150, 229])
 def test_3d_non_power_of_two(gpu, dtype, n):
-    # default plans for lengths well below a power of two take 3 * 2^k
-    # transforms (150: outer 384-point transforms, 192-point rows)
+    # default 3D plans for lengths well below a power of two: 3 * 2^k outer
+    # transforms (150: 384 points, rows of 256), else two residues of half
+    # the power of two (229: outer 256-point transforms with q = 2)
     ins, got = run_case((n,) * 3, (2 * n,) * 3, dtype, 4)
     e = sampled_err(ins, got, 48, 7)
     say("   sampled err %.3e" % e)

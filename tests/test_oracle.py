@@ -468,7 +468,7 @@ def test_quadratic_mult_three_inputs_random_coefficients():
     coef = rng.uniform(-1, 1, size=(2, 3, 3))
     got = oracle.conv_quadratic(f, coef)
     N = tuple(2 * s - 1 for s in shape)
-    F = [np.fft.fftn(x, N) for x in f]
+    F = [np.fft.fftn(x, N, axes=(0, 1)) for x in f]
     for b in range(2):
         H = sum(coef[b, i, j] * F[i] * F[j] for i in range(3) for j in range(i, 3))
         want = np.fft.ifftn(H)[: shape[0], : shape[1]]
