@@ -20,7 +20,7 @@ namespace hd {
 // paper's centered case with p = 2, eq. forCent/wDef): block t holds the
 // signed indices c = (t - tneg) m + s at array position t m + s - sh, and the
 // twiddles are zeta_{qm}^{r c}; the output c goes back to position c + H.
-template <typename T, int E, int P, int A, bool HERM>
+template <typename T, int E, int P, int A, bool HERM, bool QUAD>
 __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
   // Inputs small enough stay in registers across the residues; larger ones
   // are read again for each residue (from cache) to keep registers free.
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
       if (pair) gather(r + 1, true);
     gfft_any<T, E, +1, A, (A == 2 ? kCtFused : 0u)>(w, g, a.fd, tw, xb);
     cpx<T> prod[1][E];
-    mult_all(w, prod, a.quad, HERM && pair);
+    mult_all<QUAD>(w, prod, a.quad, HERM && pair);
     gfft_any<T, E, -1, 1, (A == 2 ? kCtFused : 0u)>(prod, g, a.fd, tw, xb);
     if constexpr (HERM) {
       if (pair) {
@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
 }
 
 
+#if !defined(HD_PART) || HD_PART == 1  // host helpers, in one object only
 size_t lds_fused1d(int m, int ps, int rows_per_block, int A, int ntw, int tbytes) {
   return ((size_t)xwords_rows(m, ps, rows_per_block, A) + ntw) * 2 * tbytes;
 }
@@ -185,6 +186,7 @@ bool fft_fits(const FftDesc& d, int E) {
     if (E % d.radix[i] != 0) return false;
   return true;
 }
+#endif
 
 template <typename T>
 hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_t s) {
@@ -192,22 +194,33 @@ hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_
   if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N) return HD_BAD;
   dim3 grid((unsigned)((a.nrows + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
   const size_t lds = lds_fused1d(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
-#define F1(EE, PP, AA)                                                                     \
-  if (E == EE && P == PP && A == AA)                                                       \
-    return a.herm ? go(k_fused1d<T, EE, PP, AA, true>, grid, block, lds, s, a)             \
-                  : go(k_fused1d<T, EE, PP, AA, false>, grid, block, lds, s, a);
+#define F2(EE, PP, AA, QQ)                                                                 \
+  return a.herm ? go(k_fused1d<T, EE, PP, AA, true, QQ>, grid, block, lds, s, a)           \
+                : go(k_fused1d<T, EE, PP, AA, false, QQ>, grid, block, lds, s, a);
+#define F1(EE, PP, AA)                  \
+  if (E == EE && P == PP && A == AA) {  \
+    if (a.quad.on) F2(EE, PP, AA, true) \
+    F2(EE, PP, AA, false)               \
+  }
   F1(4, 1, 2) F1(4, 2, 2) F1(4, 1, 3) F1(4, 2, 3)
   F1(8, 1, 2) F1(8, 2, 2) F1(8, 1, 3) F1(8, 2, 3)
   F1(12, 1, 2) F1(12, 2, 2) F1(12, 1, 3) F1(12, 2, 3)
   F1(16, 1, 2) F1(16, 2, 2) F1(16, 1, 3) F1(16, 2, 3)
 #undef F1
+#undef F2
   return HD_BAD;
 }
 
 #define HD_INST(T) \
   template hipError_t launch_fused1d<T>(const FusedArgs<T>&, int, int, int, hipStream_t);
+// both precisions, or one per object when the build splits this file
+// (HD_PART 1: FP32, 2: FP64)
+#if !defined(HD_PART) || HD_PART == 1
 HD_INST(float)
+#endif
+#if !defined(HD_PART) || HD_PART == 2
 HD_INST(double)
+#endif
 #undef HD_INST
 
 }  // namespace hd

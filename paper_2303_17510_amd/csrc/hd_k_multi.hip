@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
 // transform per input (F_a = Re, F_b = Im), the products go back packed as
 // P_a + i P_b, and the inverse Y splits by conjugate symmetry:
 // y_a(s) = (Y(s) + conj Y(-s)) / 2, y_b(s) = (Y(s) - conj Y(-s)) / (2i).
-template <typename T, int E, int A, bool HERM>
+template <typename T, int E, int A, bool HERM, bool QUAD>
 __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   const int G = a.fd.G, m = a.m, p = a.p;
   const int slot = threadIdx.x / G;
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(512) k_rows_conv(RowConvArgs<T> a) {
   __syncthreads();
   gfft_any<T, E, +1, A, (A == 2 ? kCtRows : 0u)>(x, g, a.fd, tw, xb);
   cpx<T> prod[1][E];
-  mult_all(x, prod, a.quad, HERM);
+  mult_all<QUAD>(x, prod, a.quad, HERM);
   gfft_any<T, E, -1, 1, (A == 2 ? kCtRows : 0u)>(prod, g, a.fd, tw, xb);
   if constexpr (HERM) {
     // Y(-s) from the lane that holds it, through LDS
@@ -320,12 +320,17 @@ hipError_t launch_rows_conv(const RowConvArgs<T>& a, int E, int A, hipStream_t s
   const int64_t slots = a.herm ? (a.nrows + 1) / 2 : a.nrows;
   dim3 grid((unsigned)((slots + a.rows_per_block - 1) / a.rows_per_block)), block(nt);
   const size_t lds = lds_rows(a.m, a.fd.ps, a.rows_per_block, A, tw_words(a.fd), sizeof(T));
-#define R1(EE, AA)                                                                \
-  if (E == EE && A == AA)                                                         \
-    return a.herm ? go(k_rows_conv<T, EE, AA, true>, grid, block, lds, s, a)      \
-                  : go(k_rows_conv<T, EE, AA, false>, grid, block, lds, s, a);
+#define R2(EE, AA, QQ)                                                            \
+  return a.herm ? go(k_rows_conv<T, EE, AA, true, QQ>, grid, block, lds, s, a)    \
+                : go(k_rows_conv<T, EE, AA, false, QQ>, grid, block, lds, s, a);
+#define R1(EE, AA)                     \
+  if (E == EE && A == AA) {            \
+    if (a.quad.on) R2(EE, AA, true)    \
+    R2(EE, AA, false)                  \
+  }
   R1(4, 2) R1(4, 3) R1(8, 2) R1(8, 3) R1(12, 2) R1(12, 3) R1(16, 2) R1(16, 3)
 #undef R1
+#undef R2
   return HD_BAD;
 }
 
@@ -350,8 +355,14 @@ hipError_t launch_cols_bwd(const ColBwdArgs<T>& a, int E, hipStream_t s) {
   template hipError_t launch_cols_fwd<T>(const ColFwdArgs<T>&, int, int, hipStream_t); \
   template hipError_t launch_rows_conv<T>(const RowConvArgs<T>&, int, int, hipStream_t); \
   template hipError_t launch_cols_bwd<T>(const ColBwdArgs<T>&, int, hipStream_t);
+// both precisions, or one per object when the build splits this file
+// (HD_PART 1: FP32, 2: FP64)
+#if !defined(HD_PART) || HD_PART == 1
 HD_INST(float)
+#endif
+#if !defined(HD_PART) || HD_PART == 2
 HD_INST(double)
+#endif
 #undef HD_INST
 
 }  // namespace hd

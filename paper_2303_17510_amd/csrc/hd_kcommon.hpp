@@ -89,12 +89,12 @@ __device__ __forceinline__ cpx<T> mult_at_real_pair(const cpx<T> (&w)[A][E], int
   return mk(pa, pb);
 }
 
-// The operator at every point of a lane, with the operator's branch taken
-// once (uniform) rather than per point.
-template <typename T, int A, int E>
+// The operator at every point of a lane.  QUAD is a template parameter so
+// that product kernels carry no code of the quadratic form.
+template <bool QUAD, typename T, int A, int E>
 __device__ __forceinline__ void mult_all(const cpx<T> (&w)[A][E], cpx<T> (&out)[1][E], const QuadMult<T>& q,
                                          bool real_pair) {
-  if (!q.on) {
+  if constexpr (!QUAD) {
     constexpr QuadMult<T> none{};
     if (real_pair) {
 #pragma unroll
@@ -103,14 +103,14 @@ __device__ __forceinline__ void mult_all(const cpx<T> (&w)[A][E], cpx<T> (&out)[
 #pragma unroll
       for (int e = 0; e < E; ++e) out[0][e] = mult_at(w, e, none);
     }
-    return;
-  }
-  if (real_pair) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) out[0][e] = mult_at_real_pair(w, e, q);
   } else {
+    if (real_pair) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[0][e] = mult_at(w, e, q);
+      for (int e = 0; e < E; ++e) out[0][e] = mult_at_real_pair(w, e, q);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[0][e] = mult_at(w, e, q);
+    }
   }
 }
 
