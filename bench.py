@@ -80,7 +80,24 @@ def workload(name: str):
                             "M=512^3, complex64, unit disk, hybrid",
                 "L": [256] * 3, "M": [512] * 3, "A": 3, "dtype": "c64", "config_id": 4, "B": 5,
                 "coef": BASDEVANT_3D}
+    if name == "mhd3d":
+        return {"workload": "3D quadratic conv (MHD, Elsasser form: z+_0 z-_0 - z+_2 z-_2, z+_1 z-_1 - z+_2 z-_2, "
+                            "z+_i z-_j for i != j), A=6, B=8, 256^3, M=512^3, complex64, unit disk, hybrid",
+                "L": [256] * 3, "M": [512] * 3, "A": 6, "dtype": "c64", "config_id": 4, "B": 8,
+                "coef": mhd_coefficients()}
     raise SystemExit("unknown workload " + name)
+
+
+def mhd_coefficients():
+    """Elsasser form of the 3D MHD nonlinearity: inputs z+ (0, 1, 2), z- (3, 4, 5)."""
+    def out(terms):
+        c = [[0.0] * 6 for _ in range(6)]
+        for (i, j), w in terms.items():
+            c[min(i, j)][max(i, j)] += w
+        return c
+    coef = [out({(0, 3): 1, (2, 5): -1}), out({(1, 4): 1, (2, 5): -1})]
+    coef += [out({(i, 3 + j): 1}) for i in range(3) for j in range(3) if i != j]
+    return coef
 
 
 # Basdevant forms of the Navier-Stokes nonlinearity (coefficients c[b][i][j], i <= j)
@@ -468,12 +485,14 @@ def main():
             put("hermitian_2047x2048_hybrid_c64", lambda: leg(wh4, "c64", "hybrid", 20, 3))
             put("hermitian_2047x2048_hybrid_c64_tuned", lambda: leg(wh4, "c64", "hybrid", 20, 3, tuner="exhaustive"))
             put("hermitian_2047x2048_explicit_c64", lambda: leg(wh4, "c64", "explicit", 10, 2))
-            # quadratic operators (Basdevant forms): one plan for all outputs against the
-            # pairwise products it replaces (u^2, v^2, uv in 2D; six pairs in 3D)
+            # quadratic operators (Basdevant and MHD forms): one plan for all outputs against
+            # the pairwise products it replaces (u^2, v^2, uv in 2D; six pairs in 3D; nine
+            # pairs z+_i z-_j for MHD)
             for nm, wq, base, pairs in (("basdevant_2047x2048_hermitian_c64", workload("basdevant2d_hermitian"),
                                          "hermitian_2047x2048_hybrid_c64", 3),
                                         ("basdevant_256cube_c64", workload("basdevant3d"),
-                                         "C5_256cube_hybrid_c64", 6)):
+                                         "C5_256cube_hybrid_c64", 6),
+                                        ("mhd_256cube_c64", workload("mhd3d"), "C5_256cube_hybrid_c64", 9)):
                 r = put(nm, lambda: leg(wq, "c64", "hybrid", 10, 2))
                 if r and "ms" in compare.get(base, {}):
                     compare[nm]["pairwise_products_ms"] = pairs * compare[base]["ms"]

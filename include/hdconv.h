@@ -52,15 +52,17 @@ enum {
 enum { HDCONV_METHOD_AUTO = 0, HDCONV_METHOD_HYBRID = 1, HDCONV_METHOD_EXPLICIT = 2 };
 
 /* multiplication operator (Sec. 2: mult maps the A transforms to B outputs
- * pointwise).  PRODUCT: B = 1, the product of the A transforms.  QUADRATIC:
- * B outputs (1 <= B <= 6), output b = sum_{i <= j} c[b][i][j] F_i F_j with
- * the real B x A x A coefficients in options.mult_coef (entries below the
- * diagonal unused) -- e.g. the Basdevant forms of the Navier-Stokes
- * nonlinearity, A = B = 2 in 2D and A = 3, B = 5 in 3D.  Quadratic operators
- * multiply two transforms, so their padding rule is that of A = 2; the
- * outputs are computed one after another from transforms of the inputs made
- * once (the row pass repeats its A row transforms per output), and must not
- * overlap the inputs or each other. */
+ * pointwise).  PRODUCT: B = 1, the product of the A transforms (A = 2 or 3).
+ * QUADRATIC: 2 <= A <= 6 inputs and 1 <= B <= 8 outputs, output
+ * b = sum_{i <= j} c[b][i][j] F_i F_j with the real B x A x A coefficients in
+ * options.mult_coef (entries below the diagonal unused) -- e.g. the Basdevant
+ * forms of the Navier-Stokes nonlinearity, A = B = 2 in 2D and A = 3, B = 5
+ * in 3D, or the 3D magnetohydrodynamic terms with A = 6, B = 8 (Sec. 9).
+ * Quadratic operators multiply two transforms, so their padding rule is that
+ * of A = 2; the outputs are computed one after another from transforms of
+ * the inputs made once (the row pass transforms the rows of the inputs an
+ * output needs, at most three per launch: with more, an output is the sum of
+ * several launches), and must not overlap the inputs or each other. */
 enum { HDCONV_MULT_PRODUCT = 0, HDCONV_MULT_QUADRATIC = 1 };
 
 /* per-dimension kernel variant */
@@ -199,8 +201,8 @@ int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, 
 void hdconv_options_init(hdconv_options* opt);
 
 /* Create a plan on the current HIP device.  L[d], M[d] for d < dims
- * (dims in {1,2,3}); A in {2,3}; B = 1 (or 1 .. 6 with a quadratic
- * operator); dtype HDCONV_C64 or HDCONV_C128.
+ * (dims in {1,2,3}); A in {2,3} and B = 1 (a quadratic operator: A in
+ * 2 .. 6, B in 1 .. 8); dtype HDCONV_C64 or HDCONV_C128.
  * Requires L[d] >= 1 and M[d] >= A (L[d]-1) + 1 (the padding that keeps the
  * product of A inputs unaliased, Sec. 2; centered plans: the centered minimum
  * above).  Allocates twiddle tables (FP64

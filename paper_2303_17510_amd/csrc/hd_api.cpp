@@ -54,6 +54,15 @@ struct DimDev {
 
 }  // namespace
 
+// One row-pass launch's share of an output: up to three of the plan's
+// inputs and the weights of their pairs (pair_slot order); the output is the
+// sum of its shares.
+struct Share {
+  int n = 0;                 // inputs of the launch (2 or 3)
+  int idx[kMaxA] = {0, 0, 0};  // the plan's input of each
+  double c[6] = {};
+};
+
 struct Plan {
   int dims = 0, A = 0, B = 0, dtype = 0, method = 0, flags = 0;
   int64_t L[3] = {1, 1, 1}, M[3] = {1, 1, 1};
@@ -68,15 +77,17 @@ struct Plan {
   DimDev dd[3];
   char* work_mem = nullptr;
   size_t work_bytes = 0;
-  void* pad_in[kMaxA] = {nullptr, nullptr, nullptr};  // explicit method
-  void* lvl[2][kMaxA] = {{nullptr}};                  // outer-level buffers W_d
-  void* rowwork[kMaxA] = {nullptr, nullptr, nullptr};  // inner-form work rows
+  void* pad_in[kMaxIn] = {};                          // explicit method
+  void* lvl[2][kMaxIn] = {{nullptr}};                 // outer-level buffers W_d
+  void* rowwork[kMaxIn] = {};                         // inner-form work rows
   double* acc64 = nullptr;                            // multi-block accumulator
   int64_t batch_rows = 1;                             // rows of a batched group
   int64_t copies = 1, dist = 0;                       // copies per execute, words between them
   int64_t stride[2] = {0, 0};                         // element strides of dims 0, 1 (0: dense)
   int quad = 0;                                       // quadratic multiplication operator, B outputs
-  double coef[kMaxB][6] = {};                         // its coefficients per output (pair slots)
+  // the launches of the row pass per output: shares of at most three inputs
+  // (one share with every input for products and A <= 3)
+  std::vector<Share> shares[kMaxB];
   void* rowout = nullptr;                             // quadratic: result rows of the row pass
   void* outbuf = nullptr;                             // quadratic 2D/3D: the innermost level's result
   void* padout = nullptr;                             // quadratic explicit method: padded result
@@ -146,6 +157,10 @@ static int64_t lines_of(const Plan* P, int d) {
   return P->batch_rows > 1 ? P->batch_rows : P->copies * lines_of_shape(P->L, P->dims, d);
 }
 
+// Inputs one kernel launch combines (quadratic operators with more inputs
+// run shares of at most three).
+static int kernel_inputs(const Plan* P) { return std::min(P->A, kMaxA); }
+
 static int build_dims(Plan* P, const hdconv_options* opt) {
   const int tb = tbytes_of(P->dtype);
   // centered hybrid plans run centered transforms; the explicit method pads
@@ -191,7 +206,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
                      t.p = t.q = t.n = t.D = 1;
                      t.variant = VAR_FUSED;
                      std::string w;
-                     return finish_dim(&t, P->A, tb, &w);
+                     return finish_dim(&t, kernel_inputs(P), tb, &w);
                    }())) {
           dp.m = Le;
           dp.p = dp.q = dp.n = dp.D = 1;
@@ -211,9 +226,9 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
           dp.q = dp.p;
           dp.variant = VAR_MULTI;
         }
-        if (!finish_dim(&dp, P->A, tb, &why))
+        if (!finish_dim(&dp, kernel_inputs(P), tb, &why))
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
-      } else if (!choose_dim(Le, Me, P->A, tb, contiguous, lines_of(P, d), &dp, &why, ctr, P->dims)) {
+      } else if (!choose_dim(Le, Me, kernel_inputs(P), tb, contiguous, lines_of(P, d), &dp, &why, ctr, P->dims)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
       dp.herm = hd;
@@ -250,7 +265,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
         dp.rows_per_block = opt->rows_per_block[d];
         dp.tw_pref = opt->twiddles[d];
       }
-      if (!finish_dim(&dp, P->A, tb, &why))
+      if (!finish_dim(&dp, kernel_inputs(P), tb, &why))
         return set_err(HDCONV_EUNSUPPORTED, "dim %d (m=%lld, p=%lld, q=%lld): %s", d, (long long)dp.m,
                        (long long)dp.p, (long long)dp.q, why.c_str());
     }
@@ -259,11 +274,74 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
 }
 
 template <typename T>
-static QuadMult<T> quad_of(const Plan* P, int b) {
+static QuadMult<T> quad_of(const Plan* P, const Share& sh) {
   QuadMult<T> q{};
   q.on = P->quad;
-  for (int k = 0; k < 6; ++k) q.c[k] = P->quad ? (T)P->coef[b][k] : T(0);
+  for (int k = 0; k < 6; ++k) q.c[k] = P->quad ? (T)sh.c[k] : T(0);
   return q;
+}
+
+// Splits output b of a quadratic operator (coefficients c[i][j], i <= j,
+// row-major A x A) into shares of at most three inputs: each term F_i F_j
+// joins the first share that stays within three inputs with i and j.  A
+// lone input is paired with another one at zero weight (the kernels combine
+// two or three transforms).
+static std::vector<Share> make_shares(int A, const double* c) {
+  std::vector<Share> out;
+  if (A <= kMaxA) {
+    Share sh;
+    sh.n = A;
+    for (int i = 0; i < A; ++i) sh.idx[i] = i;
+    for (int i = 0; i < A; ++i)
+      for (int j = i; j < A; ++j) sh.c[pair_slot(i, j)] = c[i * A + j];
+    out.push_back(sh);
+    return out;
+  }
+  auto local = [](Share& sh, int x) {
+    for (int k = 0; k < sh.n; ++k)
+      if (sh.idx[k] == x) return k;
+    sh.idx[sh.n] = x;
+    return sh.n++;
+  };
+  auto has = [](const Share& sh, int x) {
+    for (int k = 0; k < sh.n; ++k)
+      if (sh.idx[k] == x) return true;
+    return false;
+  };
+  for (int i = 0; i < A; ++i)
+    for (int j = i; j < A; ++j) {
+      const double w = c[i * A + j];
+      if (w == 0.0) continue;
+      Share* tgt = nullptr;
+      for (Share& sh : out) {
+        const int need = (has(sh, i) ? 0 : 1) + (i != j && !has(sh, j) ? 1 : 0);
+        if (sh.n + need <= kMaxA) {
+          tgt = &sh;
+          break;
+        }
+      }
+      if (!tgt) {
+        out.emplace_back();
+        tgt = &out.back();
+      }
+      int li = local(*tgt, i), lj = local(*tgt, j);
+      if (li > lj) std::swap(li, lj);
+      tgt->c[pair_slot(li, lj)] += w;
+    }
+  if (out.empty()) {  // the zero operator
+    out.emplace_back();
+    out.back().n = 1;
+  }
+  for (Share& sh : out)
+    if (sh.n == 1) sh.idx[sh.n++] = sh.idx[0] == 0 ? 1 : 0;
+  return out;
+}
+
+// Largest number of shares of any output.
+static int max_shares(const Plan* P) {
+  size_t n = 1;
+  for (int b = 0; b < P->B; ++b) n = std::max(n, P->shares[b].size());
+  return (int)n;
 }
 
 // Extent of dimension d as stored between passes: the engine length, or the
@@ -275,6 +353,15 @@ static double plan_traffic(const Plan* P, int* launches) {
   const double w = 2.0 * tbytes_of(P->dtype);
   const int A = P->A;
   const int nout = P->quad ? P->B : 1;  // outputs, each through the row pass and the inverse passes
+  const int groups = (int)cdiv(A, kMaxA);  // forward launches per pass (three inputs each)
+  // row-pass launches per output and the inputs they read
+  int shares = 0;
+  double share_in = 0;
+  for (int b = 0; b < nout; ++b)
+    for (const Share& sh : P->shares[b]) {
+      shares += 1;
+      share_in += sh.n;
+    }
   double bytes = 0;
   int nl = 0;
   int64_t Le[3];
@@ -296,25 +383,30 @@ static double plan_traffic(const Plan* P, int* launches) {
     for (int e = d + 1; e < P->dims; ++e) rest *= (double)stored_extent(P->dp[e]);
     const double in_el = nb * Le[d] * rest, out_el = nb * dp.q * dp.m * rest;
     bytes += A * (in_el + out_el) * w + nout * (out_el + in_el) * w;  // forward + backward
-    nl += 1 + nout;
+    nl += groups + nout;
     nb *= (double)(dp.q * dp.m);
   }
   const DimPlan& dl = P->dp[P->dims - 1];
   // words each row reads per input and writes (Hermitian rows: the stored half)
   const double rows = nb, Lr = (double)(dl.herm ? P->Lio[P->dims - 1] : Le[P->dims - 1]);
   if (dl.variant == VAR_FUSED) {
-    bytes += nout * rows * (A + 1) * Lr * w;
-    nl += nout;
+    // every share reads its inputs and writes; later shares also read the output
+    bytes += rows * (share_in + shares + (shares - nout)) * Lr * w;
+    nl += shares;
   } else {
     const int64_t blocks = cdiv(dl.n, dl.D);
     const double wk = rows * (double)dl.q * dl.m;  // all residues' rows
     // K1 (read inputs per block, write work) once, or per output with blocks
     const int k1_runs = blocks > 1 ? nout : 1;
     bytes += k1_runs * (blocks * rows * A * Lr * w + A * wk * w);
-    bytes += nout * (A + 1) * wk * w;             // K2
-    bytes += nout * (wk * w + rows * Lr * w);     // K3
-    if (blocks > 1) bytes += nout * (2.0 * blocks - 2) * rows * Lr * 16.0;  // FP64 accumulator round trips
-    nl += k1_runs * (int)blocks + nout * 2 * (int)blocks;
+    bytes += (share_in + shares) * wk * w;      // K2
+    bytes += shares * wk * w + nout * rows * Lr * w;  // K3
+    // FP64 accumulator round trips over the blocks and shares of each output
+    for (int b = 0; b < nout; ++b) {
+      const double contrib = (double)blocks * (double)P->shares[b].size();
+      if (contrib > 1) bytes += (2.0 * contrib - 2) * rows * Lr * 16.0;
+    }
+    nl += k1_runs * (int)blocks * groups + 2 * (int)blocks * shares;
   }
   if (launches) *launches = P->method == HDCONV_METHOD_EXPLICIT ? nl * (int)P->copies : nl;
   return bytes * (double)P->copies;
@@ -430,7 +522,8 @@ static int alloc_workspace(Plan* P) {
       acc_rows = (size_t)P->copies;
       acc_len = (size_t)P->dist;
     }
-    if (dl.D < dl.n) want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
+    // (also for outputs summed over several row-pass shares)
+    if (dl.D < dl.n || max_shares(P) > 1) want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
   }
   size_t total = 0;
   for (auto& x : want) total += align256(x.second);
@@ -472,134 +565,148 @@ static RootTable<T> rtab(const Plan* P, int d) {
 
 // rows of the innermost dimension: nrows rows of length dp.L, row stride dp.L,
 // or (tasks != NULL) nrows independent rows described by a device task table
-// `b` selects the output of a quadratic multiplication operator; `skip_fwd`
-// reuses the column pass of the previous output (one residue block only).
+// `b` selects the output of a quadratic multiplication operator, whose
+// shares run one after another into the same output; `skip_fwd` reuses the
+// column pass of the previous output (one residue block only).
 template <typename T>
 static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows, hipStream_t s,
                     const RowTask<T>* tasks = nullptr, int64_t row_stride = 0, int b = 0, bool skip_fwd = false) {
   const int d = P->dims - 1;
   const DimPlan& dp = P->dp[d];
   const int A = P->A;
+  const std::vector<Share>& shares = P->shares[b];
+  const int nsh = (int)shares.size();
   // words between consecutive rows of the inputs and the output (default: dense)
   const int64_t rs = row_stride ? row_stride : stored_extent(dp);
   hipError_t e;
   if (dp.variant == VAR_FUSED) {
-    FusedArgs<T> a{};
-    a.tasks = tasks;
-    for (int i = 0; i < A; ++i) a.in[i] = in ? in[i] : nullptr;
-    a.out = out;
-    a.in_stride = a.out_stride = rs;
-    a.nrows = nrows;
-    a.L = dp.L;
-    a.m = (int)dp.m;
-    a.q = (int)dp.q;
-    a.rows_per_block = dp.rows_per_block;
-    a.ctr = dp.ctr;
-    a.herm = dp.herm;
-    // paired real residue transforms (measured: 2047 x 2048 FP32 inner rows
-    // 160 -> 134 us, L = 4096 42 -> 34 us)
-    a.pair = dp.herm;
-    a.quad = quad_of<T>(P, b);
-    a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
-    a.fd = dp.fd_m;
-    a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
-    a.zqm = rtab<T>(P, d);
-    const double wb = 2.0 * sizeof(T);
-    ProfScope ps(P, s, "fused1d", (double)nrows * (A + 1) * (double)stored_extent(dp) * wb);
-    e = launch_fused1d<T>(a, dp.E_m, (int)dp.p, A, s);
-    if (e != hipSuccess) return hip_err(e, "fused1d launch");
+    for (int k = 0; k < nsh; ++k) {
+      const Share& sh = shares[k];
+      FusedArgs<T> a{};
+      a.tasks = tasks;
+      for (int i = 0; i < sh.n; ++i) a.in[i] = in ? in[sh.idx[i]] : nullptr;
+      a.out = out;
+      a.in_stride = a.out_stride = rs;
+      a.nrows = nrows;
+      a.L = dp.L;
+      a.m = (int)dp.m;
+      a.q = (int)dp.q;
+      a.rows_per_block = dp.rows_per_block;
+      a.ctr = dp.ctr;
+      a.herm = dp.herm;
+      // paired real residue transforms (measured: 2047 x 2048 FP32 inner rows
+      // 160 -> 134 us, L = 4096 42 -> 34 us)
+      a.pair = dp.herm;
+      a.quad = quad_of<T>(P, sh);
+      a.out_add = k > 0;
+      a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+      a.fd = dp.fd_m;
+      a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+      a.zqm = rtab<T>(P, d);
+      const double wb = 2.0 * sizeof(T);
+      ProfScope ps(P, s, "fused1d", (double)nrows * (sh.n + 1 + (k > 0)) * (double)stored_extent(dp) * wb);
+      e = launch_fused1d<T>(a, dp.E_m, (int)dp.p, sh.n, s);
+      if (e != hipSuccess) return hip_err(e, "fused1d launch");
+    }
     return HDCONV_OK;
   }
-  // inner form, blocks of D residues
+  // inner form, blocks of D residues; every block adds each share of the
+  // output to the FP64 accumulator unless one contribution is all there is
   const int64_t nblk = cdiv(dp.n, dp.D);
+  const int64_t ncontrib = nblk * nsh;
   for (int64_t blk = 0; blk < nblk; ++blk) {
     const int v0 = (int)(blk * dp.D);
     const int D = (int)std::min<int64_t>(dp.D, dp.n - v0);
-    ColFwdArgs<T> k1{};
-    k1.tasks = tasks;
-    for (int i = 0; i < A; ++i) {
-      k1.in[i] = in ? in[i] : nullptr;
-      k1.work[i] = (cpx<T>*)P->rowwork[i];
-    }
-    k1.in_stride = rs;
-    k1.nrows = nrows;
-    k1.L = dp.L;
-    k1.m = (int)dp.m;
-    k1.p = (int)dp.p;
-    k1.q = (int)dp.q;
-    k1.v0 = v0;
-    k1.D = D;
-    k1.S = dp.S;
-    k1.ctr = dp.ctr;
-    k1.fold = centered_folds(dp) ? 1 : 0;
-    k1.herm = dp.herm;
-    k1.fd = dp.fd_p;
-    k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
-    k1.zq = (const cpx<T>*)P->dd[d].zq;
     const double wb = 2.0 * sizeof(T);
-    if (!skip_fwd) {
-      ProfScope ps(P, s, "cols_fwd", (double)nrows * A * ((double)stored_extent(dp) + (double)D * dp.p * dp.m) * wb);
-      e = launch_cols_fwd<T>(k1, dp.E_p, A, s);
+    // forward column pass, three inputs per launch
+    for (int g0 = 0; g0 < A && !skip_fwd; g0 += kMaxA) {
+      const int na = std::min(kMaxA, A - g0);
+      ColFwdArgs<T> k1{};
+      k1.tasks = tasks;
+      for (int i = 0; i < na; ++i) {
+        k1.in[i] = in ? in[g0 + i] : nullptr;
+        k1.work[i] = (cpx<T>*)P->rowwork[g0 + i];
+      }
+      k1.in_stride = rs;
+      k1.nrows = nrows;
+      k1.L = dp.L;
+      k1.m = (int)dp.m;
+      k1.p = (int)dp.p;
+      k1.q = (int)dp.q;
+      k1.v0 = v0;
+      k1.D = D;
+      k1.S = dp.S;
+      k1.ctr = dp.ctr;
+      k1.fold = centered_folds(dp) ? 1 : 0;
+      k1.herm = dp.herm;
+      k1.fd = dp.fd_p;
+      k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+      k1.zq = (const cpx<T>*)P->dd[d].zq;
+      ProfScope ps(P, s, "cols_fwd", (double)nrows * na * ((double)stored_extent(dp) + (double)D * dp.p * dp.m) * wb);
+      e = launch_cols_fwd<T>(k1, dp.E_p, na, s);
       if (e != hipSuccess) return hip_err(e, "cols_fwd launch");
     }
+    for (int k = 0; k < nsh; ++k) {
+      const Share& sh = shares[k];
+      RowConvArgs<T> k2{};
+      for (int i = 0; i < sh.n; ++i) k2.work[i] = (cpx<T>*)P->rowwork[sh.idx[i]];
+      // quadratic operators keep the transformed inputs for the other outputs
+      k2.out = P->quad ? (cpx<T>*)P->rowout : nullptr;
+      k2.quad = quad_of<T>(P, sh);
+      k2.nrows = nrows * D * dp.p;
+      k2.m = (int)dp.m;
+      k2.p = (int)dp.p;
+      k2.n = (int)dp.n;
+      k2.v0 = v0;
+      k2.D = D;
+      k2.rows_per_block = dp.rows_per_block;
+      // two real-output rows per transform: FP64 (transform-bound), or FP32
+      // when the rows are plenty (pairing halves the slots; with few rows that
+      // leaves CUs idle, measured slower at 384 rows)
+      k2.herm = dp.herm && (sizeof(T) == 8 || k2.nrows >= 2048);
+      k2.qm = dp.q * dp.m;
+      k2.fd = dp.fd_m;
+      k2.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+      k2.zqm = rtab<T>(P, d);
+      {
+        ProfScope ps(P, s, "rows_conv", (double)nrows * D * dp.p * dp.m * (sh.n + 1) * wb);
+        e = launch_rows_conv<T>(k2, dp.E_m, sh.n, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "rows_conv launch");
 
-    RowConvArgs<T> k2{};
-    for (int i = 0; i < A; ++i) k2.work[i] = (cpx<T>*)P->rowwork[i];
-    // quadratic operators keep the transformed inputs for the other outputs
-    k2.out = P->quad ? (cpx<T>*)P->rowout : nullptr;
-    k2.quad = quad_of<T>(P, b);
-    k2.nrows = nrows * D * dp.p;
-    k2.m = (int)dp.m;
-    k2.p = (int)dp.p;
-    k2.n = (int)dp.n;
-    k2.v0 = v0;
-    k2.D = D;
-    k2.rows_per_block = dp.rows_per_block;
-    // two real-output rows per transform: FP64 (transform-bound), or FP32
-    // when the rows are plenty (pairing halves the slots; with few rows that
-    // leaves CUs idle, measured slower at 384 rows)
-    k2.herm = dp.herm && (sizeof(T) == 8 || k2.nrows >= 2048);
-    k2.qm = dp.q * dp.m;
-    k2.fd = dp.fd_m;
-    k2.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
-    k2.zqm = rtab<T>(P, d);
-    {
-      ProfScope ps(P, s, "rows_conv", (double)nrows * D * dp.p * dp.m * (A + 1) * wb);
-      e = launch_rows_conv<T>(k2, dp.E_m, A, s);
+      const int64_t ci = blk * nsh + k;  // this contribution's place in the sum
+      ColBwdArgs<T> k3{};
+      k3.tasks = tasks;
+      k3.work = (const cpx<T>*)(P->quad ? P->rowout : P->rowwork[0]);
+      k3.out = out;
+      k3.acc = P->acc64;
+      k3.acc_mode = ncontrib == 1 ? ACC_WRITE : (ci == 0 ? ACC_FIRST : (ci == ncontrib - 1 ? ACC_LAST : ACC_ADD));
+      k3.out_stride = rs;
+      k3.nrows = nrows;
+      k3.L = dp.L;
+      k3.m = (int)dp.m;
+      k3.p = (int)dp.p;
+      k3.q = (int)dp.q;
+      k3.v0 = v0;
+      k3.D = D;
+      k3.S = dp.S;
+      k3.ctr = dp.ctr;
+      k3.fold = centered_folds(dp) ? 1 : 0;
+      k3.herm = dp.herm;
+      k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+      k3.fd = dp.fd_pb;
+      k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+      k3.zq = (const cpx<T>*)P->dd[d].zq;
+      {
+        const double Lw = (double)stored_extent(dp);
+        const double accb = k3.acc_mode == ACC_WRITE ? Lw * wb
+                            : (k3.acc_mode == ACC_FIRST ? 16.0 * Lw
+                                                        : (k3.acc_mode == ACC_ADD ? 32.0 * Lw : 16.0 * Lw + Lw * wb));
+        ProfScope ps(P, s, "cols_bwd", (double)nrows * ((double)D * dp.p * dp.m * wb + accb));
+        e = launch_cols_bwd<T>(k3, dp.E_pb, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "cols_bwd launch");
     }
-    if (e != hipSuccess) return hip_err(e, "rows_conv launch");
-
-    ColBwdArgs<T> k3{};
-    k3.tasks = tasks;
-    k3.work = (const cpx<T>*)(P->quad ? P->rowout : P->rowwork[0]);
-    k3.out = out;
-    k3.acc = P->acc64;
-    k3.acc_mode = nblk == 1 ? ACC_WRITE : (blk == 0 ? ACC_FIRST : (blk == nblk - 1 ? ACC_LAST : ACC_ADD));
-    k3.out_stride = rs;
-    k3.nrows = nrows;
-    k3.L = dp.L;
-    k3.m = (int)dp.m;
-    k3.p = (int)dp.p;
-    k3.q = (int)dp.q;
-    k3.v0 = v0;
-    k3.D = D;
-    k3.S = dp.S;
-    k3.ctr = dp.ctr;
-    k3.fold = centered_folds(dp) ? 1 : 0;
-    k3.herm = dp.herm;
-    k3.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
-    k3.fd = dp.fd_pb;
-    k3.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
-    k3.zq = (const cpx<T>*)P->dd[d].zq;
-    {
-      const double Lw = (double)stored_extent(dp);
-      const double accb = k3.acc_mode == ACC_WRITE ? Lw * wb
-                          : (k3.acc_mode == ACC_FIRST ? 16.0 * Lw
-                                                      : (k3.acc_mode == ACC_ADD ? 32.0 * Lw : 16.0 * Lw + Lw * wb));
-      ProfScope ps(P, s, "cols_bwd", (double)nrows * ((double)D * dp.p * dp.m * wb + accb));
-      e = launch_cols_bwd<T>(k3, dp.E_pb, s);
-    }
-    if (e != hipSuccess) return hip_err(e, "cols_bwd launch");
   }
   return HDCONV_OK;
 }
@@ -631,7 +738,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       user.cgstride = s1;
     }
   }
-  const cpx<T>* cur[kMaxA];
+  const cpx<T>* cur[kMaxIn];
   // where the engine leaves output b: the user's array, or for the explicit
   // method its padded buffer (in place over the first input for products)
   auto engine_out = [&](int b) -> cpx<T>* {
@@ -678,30 +785,33 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
     const DimPlan& dp = P->dp[d];
     int64_t rest = 1;
     for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
-    OuterFwdArgs<T> o{};
-    for (int a = 0; a < A; ++a) {
-      o.in[a] = cur[a];
-      o.out[a] = (cpx<T>*)P->lvl[d][a];
+    for (int g0 = 0; g0 < A; g0 += kMaxA) {  // three inputs per launch
+      const int na = std::min(kMaxA, A - g0);
+      OuterFwdArgs<T> o{};
+      for (int a = 0; a < na; ++a) {
+        o.in[a] = cur[g0 + a];
+        o.out[a] = (cpx<T>*)P->lvl[d][g0 + a];
+      }
+      o.nb = nb;
+      o.in_bstride = d == 0 ? dist : Le[d] * rest;  // the user's copies are dist apart
+      if (d == 0) o.lay = user;
+      o.R = rest;
+      o.L = Le[d];
+      o.m = (int)dp.m;
+      o.q = (int)dp.q;
+      o.r0 = 0;
+      o.D = (int)dp.q;
+      o.S = dp.S;
+      o.ctr = dp.ctr;
+      o.fd = dp.fd_m;
+      o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+      o.zqm = rtab<T>(P, d);
+      {
+        ProfScope ps(P, s, "outer_fwd", (double)nb * na * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+        e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, na, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "outer_fwd launch");
     }
-    o.nb = nb;
-    o.in_bstride = d == 0 ? dist : Le[d] * rest;  // the user's copies are dist apart
-    if (d == 0) o.lay = user;
-    o.R = rest;
-    o.L = Le[d];
-    o.m = (int)dp.m;
-    o.q = (int)dp.q;
-    o.r0 = 0;
-    o.D = (int)dp.q;
-    o.S = dp.S;
-    o.ctr = dp.ctr;
-    o.fd = dp.fd_m;
-    o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
-    o.zqm = rtab<T>(P, d);
-    {
-      ProfScope ps(P, s, "outer_fwd", (double)nb * A * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
-      e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, A, s);
-    }
-    if (e != hipSuccess) return hip_err(e, "outer_fwd launch");
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
     nb *= dp.q * dp.m;
   }
@@ -792,7 +902,7 @@ static int run_plan(Plan* P, const void* const* inputs, void* const* outputs, hi
   if (P->method != HDCONV_METHOD_EXPLICIT || P->copies == 1) return run_copies<T>(P, inputs, outputs, s, P->copies);
   // the explicit baseline pads one copy at a time into its work buffers
   for (int64_t c = 0; c < P->copies; ++c) {
-    const void* in_c[kMaxA];
+    const void* in_c[kMaxIn];
     void* out_c[kMaxB];
     for (int a = 0; a < P->A; ++a) in_c[a] = (const cpx<T>*)inputs[a] + c * P->dist;
     for (int b = 0; b < P->B; ++b) out_c[b] = (cpx<T>*)outputs[b] + c * P->dist;
@@ -849,11 +959,13 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     set_err(HDCONV_EINVAL, "dims must be 1, 2 or 3 (got %d)", dims);
     return nullptr;
   }
-  if (A < 2 || A > 3) {
-    set_err(HDCONV_EUNSUPPORTED, "A must be 2 or 3 (got %d)", A);
+  const bool quad = opt && opt->mult == HDCONV_MULT_QUADRATIC;
+  // products multiply two or three transforms; quadratic operators take up to
+  // six inputs (their outputs sum pairs)
+  if (A < 2 || A > (quad ? kMaxIn : kMaxA)) {
+    set_err(HDCONV_EUNSUPPORTED, "A must be 2 or 3 (quadratic operators: 2 ... %d; got %d)", kMaxIn, A);
     return nullptr;
   }
-  const bool quad = opt && opt->mult == HDCONV_MULT_QUADRATIC;
   if (opt && opt->mult != HDCONV_MULT_PRODUCT && !quad) {
     set_err(HDCONV_EINVAL, "unknown multiplication operator %d", opt->mult);
     return nullptr;
@@ -935,12 +1047,13 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
   P->method = (opt && opt->method == HDCONV_METHOD_EXPLICIT) ? HDCONV_METHOD_EXPLICIT : HDCONV_METHOD_HYBRID;
   P->flags = opt ? opt->flags : 0;
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
-  if (quad) {
-    // coef is B x A x A (row-major); the pair (i, j), i <= j, weighs F_i F_j
-    P->quad = 1;
-    for (int b = 0; b < B; ++b)
-      for (int i = 0; i < A; ++i)
-        for (int j = i; j < A; ++j) P->coef[b][pair_slot(i, j)] = opt->mult_coef[(b * A + i) * A + j];
+  // coef is B x A x A (row-major); the pair (i, j), i <= j, weighs F_i F_j
+  P->quad = quad ? 1 : 0;
+  for (int b = 0; b < B; ++b) {
+    double c[kMaxIn * kMaxIn] = {};
+    for (int i = 0; quad && i < A; ++i)
+      for (int j = i; j < A; ++j) c[i * A + j] = opt->mult_coef[(b * A + i) * A + j];
+    P->shares[b] = make_shares(A, c);
   }
   {
     int64_t ext[3];
@@ -1525,6 +1638,10 @@ static Plan* make_group_plan(int A, int B, int dtype, const DimPlan& dp, int64_t
   P->B = B;
   P->dtype = dtype;
   P->method = HDCONV_METHOD_HYBRID;
+  {
+    const double none[kMaxA * kMaxA] = {};
+    P->shares[0] = make_shares(A, none);  // the product of the A inputs
+  }
   P->L[0] = dp.L;
   P->Lio[0] = dp.herm ? herm_stored(dp.L) : dp.L;
   P->M[0] = dp.M;

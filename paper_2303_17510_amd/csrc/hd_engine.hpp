@@ -34,12 +34,14 @@
 
 namespace hd {
 
-constexpr int kMaxA = 3;
-constexpr int kMaxB = 6;  // outputs of a quadratic multiplication operator
+constexpr int kMaxA = 3;   // inputs one kernel launch combines
+constexpr int kMaxIn = 6;  // inputs of a plan (quadratic operators; products take kMaxA)
+constexpr int kMaxB = 8;   // outputs of a quadratic multiplication operator
 
 // Quadratic multiplication operator (Sec. 2: mult maps the A transforms to B
-// outputs pointwise): one output's H = sum_{i <= j} c_ij F_i F_j, the pairs
-// (0,0), (0,1), (0,2), (1,1), (1,2), (2,2) in slots 0 .. 5 (unused: 0).
+// outputs pointwise): one launch's share of an output, H = sum_{i <= j}
+// c_ij F_i F_j over the launch's (at most three) inputs, the pairs (0,0),
+// (0,1), (0,2), (1,1), (1,2), (2,2) in slots 0 .. 5 (unused: 0).
 template <typename T>
 struct QuadMult {
   int on;     // 0: the product of the A transforms (B = 1)
@@ -82,6 +84,7 @@ struct FusedArgs {
   int herm;  // 1: Hermitian rows (half storage, see above)
   int pair;  // 1: Hermitian rows transform two residues per complex transform
   QuadMult<T> quad;  // multiplication operator of the output this launch computes
+  int out_add;       // quadratic operators: add to the output (later shares of one output)
   T scale;  // 1/(q m)
   FftDesc fd;
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)

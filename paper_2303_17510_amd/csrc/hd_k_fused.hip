@@ -164,7 +164,12 @@ __global__ void __launch_bounds__(512) k_fused1d(FusedArgs<T> a) {
         const uint32_t i = (uint32_t)(t * m + g + G * e) - sh;
         // Hermitian rows keep the outputs c = i - H >= 0, at c
         const uint32_t o = herm ? i - H : i;
-        if (i < L && (!herm || i >= H)) st_at(dst, o, cscale(acc[t][e], a.scale));
+        if (i < L && (!herm || i >= H)) {
+          cpx<T> v = cscale(acc[t][e], a.scale);
+          if constexpr (QUAD)
+            if (a.out_add) v = v + ld_at(dst, o);
+          st_at(dst, o, v);
+        }
       }
   }
 }

@@ -233,7 +233,7 @@ class Plan:
 
     def profile_end(self) -> list:
         """Per-launch-slot timing since :meth:`profile_begin` (waits for the events)."""
-        cap = 64
+        cap = 1024  # launch slots of one execute
         arr = (_L.KernelStat * cap)()
         n = ctypes.c_int(0)
         _L.check(_L.lib().hdconv_profile_end(self._h, arr, cap, ctypes.byref(n)))

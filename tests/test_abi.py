@@ -324,8 +324,15 @@ def test_quadratic_operator_validation_and_accounting():
     with pytest.raises(ValueError):
         Plan((100,), B=2, mult="quadratic", host_only=True)  # no coefficients
     with pytest.raises(_lib.HdconvError) as ei:
-        Plan((100,), B=7, mult="quadratic", coef=[basdevant[0]] * 7, host_only=True)
+        Plan((100,), B=9, mult="quadratic", coef=[basdevant[0]] * 9, host_only=True)
     assert ei.value.code == _lib.EINVAL
+    # more than three inputs only with a quadratic operator, at most six
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), A=4, host_only=True)
+    assert ei.value.code == _lib.EUNSUPPORTED
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((100,), A=7, B=1, mult="quadratic", coef=[[[0] * 7] * 7], host_only=True)
+    assert ei.value.code == _lib.EUNSUPPORTED
     with pytest.raises(_lib.HdconvError) as ei:
         Plan((100,), B=2, mult="quadratic", coef=basdevant, tuner="exhaustive")
     assert ei.value.code == _lib.EUNSUPPORTED
@@ -344,3 +351,35 @@ def test_quadratic_operator_validation_and_accounting():
               variant="multipass", host_only=True) as p:
         assert p.info()["dims"][0]["D"] == 1 and p.info()["dims"][0]["n"] == 2
         assert p.info()["launches"] == 2 * 3 * 2
+
+
+def mhd_coefficients():
+    """Elsasser form of the 3D MHD nonlinearity: inputs z+ (0, 1, 2) and z-
+    (3, 4, 5); outputs z+_0 z-_0 - z+_2 z-_2, z+_1 z-_1 - z+_2 z-_2 and the
+    six products z+_i z-_j, i != j (A = 6, B = 8)."""
+    def out(terms):
+        c = [[0.0] * 6 for _ in range(6)]
+        for (i, j), w in terms.items():
+            c[min(i, j)][max(i, j)] += w
+        return c
+    coef = [out({(0, 3): 1, (2, 5): -1}), out({(1, 4): 1, (2, 5): -1})]
+    coef += [out({(i, 3 + j): 1}) for i in range(3) for j in range(3) if i != j]
+    return coef
+
+
+def test_six_input_quadratic_operator_shares():
+    coef = mhd_coefficients()
+    # outputs with four inputs run as two launches of two, the rest as one:
+    # 2 + 2 + 6 row launches in 1D
+    with Plan((1000,), A=6, B=8, mult="quadratic", coef=coef, variant="fused", host_only=True) as p:
+        assert p.M == (2000,) and p.info()["launches"] == 10
+    # 2D: the outer forward pass in two launches of three inputs, per output
+    # its row launches and one outer inverse pass
+    with Plan((33, 47), A=6, B=8, mult="quadratic", coef=coef, host_only=True) as p:
+        assert p.info()["launches"] == 2 + 10 + 8
+    # inner-form rows with two residue blocks: per block two column launches,
+    # then per share a row and a column launch
+    with Plan((3000,), A=6, B=8, mult="quadratic", coef=coef, m=64, variant="multipass", D=1,
+              host_only=True) as p:
+        d = p.info()["dims"][0]
+        assert d["n"] == 2 and p.info()["launches"] == 8 * 2 * 2 + 2 * 2 * 10

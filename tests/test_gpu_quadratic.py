@@ -169,3 +169,49 @@ def test_copies(gpu, dtype, shape):
 def test_single_output_in_place(gpu, dtype):
     check((777,), dtype, random_coef(1, 3, 2), in_place=True)
     check((3000,), dtype, random_coef(1, 2, 3), in_place=True, m=64, variant="multipass", D=1)
+
+
+def mhd_coefficients():
+    """Elsasser form of the 3D MHD nonlinearity (A = 6, B = 8): inputs z+
+    (0, 1, 2) and z- (3, 4, 5); outputs z+_0 z-_0 - z+_2 z-_2,
+    z+_1 z-_1 - z+_2 z-_2 and the six products z+_i z-_j, i != j."""
+    def out(terms):
+        c = [[0.0] * 6 for _ in range(6)]
+        for (i, j), w in terms.items():
+            c[min(i, j)][max(i, j)] += w
+        return c
+    coef = [out({(0, 3): 1, (2, 5): -1}), out({(1, 4): 1, (2, 5): -1})]
+    coef += [out({(i, 3 + j): 1}) for i in range(3) for j in range(3) if i != j]
+    return coef
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", [(1000,), (33, 47), (6, 7, 8)])
+def test_mhd_six_inputs_eight_outputs(gpu, dtype, shape):
+    check(shape, dtype, mhd_coefficients(), profile=True)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("D", [None, 1])
+def test_mhd_multipass_rows(gpu, dtype, D):
+    info = check((3000,), dtype, mhd_coefficients(), m=64, variant="multipass", D=D, profile=True)
+    assert info["dims"][0]["variant"] == "multipass"
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("A,B", [(4, 2), (5, 3), (6, 2)])
+def test_dense_random_coefficients_many_inputs(gpu, dtype, A, B):
+    # every pair weighted: outputs split into several launches, some with a
+    # zero-weight companion input
+    check((777,), dtype, random_coef(B, A, 40 + A), profile=True)
+    check((20, 30), dtype, random_coef(B, A, 50 + A))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_mhd_centered_hermitian_explicit(gpu, dtype):
+    coef = mhd_coefficients()
+    check((301,), dtype, coef, kind="centered")
+    check((21, 31), dtype, coef, kind="hermitian")
+    check((5000,), dtype, coef, kind="hermitian", m=64, variant="multipass")
+    check((500,), dtype, coef, method="explicit", profile=True)
+    check((500,), dtype, coef, copies=2)
