@@ -476,3 +476,22 @@ def test_quadratic_mult_three_inputs_random_coefficients():
     lower = coef + np.tril(rng.uniform(-1, 1, size=(3, 3)), -1)[None]
     for g_, w_ in zip(oracle.conv_quadratic(f, lower), got):
         assert np.array_equal(g_, w_)
+
+
+def test_quadratic_mult_six_inputs_mhd_form():
+    # the 3D MHD terms in Elsasser form (z+ inputs 0-2, z- inputs 3-5), in 1D,
+    # against the DFT definition with numpy's FFT
+    L = 29
+    f = [rnd(L, 210 + a) for a in range(6)]
+    coef = np.zeros((8, 6, 6))
+    coef[0, 0, 3], coef[0, 2, 5] = 1, -1
+    coef[1, 1, 4], coef[1, 2, 5] = 1, -1
+    pairs = [(i, 3 + j) for i in range(3) for j in range(3) if i != j]
+    for b, (i, j) in enumerate(pairs):
+        coef[2 + b, i, j] = 1
+    got = oracle.conv_quadratic(f, coef)
+    N = 2 * L - 1
+    F = [np.fft.fft(x, N) for x in f]
+    want = [F[0] * F[3] - F[2] * F[5], F[1] * F[4] - F[2] * F[5]] + [F[i] * F[j] for i, j in pairs]
+    for g_, H in zip(got, want):
+        assert oracle.rel_l2(g_, np.fft.ifft(H)[:L]) < 1e-13
