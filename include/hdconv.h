@@ -268,7 +268,8 @@ void hdconv_model_destroy(void* model);
 
 /* Batched plans: `count` independent one-dimensional convolutions of uneven
  * length (dims = 1), L[i] and M[i] each as in hdconv_plan, all with the same
- * A, B and dtype.  Convolutions whose planned shape (variant, m, p, q and
+ * A in {2,3}, B = 1 (the product operator; HDCONV_EUNSUPPORTED otherwise)
+ * and dtype.  Convolutions whose planned shape (variant, m, p, q and
  * kernel widths) coincides form one group; each group runs as one set of
  * launches over a device table of per-row pointers and lengths, groups run
  * on parallel branches (four side streams forked from and joined to the

@@ -1937,6 +1937,10 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
     set_err(HDCONV_EUNSUPPORTED, "batched plans need A in {2,3} and B = 1");
     return nullptr;
   }
+  if (opt && opt->mult != HDCONV_MULT_PRODUCT) {
+    set_err(HDCONV_EUNSUPPORTED, "batched plans take the product operator only");
+    return nullptr;
+  }
   if (dtype != HDCONV_C64 && dtype != HDCONV_C128) {
     set_err(HDCONV_EINVAL, "dtype must be HDCONV_C64 or HDCONV_C128");
     return nullptr;

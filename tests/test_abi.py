@@ -383,3 +383,17 @@ def test_six_input_quadratic_operator_shares():
               host_only=True) as p:
         d = p.info()["dims"][0]
         assert d["n"] == 2 and p.info()["launches"] == 8 * 2 * 2 + 2 * 2 * 10
+
+
+def test_batched_plans_reject_quadratic_operators():
+    lib = _lib.lib()
+    opt = _lib.Options()
+    lib.hdconv_options_init(ctypes.byref(opt))
+    opt.mult = _lib.MULT_QUADRATIC
+    coef = (ctypes.c_double * 4)(1, 0, 0, 1)
+    opt.mult_coef = ctypes.cast(coef, ctypes.POINTER(ctypes.c_double))
+    Ls = (ctypes.c_int64 * 2)(100, 200)
+    Ms = (ctypes.c_int64 * 2)(200, 400)
+    h = lib.hdconv_plan_batched(Ls, Ms, 2, 2, 1, 1, _lib.C64, ctypes.byref(opt))
+    assert not h
+    assert _lib.last_error()[0] == _lib.EUNSUPPORTED
