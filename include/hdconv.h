@@ -62,7 +62,8 @@ enum { HDCONV_METHOD_AUTO = 0, HDCONV_METHOD_HYBRID = 1, HDCONV_METHOD_EXPLICIT 
  * of A = 2; the outputs are computed one after another from transforms of
  * the inputs made once (the row pass transforms the rows of the inputs an
  * output needs, at most three per launch: with more, an output is the sum of
- * several launches), and must not overlap the inputs or each other. */
+ * several launches), and must not overlap the inputs or each other (also
+ * for B = 1 when an output sums several launches). */
 enum { HDCONV_MULT_PRODUCT = 0, HDCONV_MULT_QUADRATIC = 1 };
 
 /* per-dimension kernel variant */
@@ -227,7 +228,8 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
  * null stream).  inputs: A device pointers, outputs: B device pointers, each
  * to prod(L) words of dtype (Hermitian plans: ceil(L/2) in the last
  * dimension; with copies, (C-1) dist + that many).  outputs[0] may equal one of the inputs
- * (in place, as in Algorithm 1); any other overlap is HDCONV_EINVAL.  The
+ * (in place, as in Algorithm 1; not for the quadratic operators that must
+ * run out of place, see above); any other overlap is HDCONV_EINVAL.  The
  * inputs are not modified unless aliased by the output.  Returns the launch
  * status; no synchronisation is done. */
 int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, void* stream);

@@ -1189,14 +1189,16 @@ int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, 
     if (!outputs[b]) return set_err(HDCONV_EINVAL, "outputs[%d] is NULL", b);
   auto overlap = [&](const char* x, const char* y) { return x < y + bytes && y < x + bytes; };
   const char* o = (const char*)outputs[0];
+  // several outputs, or one summed over several row-pass launches, are
+  // written while inputs are still read: then no output may touch an input
+  const bool out_of_place = P->B > 1 || max_shares(P) > 1;
   for (int a = 0; a < P->A; ++a) {
     const char* i = (const char*)inputs[a];
-    if (P->B == 1 && i != o && overlap(i, o))
+    if (!out_of_place && i != o && overlap(i, o))
       return set_err(HDCONV_EINVAL, "outputs[0] partially overlaps inputs[%d]", a);
-    // several outputs are written one after another: none may touch an input
-    for (int b = 0; P->B > 1 && b < P->B; ++b)
+    for (int b = 0; out_of_place && b < P->B; ++b)
       if (overlap(i, (const char*)outputs[b]))
-        return set_err(HDCONV_EINVAL, "outputs[%d] overlaps inputs[%d] (B > 1 runs out of place)", b, a);
+        return set_err(HDCONV_EINVAL, "outputs[%d] overlaps inputs[%d] (this operator runs out of place)", b, a);
   }
   for (int b = 0; b < P->B; ++b)
     for (int c = b + 1; c < P->B; ++c)

@@ -215,3 +215,21 @@ def test_mhd_centered_hermitian_explicit(gpu, dtype):
     check((5000,), dtype, coef, kind="hermitian", m=64, variant="multipass")
     check((500,), dtype, coef, method="explicit", profile=True)
     check((500,), dtype, coef, copies=2)
+
+
+def test_summed_output_runs_out_of_place(gpu):
+    # one output over four inputs runs as two launches that both read the
+    # inputs: the output may not alias an input
+    import torch
+    from paper_2303_17510_amd import _lib
+    coef = [[[1, 0, 0, 0], [0, 0, 0, 0], [0, 0, 0, 1], [0, 0, 0, 0]]]  # F_0^2 + F_2 F_3
+    with Plan((300,), A=4, B=1, mult="quadratic", coef=coef) as p:
+        xs = [torch.from_numpy(synth.unit_disk((300,), 7900 + a).astype(np.complex128)).cuda() for a in range(4)]
+        with pytest.raises(_lib.HdconvError) as ei:
+            p.execute(xs, xs[0])
+        assert ei.value.code == _lib.EINVAL
+        out = torch.empty_like(xs[0])
+        p.execute(xs, out)
+        torch.cuda.synchronize()
+        want = oracle.conv_quadratic([synth.as_oracle(x.cpu().numpy()) for x in xs], coef)[0]
+        assert oracle.rel_l2(out.cpu().numpy(), want) <= TOL["c128"]
