@@ -223,7 +223,7 @@ def test_summed_output_runs_out_of_place(gpu):
     import torch
     from paper_2303_17510_amd import _lib
     coef = [[[0, 1, 0, 0], [0, 0, 0, 0], [0, 0, 0, 1], [0, 0, 0, 0]]]  # F_0 F_1 + F_2 F_3
-    with Plan((300,), A=4, B=1, mult="quadratic", coef=coef) as p:
+    with Plan((300,), A=4, B=1, mult="quadratic", coef=coef, dtype="c128") as p:
         xs = [torch.from_numpy(synth.unit_disk((300,), 7900 + a).astype(np.complex128)).cuda() for a in range(4)]
         with pytest.raises(_lib.HdconvError) as ei:
             p.execute(xs, xs[0])
