@@ -113,6 +113,8 @@ def make_inputs(wl, dtype):
     from paper_2303_17510_amd import synth
     npdt = np.complex64 if dtype == "c64" else np.complex128
     shape = tuple(wl["L"][:-1]) + ((wl["L"][-1] + 1) // 2,) if wl.get("hermitian") else tuple(wl["L"])
+    if wl.get("copies", 1) > 1:
+        shape = (wl["copies"],) + shape
     xs = synth.inputs(wl["config_id"], wl["A"], shape, wl.get("dist", "disk"), dtype=npdt)
     return xs, [torch.from_numpy(x).cuda() for x in xs]
 
@@ -190,13 +192,15 @@ def leg(wl, dtype, method, steps, warmup, tuner="heuristic", m=None, **plan_kw):
         kw["hermitian"] = True
     if wl.get("B", 1) > 1:
         kw.update(B=wl["B"], mult="quadratic", coef=wl["coef"])
+    if wl.get("copies", 1) > 1:
+        kw["copies"] = wl["copies"]
     with Plan(tuple(wl["L"]), tuple(wl["M"]), A=wl["A"], dtype=dtype, method=method, tuner=tuner, **kw) as p:
         plan_s = time.perf_counter() - t0
         info = p.info()
         ms, stats, out = time_plan(p, dev, steps, warmup)
     name, avg_ms, bpl, agg = dominant(stats)
     # outputs of the convolution (a Hermitian result of length L has L entries, half stored), all B arrays
-    n_out = wl.get("B", 1)
+    n_out = wl.get("B", 1) * wl.get("copies", 1)
     for l in wl["L"]:
         n_out *= l
     r = {"stats": stats, "info": info, "dtype": dtype, "method": method, "tuner": tuner, "plan_s": plan_s,
@@ -441,6 +445,13 @@ def main():
                 put("L1500000_hybrid_c64_model", lambda: leg(w15, "c64", "hybrid", sc, 5, tuner="model"))
                 put("batched_4096_c64_model", lambda: batched_leg(sb, 3, tuner="model"))
             put("C1_8192_copies_c128", lambda: batched_leg(sb, 3, dtype="c128", Ls=[1024] * 8192, config_id=0))
+            # C1 itself: one L = 1024 convolution (latency-bound: a single workgroup), and
+            # the same problem as 8192 copies of one plan (the problem descriptor's copies)
+            w1 = {"workload": "1D complex conv, A=2, B=1, L=1024, M=2048, complex128, unit disk",
+                  "L": [1024], "M": [2048], "A": 2, "dtype": "c128", "config_id": 0}
+            put("C1_single_hybrid_c128", lambda: leg(w1, "c128", "hybrid", sc, 5))
+            put("C1_single_explicit_c128", lambda: leg(w1, "c128", "explicit", sc, 5))
+            put("C1_plan_8192_copies_c128", lambda: leg(dict(w1, copies=8192), "c128", "hybrid", sb, 3))
             # the 2D and 3D workloads, on the same GPU
             w4, w5 = workload("c4"), workload("c5_3d")
             for dt in ("c64", "c128"):
