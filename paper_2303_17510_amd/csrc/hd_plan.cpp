@@ -441,8 +441,10 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
       }
     }
     // Inner form: the least padding q m over m = 1024 .. 8192 and p a power
-    // of two, or 3 * 2^k from 96 up (small column transforms with a factor 3
-    // measured slow; FP64 ones spill, so powers of two there).  Among equal
+    // of two, or for FP32 beyond L = 2^21 also 3 * 2^k from 96 up (column
+    // transforms with a factor 3 measured slower even at 25 % less padding
+    // below that: L = 7e5 62 -> 44 us, 1.5e6 95 -> 88 us with powers of two;
+    // FP64 ones spill, so powers of two there).  Among equal
     // padding the m nearest the measured best for that size: for a single
     // convolution 2048 up to q m = 2^20, 4096 for 2^21, 8192 beyond; for many
     // rows (throughput) 4096.  Rows of 4096 points or more take 16 points per
@@ -456,7 +458,7 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
       const int64_t pmin = cdiv(L, mm);
       std::vector<int64_t> ps = {pow2_ceil(pmin)};
       const int64_t p3 = next_col_size(pmin);
-      if (tbytes == 4 && p3 % 3 == 0 && p3 >= 96) ps.push_back(p3);
+      if (tbytes == 4 && p3 % 3 == 0 && p3 >= 96 && L > (int64_t(1) << 21)) ps.push_back(p3);
       for (int64_t p : ps) {
         if (p > kMaxColP) continue;
         DimPlan c;
