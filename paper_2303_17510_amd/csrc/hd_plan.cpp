@@ -425,7 +425,13 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // up to 4096 points.  Many rows are throughput-bound: m >= L with the
     // residues looped (q = 2 for M = 2L), half the transform work.  Powers
     // of two only: sizes with a factor 3 measured slower at equal padding.
-    const int64_t m = std::max<int64_t>(8, pow2_ceil(lines <= 1 ? M : L));
+    // The rows of 2D plans up to 1024 points and of 3D plans up to 64 points
+    // also take one transform of m >= M: the recorded 2D timings give
+    // 1.12-1.32x per size class (1.0x at 2048), the 3D ones 1.09-1.16x up to
+    // 64 points and 0.87-0.95x beyond.
+    const int64_t mM = std::max<int64_t>(8, pow2_ceil(M));
+    const int64_t q1max = dims == 2 ? 1024 : (dims == 3 ? 64 : 0);
+    const int64_t m = (lines <= 1 || mM <= q1max) ? mM : std::max<int64_t>(8, pow2_ceil(L));
     // (sizes 3 * 2^k, even with 25 % less padding, measured slower here:
     // 1D single rows 1.9-2.1x, 2D rows 1.2-1.6x, 3D rows 1.1x)
     if (m <= 4096) {
