@@ -183,13 +183,15 @@ static bool pick_e_col(int64_t p, int tbytes, int* E) {
 // Points per lane of an outer-dimension transform: the workgroup holds S
 // adjacent columns, so fewer lanes per column give wider coalesced rows, but
 // short transforms run best with few points per lane (measured: 4 up to 256
-// points, 8 up to 1024, 16 beyond in FP32 and for the p = 2 form).
+// points, 8 up to 1024, 16 beyond in FP32 and for the p = 2 form except at
+// 512 points).
 static bool pick_e_outer(int64_t m, int64_t p, int tbytes, int* E) {
   if (m % 3 == 0) {
     *E = 12;
     return m % 12 == 0 && m / 12 <= kMaxThreads;
   }
-  if (tbytes == 4) *E = (p >= 2 || m > 1024) ? 16 : (m <= 256 ? 4 : 8);
+  // (the p = 2 form of 512 points: 8, recorded 2D timings 1.12-1.29x over 16)
+  if (tbytes == 4) *E = ((p >= 2 && m != 512) || m > 1024) ? 16 : (m <= 256 ? 4 : 8);
   else *E = m <= 256 ? 4 : 8;
   if (m < *E) *E = (int)m;
   while (m / *E > kMaxThreads && *E < 16) *E *= 2;
@@ -438,7 +440,18 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
       const DimPlan base_try = [&] {
         DimPlan t;
         std::string w2;
-        if (!set_geom(&t, L, M, m, 0, VAR_FUSED) || !finish_dim(&t, A, tbytes, &w2)) t.m = 0;
+        if (!set_geom(&t, L, M, m, 0, VAR_FUSED)) {
+          t.m = 0;
+          return t;
+        }
+        // a lone FP32 row of up to 1024 points: 4 points per lane, one row
+        // per workgroup (the most lanes for one latency-bound workgroup;
+        // recorded timings 1.22x at 1024 points, 0.98x at 2048)
+        if (lines <= 1 && tbytes == 4 && m >= 16 && m <= 1024) {
+          t.E_m = 4;
+          t.rows_per_block = 1;
+        }
+        if (!finish_dim(&t, A, tbytes, &w2)) t.m = 0;
         return t;
       }();
       if (base_try.m) {
