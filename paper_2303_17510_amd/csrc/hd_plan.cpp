@@ -482,7 +482,9 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // convolution 2048 up to q m = 2^20, 4096 for 2^21, 8192 beyond; for many
     // rows (throughput) 4096.  Rows of 4096 points or more take 16 points per
     // lane when there are enough of them (n p lines >= 512) to fill the
-    // chip, else 8.
+    // chip and the rows combine two inputs, else 8 (with three inputs the
+    // 16-point row kernel spills: recorded timings 1.15-1.33x for 8, whole
+    // plans L = 7.5e5 117 -> 96 us, 3.2e6 568 -> 482 us).
     DimPlan best;
     bool found = false;
     double best_key = 0;
@@ -496,7 +498,7 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
         if (p > kMaxColP) continue;
         DimPlan c;
         if (!set_geom(&c, L, M, mm, p, VAR_MULTI)) continue;
-        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && c.n * c.p * lines >= 512)) ? 16 : 8;
+        if (tbytes == 4) c.E_m = (mm >= 8192 || (mm >= 4096 && A == 2 && c.n * c.p * lines >= 512)) ? 16 : 8;
         if (!finish_dim(&c, A, tbytes, &w)) continue;
         const double qm = (double)(c.q * c.m);
         const double mt = lines > 1 ? 4096.0
