@@ -233,3 +233,28 @@ def test_summed_output_runs_out_of_place(gpu):
         torch.cuda.synchronize()
         want = oracle.conv_quadratic([synth.as_oracle(x.cpu().numpy()) for x in xs], coef)[0]
         assert oracle.rel_l2(out.cpu().numpy(), want) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_strided_rows(gpu, dtype):
+    # padded rows (element stride 40 for rows of 30): every output through
+    # the strided first outer pass; the padding words stay untouched
+    import torch
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    shape, st = (20, 30), 40
+    coef = BASDEVANT_2D
+    with Plan(shape, A=2, B=2, dtype=dtype, mult="quadratic", coef=coef, strides=(st,)) as p:
+        xs = [synth.unit_disk(shape, 7950 + a).astype(npdt) for a in range(2)]
+        flat = []
+        for x in xs:
+            buf = np.full((shape[0], st), SENTINEL, dtype=npdt)
+            buf[:, : shape[1]] = x
+            flat.append(torch.from_numpy(buf.ravel()).cuda())
+        outs = [torch.full_like(flat[0], SENTINEL) for _ in range(2)]
+        p.execute(flat, outs)
+        torch.cuda.synchronize()
+    want = oracle.conv_quadratic([synth.as_oracle(x) for x in xs], coef)
+    for b in range(2):
+        got = outs[b].cpu().numpy().reshape(shape[0], st)
+        assert oracle.rel_l2(got[:, : shape[1]], want[b]) <= TOL[dtype]
+        assert np.all(got[:, shape[1]:] == npdt(SENTINEL))
