@@ -459,9 +459,9 @@ def main():
             put("C4_2048x2048_explicit_c64", lambda: leg(w4, "c64", "explicit", 10, 2))
             if have_model:
                 put("C4_2048x2048_hybrid_c64_model", lambda: leg(w4, "c64", "hybrid", 20, 3, tuner="model"))
-            put("C5_256cube_hybrid_c64", lambda: leg(w5, "c64", "hybrid", 10, 2))
+            put("C5_256cube_hybrid_c64", lambda: leg(w5, "c64", "hybrid", 30, 5))
             if have_model:
-                put("C5_256cube_hybrid_c64_model", lambda: leg(w5, "c64", "hybrid", 10, 2, tuner="model"))
+                put("C5_256cube_hybrid_c64_model", lambda: leg(w5, "c64", "hybrid", 30, 5, tuner="model"))
             # centered convolutions (padding 3L/2 per dimension)
             wc, wc4 = workload("c2_centered"), workload("c4_centered")
             for dt in ("c64", "c128"):
@@ -485,7 +485,7 @@ def main():
             for n in (96, 100, 127, 150, 181, 200, 229, 256):
                 w3 = {"workload": "3D sweep", "L": [n] * 3, "M": [2 * n] * 3, "A": 2, "dtype": "c64",
                       "config_id": 4}
-                h = run("sweep3d_%d" % n, lambda: leg(w3, "c64", "hybrid", 5, 2))
+                h = run("sweep3d_%d" % n, lambda: leg(w3, "c64", "hybrid", 20, 5))
                 x = run("sweep3d_%d_explicit" % n, lambda: leg(w3, "c64", "explicit", 3, 1))
                 if h and x:
                     sweep[str(n)] = {"hybrid_ms": h[0]["ms"], "explicit_ms": x[0]["ms"],
@@ -504,7 +504,7 @@ def main():
                                         ("basdevant_256cube_c64", workload("basdevant3d"),
                                          "C5_256cube_hybrid_c64", 6),
                                         ("mhd_256cube_c64", workload("mhd3d"), "C5_256cube_hybrid_c64", 9)):
-                r = put(nm, lambda: leg(wq, "c64", "hybrid", 10, 2))
+                r = put(nm, lambda: leg(wq, "c64", "hybrid", 10, 3))
                 if r and "ms" in compare.get(base, {}):
                     compare[nm]["pairwise_products_ms"] = pairs * compare[base]["ms"]
                     compare[nm]["speedup_vs_pairwise"] = pairs * compare[base]["ms"] / compare[nm]["ms"]
