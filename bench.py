@@ -371,8 +371,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the hybrid-dealiasing path here runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); run without --gpus or with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the hybrid-dealiasing path runs on a single MI355X "
+              "(several GPUs would each take a share of the residues or of a batch); run without --gpus "
+              "or with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -537,7 +538,7 @@ def main():
     if flops:
         tf = flops / (dom["avg_ms"] * 1e-3) / 1e12
         # FP32 vector peak 157.3 TFLOP/s counts packed FP32 instructions,
-        # which this build does not emit: 78.6 TFLOP/s without them
+        # which the library's kernels are compiled without: 78.6 TFLOP/s without them
         pk = 157.3 if wl["dtype"] == "c64" else 78.6
         alu = {"achieved": tf, "peak": pk, "unit": "TFLOP/s", "frac": tf / pk,
                "peak_without_packed_fp32": 78.6, "flops_per_launch": flops}

@@ -40,7 +40,7 @@ enum {
   HDCONV_EINVAL = -1,      /* invalid argument (sizes, pointers, geometry) */
   HDCONV_ENOMEM = -2,      /* device allocation failed or exceeds the cap  */
   HDCONV_EDEVICE = -3,     /* a HIP call failed; message has its text       */
-  HDCONV_EUNSUPPORTED = -4,/* valid request outside what this build runs    */
+  HDCONV_EUNSUPPORTED = -4,/* valid request the library does not support    */
   HDCONV_ENODEV = -5       /* no HIP device is available                    */
 };
 
