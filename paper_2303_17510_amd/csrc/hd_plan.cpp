@@ -547,7 +547,10 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     const int64_t ma = std::max<int64_t>(8, pow2_ceil(L)), mb = std::max<int64_t>(8, pow2_ceil(cdiv(L, 2)));
     const bool oka = ma <= kMaxFusedM && set_geom(&a, L, M, ma, 0, VAR_OUTER) && finish_dim(&a, A, tbytes, &w);
     const bool okb = set_geom(&b, L, M, mb, 0, VAR_OUTER) && finish_dim(&b, A, tbytes, &w);
-    if (oka && (!okb || a.q * a.m < b.q * b.m || (a.q * a.m == b.q * b.m && ma <= 1024))) {
+    // (in 2D plans halves of 256 points or fewer lose to the whole transform
+    // even with more padding: recorded timings 1.33x for p = 1 at L ~ 350,
+    // A = 3; in 3D the halves stay ahead)
+    if (oka && (!okb || (dims == 2 && mb <= 256) || a.q * a.m < b.q * b.m || (a.q * a.m == b.q * b.m && ma <= 1024))) {
       *dp = a;
       return true;
     }
