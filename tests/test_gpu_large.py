@@ -114,7 +114,7 @@ def test_1d_maximum_length(gpu):
 @pytest.mark.parametrize("n", [150, 229])
 def test_3d_non_power_of_two(gpu, dtype, n):
     # default 3D plans for lengths well below a power of two: 3 * 2^k outer
-    # transforms (150: 384 points, rows of 256), else two residues of half
+    # transforms (150: 384 points, rows as two 128-point blocks), else two residues of half
     # the power of two (229: outer 256-point transforms with q = 2)
     ins, got = run_case((n,) * 3, (2 * n,) * 3, dtype, 4)
     e = sampled_err(ins, got, 48, 7)
