@@ -31,6 +31,13 @@
 extern "C" {
 #endif
 
+/* Opaque handles.  A plan owns its device workspace and twiddle tables, a
+ * batched plan its groups, task tables and captured graph, a cost model its
+ * device parameters. */
+typedef struct hdconv_plan_s* hdconv_plan_t;
+typedef struct hdconv_batch_s* hdconv_batch_t;
+typedef struct hdconv_model_s* hdconv_model_t;
+
 /* element types */
 enum { HDCONV_C64 = 0, HDCONV_C128 = 1 };
 
@@ -127,7 +134,7 @@ typedef struct hdconv_options {
   int tune_reps;     /* timed executes per candidate (0: 5)                     */
   double margin;     /* model tuner: time the top candidates when the predicted
                         log-time gap between the best two is below this (0: 0.05) */
-  void* model;       /* model tuner: a cost model from hdconv_model_create      */
+  hdconv_model_t model; /* model tuner: a cost model from hdconv_model_create   */
   const char* db_path; /* timed tuners: append every timing to this CSV (NULL: none) */
   int64_t copies;    /* C independent copies of the problem per execute (0: 1)  */
   int64_t dist;      /* words between the starts of consecutive copies, inputs
@@ -209,8 +216,8 @@ void hdconv_options_init(hdconv_options* opt);
  * above).  Allocates twiddle tables (FP64
  * generated, stored in dtype) and workspace with hipMalloc.  Returns NULL on
  * error (hdconv_last_error gives the reason). */
-void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype);
-void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+hdconv_plan_t hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype);
+hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                      const hdconv_options* opt);
 
 /* Copies (the paper's problem descriptor carries C copies with a stride):
@@ -232,13 +239,13 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
  * run out of place, see above); any other overlap is HDCONV_EINVAL.  The
  * inputs are not modified unless aliased by the output.  Returns the launch
  * status; no synchronisation is done. */
-int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, void* stream);
+int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream);
 
 /* Plan geometry and sizes. */
-int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out);
+int hdconv_plan_info(hdconv_plan_t plan, hdconv_plan_info_t* out);
 
 /* Release a plan (synchronises the device first).  NULL is ignored. */
-void hdconv_destroy(void* plan);
+void hdconv_destroy(hdconv_plan_t plan);
 
 /* The paper's geometry rules for one dimension and a given m (Algorithm 1,
  * eq. pqdef1, Sec. 6.1): p = max(ceil(L/m), p_min); if p <= 2 and not
@@ -247,6 +254,37 @@ void hdconv_destroy(void* plan);
  * MULTIPASS for the inner form). */
 int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner,
                     hdconv_dim_info_t* out);
+
+/* The same rules for the centered and Hermitian dimensions (flags:
+ * HDCONV_PLAN_CENTERED or HDCONV_PLAN_HERMITIAN; 0 is hdconv_geometry).  A
+ * centered dimension's signed indices -H .. L-1-H lie in
+ * hdconv_centered_span(L, m) = ceil(H/m) + ceil((L-H)/m) blocks of m points.
+ * Direct form (that span <= 2, the centered case of the paper's centered
+ * one-dimensional section): p = span, q = n = ceil(M/m).  Inner form (the
+ * paper's centered inner loop): the negative blocks fold onto the column
+ * positions of the non-negative ones, so the column DFT needs only
+ * p = max(p_min, ceil((L-H)/m)) points -- the paper's p/2 for its even block
+ * count p -- and n = ceil(M/(p m)), q = n p.  Example (the optimizer's
+ * choice for the 2D Hermitian L = 2048, M = 3072 benchmark, Sec. 7.2): m = 16
+ * spans 128 blocks, p = 64, n = 3, q = 192.  HDCONV_PLAN_HERMITIAN takes the
+ * nominal length L and works on the centered length 2 ceil(L/2) - 1 its
+ * stored half stands for (out->L).  out->centered is 1 (centered) or 2
+ * (Hermitian).  Host only; HDCONV_EINVAL for bad arguments or flags. */
+int hdconv_geometry_ex(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner, int flags,
+                       hdconv_dim_info_t* out);
+/* Blocks of m points the signed indices of a centered dimension of extent L
+ * span: ceil(H/m) + ceil((L-H)/m), H = floor(L/2) (0 for L < 1 or m < 1). */
+int64_t hdconv_centered_span(int64_t L, int64_t m);
+
+/* Least padded length M that hdconv_plan accepts for one dimension of extent
+ * L and A factors per product (a quadratic operator multiplies two: pass
+ * A = 2), written to *M.  flags 0: A(L-1)+1, the padding that keeps a linear
+ * product of A inputs unaliased (Sec. 2); HDCONV_PLAN_CENTERED: the centered
+ * minimum max(A(L-1-H)+H, L-1-H+AH)+1 (3L/2 for A = 2 and even L);
+ * HDCONV_PLAN_HERMITIAN: that minimum for the centered length
+ * 2 ceil(L/2) - 1 a stored half stands for.  HDCONV_EINVAL for L < 1, A
+ * outside 2 .. 3 or other flags. */
+int hdconv_min_padding(int64_t L, int A, int flags, int64_t* M);
 
 /* Learned cost model (the planner's model tuner).  A multilayer perceptron:
  * HDCONV_NFEATURES inputs (normalised by the training set's mean and
@@ -257,16 +295,16 @@ int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_in
  * W2[H][H], b2[H], W3[H][H], b3[H], W4[H], b4 (the network), then xmean[NF],
  * xstd[NF], ymean, ystd.  X arrays are row-major n x HDCONV_NFEATURES host
  * floats; y holds log run times.  All calls synchronise. */
-void* hdconv_model_create(int hidden, uint64_t seed);      /* Glorot-uniform init; NULL on error */
-int hdconv_model_params(void* model, float* params, int cap, int* n);
-int hdconv_model_load(void* model, const float* params, int n);
-int hdconv_model_train(void* model, const float* X, const float* y, int64_t n, int epochs, int batch, float lr,
+hdconv_model_t hdconv_model_create(int hidden, uint64_t seed);      /* Glorot-uniform init; NULL on error */
+int hdconv_model_params(hdconv_model_t model, float* params, int cap, int* n);
+int hdconv_model_load(hdconv_model_t model, const float* params, int n);
+int hdconv_model_train(hdconv_model_t model, const float* X, const float* y, int64_t n, int epochs, int batch, float lr,
                        uint64_t seed, float* final_loss);
-int hdconv_model_predict(void* model, const float* X, int64_t n, float* out);
+int hdconv_model_predict(hdconv_model_t model, const float* X, int64_t n, float* out);
 /* Gradient of the loss over all n rows with respect to the network
  * parameters (with the model's current normalisation) and the loss. */
-int hdconv_model_grad(void* model, const float* X, const float* y, int64_t n, float* grad, float* loss);
-void hdconv_model_destroy(void* model);
+int hdconv_model_grad(hdconv_model_t model, const float* X, const float* y, int64_t n, float* grad, float* loss);
+void hdconv_model_destroy(hdconv_model_t model);
 
 /* Batched plans: `count` independent one-dimensional convolutions of uneven
  * length (dims = 1), L[i] and M[i] each as in hdconv_plan, all with the same
@@ -285,7 +323,7 @@ void hdconv_model_destroy(void* model);
  * zeroed scratch buffers); EXHAUSTIVE times all, MODEL ranks them with
  * opt->model and times the top three when the best two predictions are
  * within opt->margin.  Groups whose tuned shapes coincide are merged. */
-void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
+hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
                           const hdconv_options* opt);
 
 /* inputs: count*A device pointers (convolution i uses inputs[i*A + a]);
@@ -293,14 +331,14 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
  * ceil(L[i]/2) words).  Uploads the task
  * table (asynchronously, on `stream`) and launches; the pinned staging
  * buffer is reused, so an execute waits for the previous execute's upload. */
-int hdconv_execute_batched(void* batch, const void* const* inputs, void* const* outputs, void* stream);
+int hdconv_execute_batched(hdconv_batch_t batch, const void* const* inputs, void* const* outputs, void* stream);
 
 /* Groups of a batched plan: shapes into groups[0..cap), member counts into
  * counts[0..cap), and the number of groups into *ngroups. */
-int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups);
+int hdconv_batch_info(hdconv_batch_t batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups);
 
 /* Release a batched plan (synchronises the device first).  NULL is ignored. */
-void hdconv_batch_destroy(void* batch);
+void hdconv_batch_destroy(hdconv_batch_t batch);
 
 /* Per-launch timing.  hdconv_profile_begin(plan, n) creates HIP events for
  * the next n executes of `plan`; each of those executes records an event
@@ -317,8 +355,8 @@ typedef struct hdconv_kernel_stat {
   double bytes_per_launch;  /* algorithmic bytes read + written per launch     */
 } hdconv_kernel_stat_t;
 
-int hdconv_profile_begin(void* plan, int max_executes);
-int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* count);
+int hdconv_profile_begin(hdconv_plan_t plan, int max_executes);
+int hdconv_profile_end(hdconv_plan_t plan, hdconv_kernel_stat_t* out, int cap, int* count);
 
 /* Copy the calling thread's last error message into msg (NUL terminated,
  * truncated to cap) and return its status code (HDCONV_OK if none). */

@@ -75,6 +75,10 @@ SIGNATURES = {
     "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hdconv_destroy": (None, [ctypes.c_void_p]),
     "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),
+    "hdconv_geometry_ex": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(DimInfo)]),
+    "hdconv_centered_span": (_i64, [_i64, _i64]),
+    "hdconv_min_padding": (ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64)]),
     "hdconv_candidates": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo),
                                          ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),

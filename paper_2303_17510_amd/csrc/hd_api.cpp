@@ -483,7 +483,9 @@ static int alloc_tables(Plan* P) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-static int alloc_workspace(Plan* P) {
+// The workspace of a plan as parts (where each part's pointer goes, its
+// bytes); each part starts on a 256-byte boundary.
+static std::vector<std::pair<void**, size_t>> workspace_parts(Plan* P) {
   const size_t w = 2 * (size_t)tbytes_of(P->dtype);
   int64_t Le[3];
   for (int d = 0; d < P->dims; ++d) Le[d] = P->dp[d].L;
@@ -525,20 +527,36 @@ static int alloc_workspace(Plan* P) {
     // (also for outputs summed over several row-pass shares)
     if (dl.D < dl.n || max_shares(P) > 1) want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
   }
-  size_t total = 0;
-  for (auto& x : want) total += align256(x.second);
-  P->work_bytes = total;
-  if (P->host_only || total == 0) return HDCONV_OK;
-  const char* cap = getenv("HDCONV_WORKSPACE_CAP");
-  if (cap && (size_t)atoll(cap) < total)
-    return set_err(HDCONV_ENOMEM, "workspace of %zu bytes exceeds HDCONV_WORKSPACE_CAP=%s", total, cap);
-  hipError_t e = hipMalloc((void**)&P->work_mem, total);
-  if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(workspace, %zu): %s", total, hipGetErrorString(e));
+  return want;
+}
+
+// Point the workspace parts into `base` (nullptr: clear them).
+static void carve_workspace(Plan* P, char* base) {
   size_t o = 0;
-  for (auto& x : want) {
-    *x.first = P->work_mem + o;
+  for (auto& x : workspace_parts(P)) {
+    *x.first = base ? base + o : nullptr;
     o += align256(x.second);
   }
+}
+
+// Workspace bytes, checked against the HDCONV_WORKSPACE_CAP environment
+// variable (a byte count; HDCONV_ENOMEM above it).  Host only.
+static int size_workspace(Plan* P) {
+  size_t total = 0;
+  for (auto& x : workspace_parts(P)) total += align256(x.second);
+  P->work_bytes = total;
+  const char* cap = getenv("HDCONV_WORKSPACE_CAP");
+  if (cap && total > 0 && (size_t)atoll(cap) < total)
+    return set_err(HDCONV_ENOMEM, "workspace of %zu bytes exceeds HDCONV_WORKSPACE_CAP=%s", total, cap);
+  return HDCONV_OK;
+}
+
+static int alloc_workspace(Plan* P) {
+  const size_t total = P->work_bytes;
+  if (P->host_only || total == 0) return HDCONV_OK;
+  hipError_t e = hipMalloc((void**)&P->work_mem, total);
+  if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(workspace, %zu): %s", total, hipGetErrorString(e));
+  carve_workspace(P, P->work_mem);
   return HDCONV_OK;
 }
 
@@ -948,7 +966,51 @@ int hdconv_geometry(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_in
   return HDCONV_OK;
 }
 
-void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+int hdconv_geometry_ex(int64_t L, int64_t M, int64_t m, int64_t p_min, int force_inner, int flags,
+                       hdconv_dim_info_t* out) {
+  clear_err();
+  if (!out) return set_err(HDCONV_EINVAL, "out is NULL");
+  if (L < 1 || M < 1 || m < 1 || p_min < 0) return set_err(HDCONV_EINVAL, "need L, M, m >= 1 and p_min >= 0");
+  if (flags & ~(HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
+    return set_err(HDCONV_EINVAL, "flags may hold HDCONV_PLAN_CENTERED and HDCONV_PLAN_HERMITIAN only");
+  const bool herm = (flags & HDCONV_PLAN_HERMITIAN) != 0;
+  const int ctr = (flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) ? 1 : 0;
+  const int64_t Le = herm ? herm_full(L) : L;  // the centered length a Hermitian half stands for
+  Geometry g = geometry_c(Le, M, m, p_min, force_inner != 0, ctr);
+  memset(out, 0, sizeof(*out));
+  out->L = Le;
+  out->M = M;
+  out->m = g.m;
+  out->p = g.p;
+  out->n = g.n;
+  out->q = g.q;
+  out->D = g.n;
+  out->variant = g.inner ? HDCONV_VARIANT_MULTIPASS : HDCONV_VARIANT_FUSED;
+  out->centered = herm ? 2 : ctr;
+  return HDCONV_OK;
+}
+
+int64_t hdconv_centered_span(int64_t L, int64_t m) {
+  if (L < 1 || m < 1) return 0;
+  return centered_blocks(L, m);
+}
+
+int hdconv_min_padding(int64_t L, int A, int flags, int64_t* M) {
+  clear_err();
+  if (!M) return set_err(HDCONV_EINVAL, "M is NULL");
+  if (L < 1 || A < 2 || A > kMaxA) return set_err(HDCONV_EINVAL, "need L >= 1 and A in 2 .. %d", kMaxA);
+  if (flags & ~(HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
+    return set_err(HDCONV_EINVAL, "flags may hold HDCONV_PLAN_CENTERED and HDCONV_PLAN_HERMITIAN only");
+  if (flags & HDCONV_PLAN_HERMITIAN)
+    *M = centered_min_padding(herm_full(L), A);
+  else if (flags & HDCONV_PLAN_CENTERED)
+    *M = centered_min_padding(L, A);
+  else
+    *M = (int64_t)A * (L - 1) + 1;
+  return HDCONV_OK;
+}
+
+hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                      const hdconv_options* opt) {
   clear_err();
   if (!L || !M) {
@@ -1033,7 +1095,7 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
       T->timed_candidates = nt;
       T->tuned_ms = ms;
     }
-    return T;
+    return (hdconv_plan_t)T;
   }
   Plan* P = new (std::nothrow) Plan();
   if (!P) {
@@ -1096,6 +1158,7 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     if (P->method == HDCONV_METHOD_EXPLICIT) P->npad[d] = std::max<int64_t>(8, next_fft_size(M[d]));
   }
   int rc = build_dims(P, opt);
+  if (rc == HDCONV_OK) rc = size_workspace(P);
   if (rc != HDCONV_OK) {
     free_plan(P);
     return nullptr;
@@ -1120,14 +1183,14 @@ void* hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, int dims,
     return nullptr;
   }
   plan_traffic(P, &P->launches);
-  return P;
+  return (hdconv_plan_t)P;
 }
 
-void* hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype) {
+hdconv_plan_t hdconv_plan(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype) {
   return hdconv_plan_ex(L, M, A, B, dims, dtype, nullptr);
 }
 
-int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
+int hdconv_plan_info(hdconv_plan_t plan, hdconv_plan_info_t* out) {
   clear_err();
   if (!plan || !out) return set_err(HDCONV_EINVAL, "plan and out must not be NULL");
   const Plan* P = (const Plan*)plan;
@@ -1166,7 +1229,7 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
   }
   out->workspace_bytes = P->work_bytes;
   out->table_bytes = P->table_bytes;
-  out->compulsory_bytes = (double)(P->A + P->B) * ltot * 2.0 * tbytes_of(P->dtype);
+  out->compulsory_bytes = (double)(P->A + P->B) * ltot * (double)P->copies * 2.0 * tbytes_of(P->dtype);
   out->traffic_bytes = plan_traffic(P, &out->launches);
   out->tuner = P->tuner;
   out->tuned_candidates = P->tuned_candidates;
@@ -1175,7 +1238,7 @@ int hdconv_plan_info(const void* plan, hdconv_plan_info_t* out) {
   return HDCONV_OK;
 }
 
-int hdconv_execute(void* plan, const void* const* inputs, void* const* outputs, void* stream) {
+int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream) {
   clear_err();
   if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
   Plan* P = (Plan*)plan;
@@ -1220,7 +1283,7 @@ static void prof_release(Plan* P) {
   P->prof = Plan::Prof{};
 }
 
-int hdconv_profile_begin(void* plan, int max_executes) {
+int hdconv_profile_begin(hdconv_plan_t plan, int max_executes) {
   clear_err();
   if (!plan || max_executes < 1) return set_err(HDCONV_EINVAL, "need a plan and max_executes >= 1");
   Plan* P = (Plan*)plan;
@@ -1242,7 +1305,7 @@ int hdconv_profile_begin(void* plan, int max_executes) {
   return HDCONV_OK;
 }
 
-int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* count) {
+int hdconv_profile_end(hdconv_plan_t plan, hdconv_kernel_stat_t* out, int cap, int* count) {
   clear_err();
   if (!plan) return set_err(HDCONV_EINVAL, "plan is NULL");
   Plan* P = (Plan*)plan;
@@ -1273,7 +1336,7 @@ int hdconv_profile_end(void* plan, hdconv_kernel_stat_t* out, int cap, int* coun
   return HDCONV_OK;
 }
 
-void hdconv_destroy(void* plan) {
+void hdconv_destroy(hdconv_plan_t plan) {
   if (plan) prof_release((Plan*)plan);
   free_plan((Plan*)plan);
 }
@@ -1357,7 +1420,7 @@ static int list_candidates(const int64_t* L, const int64_t* M, int A, int dims, 
   return HDCONV_OK;
 }
 
-static int time_plan_ms(void* plan, int A, size_t bytes, int reps, double* ms) {
+static int time_plan_ms(hdconv_plan_t plan, int A, size_t bytes, int reps, double* ms) {
   void* buf[kMaxA + 1] = {nullptr, nullptr, nullptr, nullptr};
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1530,7 +1593,7 @@ int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims
   clear_err();
   if (!shape || !ms || reps < 1) return set_err(HDCONV_EINVAL, "need a shape, ms and reps >= 1");
   hdconv_options o = opts_from_shape(shape, dims);
-  void* plan = hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
+  hdconv_plan_t plan = hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
   if (!plan) return g_err_code;
   size_t bytes = 2 * (size_t)tbytes_of(dtype);
   for (int d = 0; d < dims; ++d) bytes *= (size_t)L[d];
@@ -1584,7 +1647,7 @@ int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, 
   out[11] = lg((double)launches);
   out[12] = lg(work);
   out[43] = lg((double)P->work_bytes + 1.0);
-  hdconv_destroy(P);
+  hdconv_destroy((hdconv_plan_t)P);
   return HDCONV_OK;
 }
 
@@ -1650,7 +1713,7 @@ static Plan* make_group_plan(int A, int B, int dtype, const DimPlan& dp, int64_t
   P->dp[0] = dp;
   P->batch_rows = rows;
   P->device = device;
-  if (alloc_tables(P) != HDCONV_OK || alloc_workspace(P) != HDCONV_OK) {
+  if (size_workspace(P) != HDCONV_OK || alloc_tables(P) != HDCONV_OK || alloc_workspace(P) != HDCONV_OK) {
     free_plan(P);
     return nullptr;
   }
@@ -1924,7 +1987,7 @@ static int tune_batch_groups(int A, int B, int dtype, int device, const hdconv_o
 
 extern "C" {
 
-void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
+hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
                           const hdconv_options* opt) {
   clear_err();
   if (!L || !M || count < 1) {
@@ -2053,10 +2116,10 @@ void* hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int
     free_batch(Bt);
     return nullptr;
   }
-  return Bt;
+  return (hdconv_batch_t)Bt;
 }
 
-int hdconv_execute_batched(void* batch, const void* const* inputs, void* const* outputs, void* stream) {
+int hdconv_execute_batched(hdconv_batch_t batch, const void* const* inputs, void* const* outputs, void* stream) {
   clear_err();
   if (!batch || !inputs || !outputs) return set_err(HDCONV_EINVAL, "batch, inputs and outputs must not be NULL");
   Batch* Bt = (Batch*)batch;
@@ -2073,7 +2136,7 @@ int hdconv_execute_batched(void* batch, const void* const* inputs, void* const* 
                                  : run_batched<double>(Bt, inputs, outputs, s);
 }
 
-int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups) {
+int hdconv_batch_info(hdconv_batch_t batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups) {
   clear_err();
   if (!batch) return set_err(HDCONV_EINVAL, "batch is NULL");
   const Batch* Bt = (const Batch*)batch;
@@ -2104,6 +2167,6 @@ int hdconv_batch_info(const void* batch, hdconv_dim_info_t* groups, int64_t* cou
   return HDCONV_OK;
 }
 
-void hdconv_batch_destroy(void* batch) { free_batch((Batch*)batch); }
+void hdconv_batch_destroy(hdconv_batch_t batch) { free_batch((Batch*)batch); }
 
 }  // extern "C"

@@ -46,41 +46,45 @@ __global__ void __launch_bounds__(512) k_outer_fwd(OuterFwdArgs<T> a) {
   const int g = threadIdx.x / S;
   const int64_t col = (int64_t)blockIdx.x * S + c;
   const bool valid = col < a.R;
-  const int64_t b = blockIdx.y;
   const int ai = blockIdx.z;
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
-  const cpx<T>* src = a.in[ai] + b * a.in_bstride + (valid ? col_offset(a.lay, col) : 0);
   const int64_t js = a.lay.jstride ? a.lay.jstride : R;
   const CtrShift cs = ctr_shift<P>(a.ctr, a.L, m);
   cpx<T>* lds = smem_as<T>();
   Xchg<T> xb{lds + c, S, 30, m * S};
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
 
-  cpx<T> x[P][E];
-#pragma unroll
-  for (int t = 0; t < P; ++t)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
-      x[t][e] = (valid && i >= 0 && i < a.L) ? src[i * js] : czero<T>();
-    }
-  __syncthreads();
-  for (int dr = 0; dr < a.D; ++dr) {
-    const int64_t r = a.r0 + dr;  // r < q
-    const uint32_t st = (uint32_t)r * (uint32_t)G;
-    cpx<T> w[1][E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
+  // planes (copies, outer levels) beyond the grid's y extent loop; every
+  // transform ends with a barrier after its last LDS read, so the next
+  // plane's exchanges cannot overtake it
+  for (int64_t b = blockIdx.y; b < a.nb; b += gridDim.y) {
+    const cpx<T>* src = a.in[ai] + b * a.in_bstride + (valid ? col_offset(a.lay, col) : 0);
+    cpx<T> x[P][E];
 #pragma unroll
     for (int t = 0; t < P; ++t)
-      a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
-                            [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
-    gfft_any<T, E, +1, 1, kCtOuter>(w, g, a.fd, tw, xb);
-    if (valid) {
-      cpx<T>* dst = a.out[ai] + ((b * a.D + dr) * m) * R + col;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[(int64_t)(g + G * e) * R] = w[0][e];
+      for (int e = 0; e < E; ++e) {
+        const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
+        x[t][e] = (valid && i >= 0 && i < a.L) ? src[i * js] : czero<T>();
+      }
+    __syncthreads();
+    for (int dr = 0; dr < a.D; ++dr) {
+      const int64_t r = a.r0 + dr;  // r < q
+      const uint32_t st = (uint32_t)r * (uint32_t)G;
+      cpx<T> w[1][E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[0][e] = czero<T>();
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+        a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
+                              [&](int e, cpx<T> z) { w[0][e] = w[0][e] + cmul(x[t][e], z); });
+      gfft_any<T, E, +1, 1, kCtOuter>(w, g, a.fd, tw, xb);
+      if (valid) {
+        cpx<T>* dst = a.out[ai] + ((b * a.D + dr) * m) * R + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[(int64_t)(g + G * e) * R] = w[0][e];
+      }
     }
   }
 }
@@ -93,7 +97,6 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
   const int g = threadIdx.x / S;
   const int64_t col = (int64_t)blockIdx.x * S + c;
   const bool valid = col < a.R;
-  const int64_t b = blockIdx.y;
   const int64_t R = a.R;
   const int64_t qm = (int64_t)a.q * m;
   const CtrShift cs = ctr_shift<P>(a.ctr, a.L, m);
@@ -102,35 +105,38 @@ __global__ void __launch_bounds__(512) k_outer_bwd(OuterBwdArgs<T> a) {
   const TwLds<T> tw = stage_table(a.fd, a.fft_tw, lds + xwords_cols(m, S, 1));
   __syncthreads();
 
-  cpx<T> acc[P][E];
-#pragma unroll
-  for (int t = 0; t < P; ++t)
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
-  for (int dr = 0; dr < a.D; ++dr) {
-    const int64_t r = a.r0 + dr;  // r < q
-    const uint32_t st = (uint32_t)r * (uint32_t)G;
-    const cpx<T>* src = a.y + ((b * a.D + dr) * m) * R + col;
-    cpx<T> y[1][E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) y[0][e] = valid ? src[(int64_t)(g + G * e) * R] : czero<T>();
-    gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
+  // planes beyond the grid's y extent loop (see k_outer_fwd)
+  for (int64_t b = blockIdx.y; b < a.nb; b += gridDim.y) {
+    cpx<T> acc[P][E];
 #pragma unroll
     for (int t = 0; t < P; ++t)
-      a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
-                            [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
-  }
-  if (!valid) return;
-  const int64_t coff = col_offset(a.lay, col), js = a.lay.jstride ? a.lay.jstride : R;
-  cpx<T>* dst = a.out + b * a.out_bstride + coff;
-  double* acc64 = a.acc ? a.acc + 2 * (b * a.out_bstride + coff) : nullptr;
 #pragma unroll
-  for (int t = 0; t < P; ++t)
+      for (int e = 0; e < E; ++e) acc[t][e] = czero<T>();
+    for (int dr = 0; dr < a.D; ++dr) {
+      const int64_t r = a.r0 + dr;  // r < q
+      const uint32_t st = (uint32_t)r * (uint32_t)G;
+      const cpx<T>* src = a.y + ((b * a.D + dr) * m) * R + col;
+      cpx<T> y[1][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
-      if (i >= 0 && i < a.L) acc_store(dst, acc64, a.acc_mode, i * js, acc[t][e], a.scale);
+      for (int e = 0; e < E; ++e) y[0][e] = valid ? src[(int64_t)(g + G * e) * R] : czero<T>();
+      gfft_any<T, E, -1, 1, kCtOuter>(y, g, a.fd, tw, xb);
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+        a.zqm.template run<E>(block_exp((uint32_t)r, t, cs.tneg, g, m, (uint32_t)qm), st,
+                              [&](int e, cpx<T> z) { acc[t][e] = acc[t][e] + cmulc(y[0][e], z); });
     }
+    if (!valid) continue;
+    const int64_t coff = col_offset(a.lay, col), js = a.lay.jstride ? a.lay.jstride : R;
+    cpx<T>* dst = a.out + b * a.out_bstride + coff;
+    double* acc64 = a.acc ? a.acc + 2 * (b * a.out_bstride + coff) : nullptr;
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t i = (int64_t)t * m + g + G * e - cs.sh;
+        if (i >= 0 && i < a.L) acc_store(dst, acc64, a.acc_mode, i * js, acc[t][e], a.scale);
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -175,8 +181,8 @@ __global__ void __launch_bounds__(256) k_box_copy(BoxCopyArgs<T> a) {
 template <typename T>
 hipError_t launch_outer_fwd(const OuterFwdArgs<T>& a, int E, int P, int A, hipStream_t s) {
   const int nt = a.S * a.fd.G;
-  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb > 65535) return HD_BAD;
-  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)a.nb, A), block(nt);
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb < 1) return HD_BAD;
+  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)std::min<int64_t>(a.nb, 65535), A), block(nt);
   const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
 #define O1(EE, PP) \
   if (E == EE && P == PP) return go(k_outer_fwd<T, EE, PP>, grid, block, lds, s, a);
@@ -188,8 +194,8 @@ hipError_t launch_outer_fwd(const OuterFwdArgs<T>& a, int E, int P, int A, hipSt
 template <typename T>
 hipError_t launch_outer_bwd(const OuterBwdArgs<T>& a, int E, int P, hipStream_t s) {
   const int nt = a.S * a.fd.G;
-  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb > 65535) return HD_BAD;
-  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)a.nb), block(nt);
+  if (nt > 512 || !fft_fits(a.fd, E) || a.m != a.fd.N || a.nb < 1) return HD_BAD;
+  dim3 grid((unsigned)((a.R + a.S - 1) / a.S), (unsigned)std::min<int64_t>(a.nb, 65535)), block(nt);
   const size_t lds = lds_outer(a.m, a.S, tw_words(a.fd), sizeof(T));
 #define O1(EE, PP) \
   if (E == EE && P == PP) return go(k_outer_bwd<T, EE, PP>, grid, block, lds, s, a);

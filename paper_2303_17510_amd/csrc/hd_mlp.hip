@@ -263,7 +263,7 @@ using namespace hd;
 
 extern "C" {
 
-void* hdconv_model_create(int hidden, uint64_t seed) {
+hdconv_model_t hdconv_model_create(int hidden, uint64_t seed) {
   if (hidden < 1 || hidden > 1024) return nullptr;
   Mlp* M = new (std::nothrow) Mlp();
   if (!M) return nullptr;
@@ -294,13 +294,13 @@ void* hdconv_model_create(int hidden, uint64_t seed) {
             hipMemcpy(M->d_p, p.data(), o * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemset(M->d_m, 0, o * sizeof(float)) == hipSuccess && hipMemset(M->d_v, 0, o * sizeof(float)) == hipSuccess;
   if (!ok) {
-    hdconv_model_destroy(M);
+    hdconv_model_destroy((hdconv_model_t)M);
     return nullptr;
   }
-  return M;
+  return (hdconv_model_t)M;
 }
 
-void hdconv_model_destroy(void* model) {
+void hdconv_model_destroy(hdconv_model_t model) {
   if (!model) return;
   Mlp* M = (Mlp*)model;
   (void)hipDeviceSynchronize();
@@ -309,7 +309,7 @@ void hdconv_model_destroy(void* model) {
   delete M;
 }
 
-int hdconv_model_params(void* model, float* params, int cap, int* n) {
+int hdconv_model_params(hdconv_model_t model, float* params, int cap, int* n) {
   if (!model) return HDCONV_EINVAL;
   const Mlp& M = *(const Mlp*)model;
   const int tot = M.nnet + (int)M.norm.size();
@@ -321,7 +321,7 @@ int hdconv_model_params(void* model, float* params, int cap, int* n) {
   return HDCONV_OK;
 }
 
-int hdconv_model_load(void* model, const float* params, int n) {
+int hdconv_model_load(hdconv_model_t model, const float* params, int n) {
   if (!model || !params) return HDCONV_EINVAL;
   Mlp& M = *(Mlp*)model;
   if (n != M.nnet + (int)M.norm.size()) return HDCONV_EINVAL;
@@ -333,11 +333,11 @@ int hdconv_model_load(void* model, const float* params, int n) {
   return HDCONV_OK;
 }
 
-int hdconv_model_predict(void* model, const float* X, int64_t n, float* out) {
+int hdconv_model_predict(hdconv_model_t model, const float* X, int64_t n, float* out) {
   return mlp_predict_host(model, X, n, out);
 }
 
-int hdconv_model_grad(void* model, const float* X, const float* y, int64_t n, float* grad, float* loss) {
+int hdconv_model_grad(hdconv_model_t model, const float* X, const float* y, int64_t n, float* grad, float* loss) {
   if (!model || !X || !y || n < 1) return HDCONV_EINVAL;
   Mlp& M = *(Mlp*)model;
   hipStream_t s = nullptr;
@@ -368,7 +368,7 @@ int hdconv_model_grad(void* model, const float* X, const float* y, int64_t n, fl
   return e == hipSuccess ? HDCONV_OK : HDCONV_EDEVICE;
 }
 
-int hdconv_model_train(void* model, const float* X, const float* y, int64_t n, int epochs, int batch, float lr,
+int hdconv_model_train(hdconv_model_t model, const float* X, const float* y, int64_t n, int epochs, int batch, float lr,
                        uint64_t seed, float* final_loss) {
   if (!model || !X || !y || n < 2 || epochs < 1 || batch < 1 || !(lr > 0)) return HDCONV_EINVAL;
   Mlp& M = *(Mlp*)model;

@@ -49,19 +49,35 @@ def geometry(L: int, M: int, m: int, p_min: int = 0, force_inner: bool = False) 
             "variant": _L.VARIANT_NAMES[out.variant]}
 
 
+def min_padding(L: int, A: int = 2, centered: bool = False, hermitian: bool = False) -> int:
+    """Least M the library accepts for one dimension of extent L with A
+    factors per product: A(L-1)+1, or the centered / Hermitian minimum."""
+    flags = _L.PLAN_HERMITIAN if hermitian else (_L.PLAN_CENTERED if centered else 0)
+    out = ctypes.c_int64()
+    _L.check(_L.lib().hdconv_min_padding(int(L), int(A), flags, ctypes.byref(out)))
+    return int(out.value)
+
+
 def centered_min_padding(L: int, A: int = 2) -> int:
-    """Least M of a centered dimension (indices -H .. L-1-H, H = L // 2):
-    the A-fold index sums span -A H .. A(L-1-H), and no output index may meet
-    another sum congruent to it modulo the padded length."""
-    H = L // 2
-    P = L - 1 - H
-    return max(A * P + H, P + A * H) + 1
+    """Least M of a centered dimension (indices -H .. L-1-H, H = L // 2)."""
+    return min_padding(L, A, centered=True)
 
 
 def hermitian_min_padding(L: int, A: int = 2) -> int:
-    """Least M of a Hermitian dimension of nominal length L: the stored
-    ceil(L/2) entries stand for the centered length 2 ceil(L/2) - 1."""
-    return centered_min_padding(2 * ((L + 1) // 2) - 1, A)
+    """Least M of a Hermitian dimension of nominal length L."""
+    return min_padding(L, A, hermitian=True)
+
+
+def geometry_centered(L: int, M: int, m: int, p_min: int = 0, force_inner: bool = False,
+                      hermitian: bool = False) -> dict:
+    """The library's centered (or Hermitian) geometry for one dimension and m."""
+    out = _L.DimInfo()
+    flags = _L.PLAN_HERMITIAN if hermitian else _L.PLAN_CENTERED
+    _L.check(_L.lib().hdconv_geometry_ex(int(L), int(M), int(m), int(p_min), int(bool(force_inner)), flags,
+                                          ctypes.byref(out)))
+    return {"L": out.L, "M": out.M, "m": out.m, "p": out.p, "n": out.n, "q": out.q,
+            "variant": _L.VARIANT_NAMES[out.variant], "centered": out.centered,
+            "span": int(_L.lib().hdconv_centered_span(int(out.L), int(m)))}
 
 
 class Plan:

@@ -61,3 +61,12 @@ def batched_lengths(count: int = 4096, lo_log2: float = 6.0, span_log2: float = 
     rng = np.random.Generator(np.random.PCG64(seed))
     u = rng.random(int(count))
     return np.rint(2.0 ** (lo_log2 + span_log2 * u)).astype(np.int64)
+
+
+def batched_inputs(Ls, A: int = 2, config_id: int = 2, dtype=np.complex128):
+    """The A inputs of a batch of 1D convolutions of lengths ``Ls``, each
+    drawn as one unit-disk array of sum(Ls) entries (seed of input ``a``:
+    ``seed_for(config_id, a)``); convolution i uses the slice at offset
+    sum(Ls[:i]).  ``dtype`` complex64 rounds the FP64 draws."""
+    tot = int(np.sum(np.asarray(Ls, dtype=np.int64)))
+    return [unit_disk((tot,), seed_for(config_id, a)).astype(dtype) for a in range(A)]

@@ -53,10 +53,70 @@ def test_inner_loop_rules():
         assert (r["p"], r["n"], r["q"]) == (c["p"], c["n"], c["q"]), c
         assert r["variant"] == "multipass"
     ce = g["centered_example"]
-    # centered rule (Sec. 6.2): p even, n = ceil(2M/(p m)), q = n p / 2
-    p = 2 * math.ceil(ce["L"] / (2 * ce["m"]))
-    n = math.ceil(2 * ce["M"] / (p * ce["m"]))
-    assert (p, n, n * p // 2) == (ce["p"], ce["n"], ce["q"])
+    # the library's centered geometry (hdconv_geometry_ex): the paper's p
+    # counts the m-point blocks the signed indices span; the column DFT folds
+    # the negative blocks onto the non-negative ones, so it has p/2 points,
+    # and n = ceil(M/((p/2) m)) = ceil(2M/(p m)), q = n p/2 (Sec. 6.2, 7.2)
+    from paper_2303_17510_amd.hdconv import geometry_centered
+    r = geometry_centered(ce["L"], ce["M"], ce["m"])
+    assert r["span"] == ce["p"]
+    assert (2 * r["p"], r["n"], r["q"]) == (ce["p"], ce["n"], ce["q"])
+    assert r["variant"] == "multipass" and r["centered"] == 1
+
+
+def _brute_min_padding(L, A, centered):
+    # least M such that no A-fold index sum other than an output index c is
+    # congruent to c modulo M (plain indices 0 .. L-1, outputs 0 .. L-1;
+    # centered -H .. L-1-H for both)
+    H = L // 2 if centered else 0
+    lo, hi = -A * H, A * (L - 1 - H)
+    outs = range(-H, L - H)
+    M = 1
+    while True:
+        if all(s == c or (s - c) % M != 0 for c in outs for s in range(lo, hi + 1)):
+            return M
+        M += 1
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 7, 8, 16, 31])
+@pytest.mark.parametrize("A", [2, 3])
+def test_min_padding_matches_brute_force(L, A):
+    from paper_2303_17510_amd.hdconv import min_padding
+    assert min_padding(L, A) == _brute_min_padding(L, A, False) == A * (L - 1) + 1
+    assert min_padding(L, A, centered=True) == _brute_min_padding(L, A, True)
+    # a Hermitian half of nominal length L stands for the centered length 2 ceil(L/2) - 1
+    Lc = 2 * ((L + 1) // 2) - 1
+    assert min_padding(L, A, hermitian=True) == _brute_min_padding(Lc, A, True)
+
+
+def test_min_padding_paper_values():
+    from paper_2303_17510_amd.hdconv import min_padding
+    # centered and Hermitian benchmarks use M = 3L/2 (Sec. 7): the centered
+    # minimum for even L and two factors
+    for L in (2, 64, 2048, 1 << 20):
+        assert min_padding(L, 2, centered=True) == 3 * L // 2
+        assert min_padding(L, 2, hermitian=True) <= 3 * L // 2
+    with pytest.raises(_lib.HdconvError):
+        min_padding(0, 2)
+    with pytest.raises(_lib.HdconvError):
+        min_padding(10, 4)
+
+
+def test_workspace_cap(monkeypatch):
+    # the cap is checked on the host before any device call: an inner-form
+    # plan needs work rows, a whole-row plan none
+    with Plan((1 << 20,), (1 << 21,), host_only=True) as p:
+        need = p.info()["workspace_bytes"]
+    assert need > 0
+    monkeypatch.setenv("HDCONV_WORKSPACE_CAP", str(need - 1))
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((1 << 20,), (1 << 21,))
+    assert ei.value.code == _lib.ENOMEM and "HDCONV_WORKSPACE_CAP" in str(ei.value)
+    with pytest.raises(_lib.HdconvError) as ei:
+        Plan((1 << 20,), (1 << 21,), host_only=True)
+    assert ei.value.code == _lib.ENOMEM
+    monkeypatch.setenv("HDCONV_WORKSPACE_CAP", str(need))
+    Plan((1 << 20,), (1 << 21,), host_only=True).close()
 
 
 @pytest.mark.parametrize("L", [1, 2, 3, 7, 100, 1023, 1024, 1025, 4096, 100000])

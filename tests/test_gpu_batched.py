@@ -141,3 +141,33 @@ def test_batched_tuned_per_bucket(gpu):
                                                                                    t_tuned, worst))
     assert worst <= TOL["c64"]
     assert t_tuned <= 1.15 * t_heur
+
+
+@pytest.mark.parametrize("tuner", ["heuristic", "exhaustive"])
+def test_batched_benchmark_workload(gpu, tuner):
+    # the benchmark's batch itself: 4096 complex64 convolutions, L
+    # log-uniform in [64, 65536] from its seed, M = 2L, inputs from the
+    # benchmark's generator; every convolution against the oracle
+    import torch
+    Ls = [int(v) for v in synth.batched_lengths()]
+    assert len(Ls) == 4096
+    xs = synth.batched_inputs(Ls, 2, 2, dtype=np.complex64)
+    big = [torch.from_numpy(x).cuda() for x in xs]
+    out_big = torch.full_like(big[0], float("nan"))
+    offs = np.concatenate([[0], np.cumsum(Ls)])
+    ins = [[big[a][offs[i]:offs[i + 1]] for a in range(2)] for i in range(len(Ls))]
+    outs = [out_big[offs[i]:offs[i + 1]] for i in range(len(Ls))]
+    with BatchPlan(Ls, dtype="c64", tuner=tuner) as bp:
+        say("groups", [(g["variant"], g["m"], g["p"], g["q"], g["count"]) for g in bp.groups()])
+        bound = bp.bind(ins, outs)
+        for _ in range(3):   # eager, capture, replay: the bench times replays
+            bound.execute()
+        torch.cuda.synchronize()
+    o = out_big.cpu().numpy()
+    worst = 0.0
+    for i in range(len(Ls)):
+        a, b = offs[i], offs[i + 1]
+        ref = oracle.conv_explicit([synth.as_oracle(xs[0][a:b]), synth.as_oracle(xs[1][a:b])])
+        worst = max(worst, oracle.rel_l2(o[a:b], ref))
+    say("4096-convolution batch (%s): worst rel L2 %.3e" % (tuner, worst))
+    assert worst <= TOL["c64"]
