@@ -240,6 +240,9 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       if (contiguous && fv == VAR_OUTER) return set_err(HDCONV_EINVAL, "dim %d: outer variant on the innermost dimension", d);
       if (!contiguous && fv != VAR_OUTER) return set_err(HDCONV_EUNSUPPORTED, "dim %d: outer dimensions use the outer variant", d);
       int64_t m = fm ? fm : next_fft_size(fv == VAR_MULTI ? cdiv(Le, std::max<int64_t>(fp, 4)) : Le);
+      // a forced inner form without a forced m: rows of at most 4096 points
+      // (the row pass's best size), the column count then follows from L
+      if (!fm && fv == VAR_MULTI && m > 4096) m = 4096;
       Geometry g = geometry_c(Le, Me, m, fp, fv == VAR_MULTI, ctr);
       if (g.inner && fv != VAR_MULTI)
         return set_err(HDCONV_EINVAL, "dim %d: m=%lld gives p=%lld > 2, which needs the multipass variant", d,
@@ -551,12 +554,22 @@ static int size_workspace(Plan* P) {
   return HDCONV_OK;
 }
 
+// With HDCONV_POISON_WORKSPACE set in the environment every new workspace is
+// filled with all-ones bytes (a NaN in FP32 and FP64), so a kernel that reads
+// a workspace word no earlier kernel of the execute wrote shows up as NaN
+// outputs.  A debugging aid; off by default.
 static int alloc_workspace(Plan* P) {
   const size_t total = P->work_bytes;
   if (P->host_only || total == 0) return HDCONV_OK;
   hipError_t e = hipMalloc((void**)&P->work_mem, total);
   if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(workspace, %zu): %s", total, hipGetErrorString(e));
   carve_workspace(P, P->work_mem);
+  const char* poison = getenv("HDCONV_POISON_WORKSPACE");
+  if (poison && poison[0] && poison[0] != '0') {
+    e = hipMemset(P->work_mem, 0xff, total);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_err(e, "hipMemset(workspace poison)");
+  }
   return HDCONV_OK;
 }
 
