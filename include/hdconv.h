@@ -86,7 +86,9 @@ enum {
   HDCONV_PLAN_HOST_ONLY = 1, /* plan geometry only: no device memory, cannot execute */
   HDCONV_BATCH_NO_GRAPH = 2, /* batched plans: launch eagerly on every execute      */
   HDCONV_PLAN_CENTERED = 4,  /* centered convolution (see below); plans and batches */
-  HDCONV_PLAN_HERMITIAN = 8  /* Hermitian convolution (see below); plans, 1D batches    */
+  HDCONV_PLAN_HERMITIAN = 8, /* Hermitian convolution (see below); plans, 1D batches    */
+  HDCONV_PLAN_NO_WORKSPACE = 16 /* no workspace of its own: runs through
+                                   hdconv_execute_noalloc only (see there)   */
 };
 
 /* Centered convolutions (the paper's section on centered convolutions in one
@@ -240,6 +242,23 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
  * inputs are not modified unless aliased by the output.  Returns the launch
  * status; no synchronisation is done. */
 int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream);
+
+/* For callers that cannot allocate device memory while they run: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Runs `plan` exactly like hdconv_execute (same kernels, same arguments and
+ * rules), but its workspace is the library's static device scratch area of
+ * HDCONV_SCRATCH_BYTES instead of the plan's own; the call allocates and
+ * frees nothing.  Create the plan beforehand (hdconv_plan_ex allocates its
+ * twiddle tables; with HDCONV_PLAN_NO_WORKSPACE it allocates no workspace).
+ * A plan whose workspace (hdconv_plan_info: workspace_bytes) exceeds
+ * HDCONV_SCRATCH_BYTES is rejected with HDCONV_EUNSUPPORTED before anything
+ * runs.  Each GPU the library runs on holds one scratch area, located on the
+ * first call on that device and kept until the process ends; every call on a
+ * device shares it and nothing in it is assumed to start at zero.  Calls that
+ * overlap in time on one device (different streams or host threads) race on
+ * it: serialise them. */
+#define HDCONV_SCRATCH_BYTES ((size_t)64 << 20)
+int hdconv_execute_noalloc(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream);
 
 /* Plan geometry and sizes. */
 int hdconv_plan_info(hdconv_plan_t plan, hdconv_plan_info_t* out);

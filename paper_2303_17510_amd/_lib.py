@@ -21,6 +21,8 @@ PLAN_HOST_ONLY = 1
 BATCH_NO_GRAPH = 2
 PLAN_CENTERED = 4
 PLAN_HERMITIAN = 8
+PLAN_NO_WORKSPACE = 16
+SCRATCH_BYTES = 64 << 20  # static scratch of hdconv_execute_noalloc
 MULT_PRODUCT, MULT_QUADRATIC = 0, 1
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
 NFEATURES = 44
@@ -72,6 +74,8 @@ SIGNATURES = {
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]),
     "hdconv_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "hdconv_execute_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "hdconv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hdconv_destroy": (None, [ctypes.c_void_p]),
     "hdconv_geometry": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(DimInfo)]),

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -560,7 +561,7 @@ static int size_workspace(Plan* P) {
 // outputs.  A debugging aid; off by default.
 static int alloc_workspace(Plan* P) {
   const size_t total = P->work_bytes;
-  if (P->host_only || total == 0) return HDCONV_OK;
+  if (P->host_only || total == 0 || (P->flags & HDCONV_PLAN_NO_WORKSPACE)) return HDCONV_OK;
   hipError_t e = hipMalloc((void**)&P->work_mem, total);
   if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "hipMalloc(workspace, %zu): %s", total, hipGetErrorString(e));
   carve_workspace(P, P->work_mem);
@@ -572,6 +573,34 @@ static int alloc_workspace(Plan* P) {
   }
   return HDCONV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Static device scratch of hdconv_execute_noalloc.  In host code the array's
+// name only stands for the variable; its device address (one per GPU) comes
+// from hipGetSymbolAddress, called once per device with that device current.
+static __device__ __align__(256) char hd_scratch[HDCONV_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch area on the current device `dev`.
+int scratch_of(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_err(HDCONV_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(hd_scratch));
+    if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_err(HDCONV_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HDCONV_OK;
+}
+}  // namespace
 
 static void free_plan(Plan* P) {
   if (!P) return;
@@ -1251,11 +1280,9 @@ int hdconv_plan_info(hdconv_plan_t plan, hdconv_plan_info_t* out) {
   return HDCONV_OK;
 }
 
-int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream) {
-  clear_err();
-  if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
-  Plan* P = (Plan*)plan;
-  if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
+// Argument checks and the launches of one execute, with the workspace parts
+// pointing wherever the caller carved them.
+static int execute_plan(Plan* P, const void* const* inputs, void* const* outputs, void* stream) {
   // span of one array: (C-1) dist + one copy's extent
   const size_t bytes =
       2 * (size_t)tbytes_of(P->dtype) * ((size_t)(P->copies - 1) * (size_t)P->dist + (size_t)P->span);
@@ -1288,6 +1315,41 @@ int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* o
   int rc = P->dtype == HDCONV_C64 ? run_plan<float>(P, inputs, outputs, s)
                                   : run_plan<double>(P, inputs, outputs, s);
   if (P->prof.on && P->prof.used < P->prof.max_exec) P->prof.used++;
+  return rc;
+}
+
+int hdconv_execute(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream) {
+  clear_err();
+  if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
+  Plan* P = (Plan*)plan;
+  if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
+  if (P->work_bytes && !P->work_mem)
+    return set_err(HDCONV_EINVAL, "plan has no workspace (HDCONV_PLAN_NO_WORKSPACE): run it with hdconv_execute_noalloc");
+  return execute_plan(P, inputs, outputs, stream);
+}
+
+int hdconv_execute_noalloc(hdconv_plan_t plan, const void* const* inputs, void* const* outputs, void* stream) {
+  clear_err();
+  if (!plan || !inputs || !outputs) return set_err(HDCONV_EINVAL, "plan, inputs and outputs must not be NULL");
+  Plan* P = (Plan*)plan;
+  if (P->host_only) return set_err(HDCONV_EINVAL, "plan was created with HDCONV_PLAN_HOST_ONLY");
+  if (P->work_bytes > HDCONV_SCRATCH_BYTES)
+    return set_err(HDCONV_EUNSUPPORTED, "workspace of %zu bytes exceeds the %zu-byte scratch of hdconv_execute_noalloc",
+                   P->work_bytes, (size_t)HDCONV_SCRATCH_BYTES);
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  if (cur != P->device) return set_err(HDCONV_EINVAL, "plan belongs to device %d, current device is %d", P->device, cur);
+  char* base = nullptr;
+  if (P->work_bytes) {
+    int rc = scratch_of(cur, &base);
+    if (rc != HDCONV_OK) return rc;
+  }
+  // the same launches with the workspace parts carved from the scratch, then
+  // the plan's own workspace (or none) again
+  carve_workspace(P, base);
+  const int rc = execute_plan(P, inputs, outputs, stream);
+  carve_workspace(P, P->work_mem);
   return rc;
 }
 

@@ -99,6 +99,8 @@ class Plan:
     indices of a Hermitian centered array (``f_{-c} = conj f_c``; 2D/3D:
     ``F(k, -c) = conj F(-k, c)`` with centered outer dimensions of odd
     extent), and so does the output; ``M`` defaults to the minimum padding.
+    ``no_workspace``: the plan allocates no workspace and runs only through
+    :meth:`execute_noalloc` (the library's static device scratch).
     ``mult="quadratic"`` with real coefficients ``coef`` of shape
     ``(B, A, A)``: B outputs, output b = sum_{i <= j} coef[b][i][j] F_i F_j
     pointwise in transform space (entries below the diagonal unused); the
@@ -110,7 +112,8 @@ class Plan:
                  host_only: bool = False, E_m=None, E_p=None, S=None, rows_per_block=None,
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
                  db_path: str | None = None, centered: bool = False, hermitian: bool = False,
-                 copies: int = 1, dist: int = 0, strides=None, mult: str = "product", coef=None):
+                 copies: int = 1, dist: int = 0, strides=None, mult: str = "product", coef=None,
+                 no_workspace: bool = False):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if mult not in ("product", "quadratic"):
@@ -126,7 +129,7 @@ class Plan:
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.method = _METHODS[method]
         opt.flags = ((_L.PLAN_HOST_ONLY if host_only else 0) | (_L.PLAN_CENTERED if centered else 0) |
-                     (_L.PLAN_HERMITIAN if hermitian else 0))
+                     (_L.PLAN_HERMITIAN if hermitian else 0) | (_L.PLAN_NO_WORKSPACE if no_workspace else 0))
         self.centered, self.hermitian = bool(centered), bool(hermitian)
         # shape of the arrays passed in and out
         self.io_shape = L[:-1] + ((L[-1] + 1) // 2,) if hermitian else L
@@ -226,6 +229,15 @@ class Plan:
     def execute(self, inputs, out, stream=None):
         """Run asynchronously on ``stream`` (default: torch's current stream).
         ``out``: one tensor, or a sequence of B tensors (B > 1)."""
+        return self._run(_L.lib().hdconv_execute, inputs, out, stream)
+
+    def execute_noalloc(self, inputs, out, stream=None):
+        """As :meth:`execute`, with the library's static device scratch as
+        the workspace (hdconv_execute_noalloc: nothing is allocated; calls
+        that overlap on one device race on the scratch)."""
+        return self._run(_L.lib().hdconv_execute_noalloc, inputs, out, stream)
+
+    def _run(self, fn, inputs, out, stream):
         torch = _torch()
         if len(inputs) != self.A:
             raise ValueError("expected %d inputs" % self.A)
@@ -240,7 +252,7 @@ class Plan:
             stream = torch.cuda.current_stream(outs_t[0].device)
         ins = (ctypes.c_void_p * self.A)(*[t.data_ptr() for t in inputs])
         outs = (ctypes.c_void_p * self.B)(*[t.data_ptr() for t in outs_t])
-        _L.check(_L.lib().hdconv_execute(self._h, ins, outs, ctypes.c_void_p(stream.cuda_stream)))
+        _L.check(fn(self._h, ins, outs, ctypes.c_void_p(stream.cuda_stream)))
         return out
 
     def profile_begin(self, max_executes: int):
