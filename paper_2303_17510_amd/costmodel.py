@@ -32,9 +32,48 @@ SEED_TRAIN = 17510500
 SEED_HELDOUT = 17510501
 
 
+SHAPE_FIELDS = ("variant", "m", "p", "q", "E_m", "E_p", "S", "rows_per_block")
+
+
+def _shape_rows(shape):
+    """Per-dimension shape fields as a 3 x 8 integer array (unused dimensions 0)."""
+    out = np.zeros((3, len(SHAPE_FIELDS)), dtype=np.int64)
+    for d, s in enumerate(shape):
+        for k, f in enumerate(SHAPE_FIELDS):
+            v = s[f]
+            if f == "variant":
+                v = {"fused": 1, "multipass": 2, "outer": 3}.get(v, v)
+            out[d, k] = int(v)
+    return out
+
+
+def _shape_of(rows, dims):
+    names = {1: "fused", 2: "multipass", 3: "outer"}
+    return [{f: (names[int(rows[d, k])] if f == "variant" else int(rows[d, k])) for k, f in enumerate(SHAPE_FIELDS)}
+            for d in range(dims)]
+
+
+def refeature(data, dtype="c64"):
+    """Recompute the feature rows of stored candidates with this library's
+    feature function (host-only plans): timings collected once stay usable
+    when the feature set changes."""
+    X = np.zeros((len(data["y"]), tune.NF), dtype=np.float32)
+    for i in range(len(data["y"])):
+        dims = int(data["dims"][i])
+        L = [int(v) for v in data["L"][i][:dims]]
+        M = [int(v) for v in data["M"][i][:dims]]
+        X[i] = tune.features(L, M, _shape_of(data["shape"][i], dims), A=int(data["A"][i]), dtype=dtype)
+    out = dict(data)
+    out["X"] = X
+    return out
+
+
 def collect(geoms, reps=3, dtype="c64", log=None, time_budget_s=None, ids=None):
-    """Rows of every candidate of every geometry: dict of numpy arrays."""
+    """Rows of every candidate of every geometry: dict of numpy arrays (the
+    features, log ms, geometry id, varied dimension, dimensions, and the
+    geometry and per-dimension shape each row was timed with)."""
     X, y, gid, var, dims_l = [], [], [], [], []
+    Ls, Ms, As, shp = [], [], [], []
     t0 = time.time()
     for i, g in enumerate(geoms):
         if time_budget_s and time.time() - t0 > time_budget_s:
@@ -59,13 +98,19 @@ def collect(geoms, reps=3, dtype="c64", log=None, time_budget_s=None, ids=None):
             gid.append(gi)
             var.append(v)
             dims_l.append(len(g["L"]))
+            Ls.append(list(g["L"]) + [1] * (3 - len(g["L"])))
+            Ms.append(list(g["M"]) + [1] * (3 - len(g["M"])))
+            As.append(g["A"])
+            shp.append(_shape_rows(shape))
             n_ok += 1
         if log and (i % 20 == 0):
             log("geometry %d/%d L=%s A=%d: %d candidates timed, %.0f s" % (i, len(geoms), g["L"], g["A"], n_ok,
                                                                           time.time() - t0))
     return {"X": np.array(X, dtype=np.float32).reshape(-1, tune.NF), "y": np.array(y, dtype=np.float32),
             "gid": np.array(gid, dtype=np.int64), "varied": np.array(var, dtype=np.int64),
-            "dims": np.array(dims_l, dtype=np.int64)}
+            "dims": np.array(dims_l, dtype=np.int64), "L": np.array(Ls, dtype=np.int64).reshape(-1, 3),
+            "M": np.array(Ms, dtype=np.int64).reshape(-1, 3), "A": np.array(As, dtype=np.int64),
+            "shape": np.array(shp, dtype=np.int64).reshape(-1, 3, len(SHAPE_FIELDS))}
 
 
 def save(data, path):
@@ -125,6 +170,9 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=300)
     t.add_argument("--seed", type=int, default=0)
+    r = sub.add_parser("refeature", help="recompute the features of stored timings (host only)")
+    r.add_argument("--data", required=True)
+    r.add_argument("--out", required=True)
     e = sub.add_parser("evaluate")
     e.add_argument("--model", required=True)
     e.add_argument("--data", nargs="+", required=True)
@@ -142,6 +190,10 @@ def main(argv=None):
         d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None, ids=sel)
         save(d, a.out)
         log("saved %d rows from %d geometries to %s" % (len(d["y"]), len(np.unique(d["gid"])), a.out))
+    elif a.cmd == "refeature":
+        d = refeature({k: v for k, v in np.load(a.data, allow_pickle=False).items()})
+        save(d, a.out)
+        log("recomputed %d feature rows into %s" % (len(d["y"]), a.out))
     elif a.cmd == "train":
         d = load(a.data)
         t0 = time.time()

@@ -71,6 +71,7 @@ struct Plan {
   int64_t npad[3] = {0, 0, 0};
   DimPlan dp[3];
   int device = -1;
+  int cus = 1;  // compute units of the device (sizes persistent grids)
   bool host_only = false;
   // device memory
   char* table_mem = nullptr;
@@ -231,6 +232,17 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
           return set_err(HDCONV_EUNSUPPORTED, "explicit padding, dim %d (N'=%lld): %s", d, (long long)Le, why.c_str());
       } else if (!choose_dim(Le, Me, kernel_inputs(P), tb, contiguous, lines_of(P, d), &dp, &why, ctr, P->dims)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
+      }
+      if (opt && (opt->E_m[d] || opt->E_p[d] || opt->S[d] || opt->rows_per_block[d] || opt->twiddles[d])) {
+        // the chosen geometry with the caller's launch shape
+        if (opt->E_m[d]) dp.E_m = opt->E_m[d];
+        if (opt->E_p[d]) dp.E_p = opt->E_p[d];
+        if (opt->S[d] || opt->E_m[d] || opt->E_p[d]) dp.S = opt->S[d];
+        if (opt->rows_per_block[d] || opt->E_m[d]) dp.rows_per_block = opt->rows_per_block[d];
+        if (opt->twiddles[d]) dp.tw_pref = opt->twiddles[d];
+        if (!finish_dim(&dp, kernel_inputs(P), tb, &why))
+          return set_err(HDCONV_EUNSUPPORTED, "dim %d (m=%lld, p=%lld, q=%lld): %s", d, (long long)dp.m,
+                         (long long)dp.p, (long long)dp.q, why.c_str());
       }
       dp.herm = hd;
     } else {
@@ -639,6 +651,26 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
   // words between consecutive rows of the inputs and the output (default: dense)
   const int64_t rs = row_stride ? row_stride : stored_extent(dp);
   hipError_t e;
+  if (dp.variant == VAR_FUSED && !tasks && nsh == 1 && !P->quad && dp.p <= 2 && !dp.ctr && !dp.herm && in &&
+      rows_lean_supported((int)dp.m, dp.E_m, shares[0].n, (int)dp.q, (int)sizeof(T))) {
+    // many rows of one or two blocks: the lean row kernel (the same arithmetic)
+    const Share& sh = shares[0];
+    LeanRowArgs<T> a{};
+    for (int i = 0; i < sh.n; ++i) a.in[i] = in[sh.idx[i]];
+    a.out = out;
+    a.in_stride = a.out_stride = rs;
+    a.nrows = nrows;
+    a.L = (uint32_t)dp.L;
+    a.q = (int)dp.q;
+    a.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+    a.fd = dp.fd_m;
+    a.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+    a.zqm = rtab<T>(P, d);
+    ProfScope ps(P, s, "rows_lean", (double)nrows * (sh.n + 1) * (double)dp.L * 2.0 * sizeof(T));
+    e = launch_rows_lean<T>(a, dp.E_m, sh.n, P->cus, s);
+    if (e != hipSuccess) return hip_err(e, "rows_lean launch");
+    return HDCONV_OK;
+  }
   if (dp.variant == VAR_FUSED) {
     for (int k = 0; k < nsh; ++k) {
       const Share& sh = shares[k];
@@ -845,7 +877,33 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
     const DimPlan& dp = P->dp[d];
     int64_t rest = 1;
     for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
-    for (int g0 = 0; g0 < A; g0 += kMaxA) {  // three inputs per launch
+    // the lean outer kernel for ordinary dimensions of one block over dense planes
+    const bool dense = d > 0 || (user.jstride == 0 && user.cgrp == 0);
+    const bool lean = dense && !dp.ctr && dp.p <= 2 && outer_lean_supported((int)dp.m, dp.E_m, dp.S, (int)dp.q, (int)sizeof(T));
+    for (int g0 = 0; g0 < A && lean; g0 += kMaxA) {
+      const int na = std::min(kMaxA, A - g0);
+      OuterLeanArgs<T> o{};
+      for (int a = 0; a < na; ++a) {
+        o.in[a] = cur[g0 + a];
+        o.out[a] = (cpx<T>*)P->lvl[d][g0 + a];
+      }
+      o.na = na;
+      o.nb = nb;
+      o.in_bstride = d == 0 ? dist : Le[d] * rest;
+      o.R = rest;
+      o.L = (uint32_t)Le[d];
+      o.q = (int)dp.q;
+      o.fd = dp.fd_m;
+      o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+      o.zqm = rtab<T>(P, d);
+      {
+        ProfScope ps(P, s, "outer_lean_fwd",
+                     (double)nb * na * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+        e = launch_outer_lean<T>(o, dp.E_m, dp.S, true, P->cus, s);
+      }
+      if (e != hipSuccess) return hip_err(e, "outer_lean_fwd launch");
+    }
+    for (int g0 = 0; g0 < A && !lean; g0 += kMaxA) {  // three inputs per launch
       const int na = std::min(kMaxA, A - g0);
       OuterFwdArgs<T> o{};
       for (int a = 0; a < na; ++a) {
@@ -896,6 +954,28 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       nb /= dp.q * dp.m;
       int64_t rest = 1;
       for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
+      const bool dense = d > 0 || (user.jstride == 0 && user.cgrp == 0);
+      if (dense && !dp.ctr && dp.p <= 2 && outer_lean_supported((int)dp.m, dp.E_m, dp.S, (int)dp.q, (int)sizeof(T))) {
+        OuterLeanArgs<T> o{};
+        o.in[0] = yl;
+        o.out[0] = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
+        o.nb = nb;
+        o.out_bstride = d == 0 ? dist : Le[d] * rest;
+        o.R = rest;
+        o.L = (uint32_t)Le[d];
+        o.q = (int)dp.q;
+        o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+        o.fd = dp.fd_m;
+        o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+        o.zqm = rtab<T>(P, d);
+        {
+          ProfScope ps(P, s, "outer_lean_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+          e = launch_outer_lean<T>(o, dp.E_m, dp.S, false, P->cus, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "outer_lean_bwd launch");
+        yl = o.out[0];
+        continue;
+      }
       OuterBwdArgs<T> o{};
       o.y = yl;
       o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
@@ -1214,11 +1294,13 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
       return nullptr;
     }
     e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
     if (e != hipSuccess) {
       hip_err(e, "hipGetDevice");
       free_plan(P);
       return nullptr;
     }
+    if (P->cus < 1) P->cus = 1;
   }
   if ((rc = alloc_tables(P)) != HDCONV_OK || (rc = alloc_workspace(P)) != HDCONV_OK) {
     free_plan(P);

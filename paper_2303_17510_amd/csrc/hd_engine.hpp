@@ -91,6 +91,22 @@ struct FusedArgs {
   RootTable<T> zqm;  // powers of zeta_{qm}
 };
 
+// Whole rows of one block (p = 1), product operator, dense rows: the lean
+// row kernel for launches over many rows (hd_k_lean.hip).
+template <typename T>
+struct LeanRowArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out;
+  int64_t in_stride, out_stride;  // elements between consecutive rows
+  int64_t nrows;
+  uint32_t L;  // row length (<= m)
+  int q;       // residues
+  T scale;     // 1/(q m)
+  FftDesc fd;  // m points (the kernel reads its per-stage twiddle tables)
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;  // powers of zeta_{qm}
+};
+
 // Inner form, pass 1: for a tile of S consecutive columns s of the p x m
 // view f_{tm+s} of each row, the p-point DFT over t of zeta_q^{vt} f_{tm+s}
 // for residues v0 .. v0+D-1.  Output work[a][(row D + dv) p + u][s].
@@ -193,6 +209,25 @@ struct OuterBwdArgs {
   RootTable<T> zqm;
 };
 
+// Outer dimension, direct form with one block, dense planes: the lean outer
+// kernel (hd_k_lean.hip).  Forward: in[a] -> out[a] (level buffers) for the
+// na inputs of the launch; backward: in[0] (the level buffer) -> out[0].
+template <typename T>
+struct OuterLeanArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out[kMaxA];
+  int na;                           // forward: inputs of this launch
+  int64_t nb;                       // planes
+  int64_t in_bstride, out_bstride;  // words between planes of the user-side array (fwd: in, bwd: out)
+  int64_t R;                        // columns per plane (contiguous)
+  uint32_t L;                       // length of the transformed dimension (<= m)
+  int q;                            // residues
+  T scale;                          // backward: 1/(q m)
+  FftDesc fd;                       // m points (the kernel reads its per-stage twiddle tables)
+  const cpx<T>* fft_tw;
+  RootTable<T> zqm;
+};
+
 // Zero padding / truncation copies between a dense box L[0..2] and a dense
 // box N[0..2] (the explicit method's materialised padding).
 template <typename T>
@@ -211,6 +246,17 @@ struct BoxCopyArgs {
 // instance; the host checks that the plan's geometry fits before calling.
 template <typename T>
 hipError_t launch_fused1d(const FusedArgs<T>& a, int E, int P, int A, hipStream_t s);
+template <typename T>
+hipError_t launch_rows_lean(const LeanRowArgs<T>& a, int E, int A, int cus, hipStream_t s);
+template <typename T>
+hipError_t launch_outer_lean(const OuterLeanArgs<T>& a, int E, int S, bool fwd, int cus, hipStream_t s);
+// Sizes, points per lane and columns per workgroup the lean outer kernel is
+// built for (tbytes: bytes of a real word).
+bool outer_lean_supported(int m, int E, int S, int q, int tbytes);
+// Sizes, points per lane, input and residue counts the lean row kernel is
+// built for.
+constexpr int kLeanMaxQ = 8;
+bool rows_lean_supported(int m, int E, int A, int q, int tbytes);
 template <typename T>
 hipError_t launch_cols_fwd(const ColFwdArgs<T>& a, int E, int A, hipStream_t s);
 template <typename T>

@@ -149,7 +149,19 @@ static int pow2_floor(int64_t x) {
 // Powers of two: measured on gfx950, the row pass is fastest with fewer,
 // wider passes (16 points per lane in FP32 from m = 2048, 8 in FP64), the
 // whole-row kernel with 8 (FP32, m >= 1024) or 4 points per lane.
-static bool pick_e_row(int64_t m, int64_t p, bool fused, int tbytes, int* E) {
+static bool pow2_in(int64_t m, int64_t lo, int64_t hi) { return m >= lo && m <= hi && (m & (m - 1)) == 0; }
+
+static bool pick_e_row(int64_t m, int64_t p, bool fused, bool ctr, int tbytes, int* E) {
+  // whole rows of one or two blocks (not centered) run the lean row kernel
+  // (hd_k_lean.hip): 8 points per lane in FP32, 4 in FP64 (measured at 256
+  // points, 256^2 rows: 0.46 ms against 0.90 ms for the general whole-row
+  // kernel)
+  // (FP64 rows of 2048 points: the general kernel with 8 points per lane,
+  // 0.29 against 0.32-0.34 ms for the 2048^2 row pass)
+  if (fused && p <= 2 && !ctr && pow2_in(m, 64, tbytes == 4 ? 2048 : 1024)) {
+    *E = tbytes == 4 ? 8 : 4;
+    return true;
+  }
   if (m % 3 == 0) {
     *E = 12;
     return m % 12 == 0 && m / 12 <= kMaxThreads;
@@ -187,7 +199,14 @@ static bool pick_e_col(int64_t p, int tbytes, int* E) {
 // short transforms run best with few points per lane (measured: 4 up to 256
 // points, 8 up to 1024, 16 beyond in FP32 and for the p = 2 form except at
 // 512 points).
-static bool pick_e_outer(int64_t m, int64_t p, int tbytes, int* E) {
+static bool pick_e_outer(int64_t m, int64_t p, bool ctr, int tbytes, int* E) {
+  // one or two blocks of 64 .. 1024 points (not centered) run the lean
+  // outer kernel: 8 points per lane up to 256 points, else 16 (FP64: 4,
+  // else 8)
+  if (p <= 2 && !ctr && pow2_in(m, 64, 1024)) {
+    *E = (tbytes == 4 ? 8 : 4) * (m <= 256 ? 1 : 2);
+    return true;
+  }
   if (m % 3 == 0) {
     *E = 12;
     return m % 12 == 0 && m / 12 <= kMaxThreads;
@@ -239,7 +258,7 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
         if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 8192");
         if (dp->p > kMaxColP || !col_size_ok(dp->p)) return fail("unsupported p for the column passes");
       }
-      if (dp->E_m == 0 && !pick_e_row(dp->m, dp->p, fused, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
+      if (dp->E_m == 0 && !pick_e_row(dp->m, dp->p, fused, dp->ctr != 0, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
       if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("row points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto need = [&](int r) {
@@ -283,14 +302,17 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
       if (dp->D != dp->n) return fail("outer variant processes all residues");
       if (dp->m < 8) return fail("outer variant needs m >= 8");
-      if (dp->E_m == 0 && !pick_e_outer(dp->m, dp->p, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
+      if (dp->E_m == 0 && !pick_e_outer(dp->m, dp->p, dp->ctr != 0, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
       if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("outer points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto oneed = [&](int S) { return ((size_t)dp->m * S + tw_words(dp->fd_m)) * cb; };
       dp->fd_m.twmode = dp->tw_pref == 2;
       if (dp->tw_pref == 0 && oneed(8) > 128 * 1024) dp->fd_m.twmode = 0;
       if (dp->S == 0) {
-        int S = std::min(pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G)), 64);
+        // the lean outer kernel: 16 columns (measured at 256 points: 16
+        // columns 1.30 ms against 8 columns 1.59 ms for the whole 256^3 plan)
+        const bool lean = dp->p <= 2 && !dp->ctr && pow2_in(dp->m, 64, 1024);
+        int S = std::min(pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G)), lean ? 16 : 64);
         while (S > 1 && oneed(S) > 128 * 1024) S /= 2;
         dp->S = S;
       }
@@ -526,22 +548,31 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
   // the autotuner's 2D/3D timings): powers of two only; up to 1024 points one
   // transform of m >= M (q = 1); beyond, the direct form with p = 1 or p = 2
   // (half the length: twice the columns per workgroup) and the least padding,
-  // ties to p = 2 once the p = 1 transform would exceed 1024 points.  In 3D
-  // plans, from 256 points on, two residues of half the length (q = 2,
-  // p = 1) instead of the one transform: the recorded 3D timings put them
-  // 6-45 % ahead per dimension (the 2D timings favour q = 1 at every size).
+  // ties to p = 2 once the p = 1 transform would exceed 1024 points.  3D
+  // plans beyond 64 points: see below.
   {
     const int64_t m1 = std::max<int64_t>(8, pow2_ceil(M));
-    // 3D plans: a transform of 3 * 2^k points (192 ... 768) when it pads at
-    // least 20 % less (3D cubes L = 150: 1.60 -> 1.22 ms; smaller and larger
-    // sizes, and 2D plans, measured slower)
-    const int64_t m13 = next_fft_size(M);
-    if (dims == 3 && m13 < m1 && m13 % 3 == 0 && 5 * m13 <= 4 * m1 && m13 >= 192 && m13 <= 768 &&
-        set_geom(dp, L, M, m13, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w))
-      return true;
-    if (dims == 3 && m1 >= 256 && m1 <= 1024 && set_geom(dp, L, M, m1 / 2, 0, VAR_OUTER) && dp->p == 1 &&
-        finish_dim(dp, A, tbytes, &w))
-      return true;
+    // 3D plans beyond 64 points: the power of two m >= L (p = 1) or its half
+    // (p = 2), the least padding q m, ties to p = 1.  Both run the lean outer
+    // kernel; measured for whole 3D cubes against the earlier choices (3 * 2^k
+    // transforms, two residues of half the power of two): 96^3 0.170 ->
+    // 0.084 ms, 150^3 1.02 -> 0.61, 192^3 1.21 -> 0.63, 320^3 8.4 -> 3.8,
+    // 384^3 10.5 -> 4.7; at 229^3 the tie goes to p = 1 (1.72 against 1.89).
+    const int64_t mA = std::max<int64_t>(8, pow2_ceil(L));
+    if (dims == 3 && mA >= 128 && mA <= 2048) {
+      DimPlan a, b;
+      std::string w2;
+      const bool oka = mA <= 1024 && set_geom(&a, L, M, mA, 0, VAR_OUTER) && finish_dim(&a, A, tbytes, &w2);
+      const bool okb = set_geom(&b, L, M, mA / 2, 0, VAR_OUTER) && b.p == 2 && finish_dim(&b, A, tbytes, &w2);
+      if (oka && (!okb || a.q * a.m <= b.q * b.m)) {
+        *dp = a;
+        return true;
+      }
+      if (okb) {
+        *dp = b;
+        return true;
+      }
+    }
     if (m1 <= 1024 && set_geom(dp, L, M, m1, 0, VAR_OUTER) && finish_dim(dp, A, tbytes, &w)) return true;
     DimPlan a, b;
     const int64_t ma = std::max<int64_t>(8, pow2_ceil(L)), mb = std::max<int64_t>(8, pow2_ceil(cdiv(L, 2)));

@@ -141,6 +141,8 @@ class CostModel:
     def load_file(cls, path: str) -> "CostModel":
         with open(path + ".json") as fh:
             hdr = json.load(fh)
+        if int(hdr.get("nfeatures", -1)) != NF:
+            raise ValueError("%s was trained on %s features; this library computes %d" % (path, hdr.get("nfeatures"), NF))
         m = cls(hidden=int(hdr["hidden"]))
         m.load(np.fromfile(path, dtype="<f4"))
         return m

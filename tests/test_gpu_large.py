@@ -198,9 +198,9 @@ def test_1d_maximum_length(gpu):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n", [150, 229])
 def test_3d_non_power_of_two(gpu, dtype, n):
-    # default 3D plans for lengths well below a power of two: 3 * 2^k outer
-    # transforms (150: 384 points, rows as two 128-point blocks), else two residues of half
-    # the power of two (229: outer 256-point transforms with q = 2)
+    # default 3D plans for lengths well below a power of two: two blocks of
+    # half the power of two in every dimension (150: 128-point blocks, q = 3),
+    # else one block of the power of two (229: 256 points, q = 2)
     ins, got = run_case((n,) * 3, (2 * n,) * 3, dtype, 4)
     e = sampled_err(ins, got, 48, 7)
     say("   sampled err %.3e" % e)
