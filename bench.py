@@ -254,9 +254,10 @@ def explicit_best(wl, dtype, steps, warmup):
     return best
 
 
-def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=None, config_id=2):
+def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=None, config_id=2, grouped=False):
     """Independent 1D convolutions in one graph launch: by default the 4096
-    lengths L log-uniform in [64, 65536] (seeded), M = 2L."""
+    lengths L log-uniform in [64, 65536] (seeded), M = 2L.  The heuristic
+    plan runs as one persistent kernel (``grouped``: per-group launches)."""
     import numpy as np
     import torch
     from paper_2303_17510_amd import BatchPlan, synth
@@ -272,9 +273,10 @@ def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=No
     ins = [[big[a][offs[i]:offs[i + 1]] for a in range(2)] for i in range(count)]
     outs = [out_big[offs[i]:offs[i + 1]] for i in range(count)]
     t0 = time.perf_counter()
-    with BatchPlan(Ls, dtype=dtype, tuner=tuner) as bp:
+    with BatchPlan(Ls, dtype=dtype, tuner=tuner, grouped=grouped) as bp:
         plan_s = time.perf_counter() - t0
         groups = bp.groups()
+        stats = bp.stats()
         bound = bp.bind(ins, outs)   # pointer tables built once, outside the timed region
         for _ in range(max(2, warmup)):   # the second execute captures the graph
             bound.execute()
@@ -288,7 +290,9 @@ def batched_leg(steps, warmup, dtype="c64", count=4096, tuner="heuristic", Ls=No
         torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     w = 8 if dtype == "c64" else 16
-    rec = {"dtype": dtype, "method": "hybrid, batched graph", "tuner": tuner, "plan_s": plan_s,
+    form = "persistent kernel" if stats["persistent"] else "grouped launches"
+    rec = {"dtype": dtype, "method": "hybrid, batched graph (%s)" % form, "tuner": tuner, "plan_s": plan_s,
+           "persistent": stats["persistent"], "grid": stats["grid"], "tasks": stats["tasks"],
            "convolutions": count, "outputs": tot, "ms": ms, "outputs_per_s": tot / (ms * 1e-3),
            "compulsory_frac": 3 * w * tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "groups": [(g["variant"], g["m"], g["p"], g["q"], g["count"]) for g in groups]}
@@ -498,6 +502,7 @@ def main():
                 put("1d_1.5M_hybrid_%s" % dt, "c2_1p5m", lambda: leg(w15, dt, "hybrid", 50, 5))
                 put("1d_1.5M_explicit_%s" % dt, "c2_1p5m", lambda: explicit_best(w15, dt, 20, 5))
             put("batched_4096_c64", "batched", lambda: batched_leg(20, 3))
+            put("batched_4096_c64_grouped", None, lambda: batched_leg(20, 3, grouped=True))
             put("batched_4096_c64_exhaustive", None, lambda: batched_leg(20, 3, tuner="exhaustive"))
             w1 = WORKLOADS["c1"]
             put("c1_single_hybrid_c128", "c1", lambda: leg(w1, "c128", "hybrid", 100, 10))

@@ -87,8 +87,19 @@ enum {
   HDCONV_BATCH_NO_GRAPH = 2, /* batched plans: launch eagerly on every execute      */
   HDCONV_PLAN_CENTERED = 4,  /* centered convolution (see below); plans and batches */
   HDCONV_PLAN_HERMITIAN = 8, /* Hermitian convolution (see below); plans, 1D batches    */
-  HDCONV_PLAN_NO_WORKSPACE = 16 /* no workspace of its own: runs through
+  HDCONV_PLAN_NO_WORKSPACE = 16, /* no workspace of its own: runs through
                                    hdconv_execute_noalloc only (see there)   */
+  HDCONV_PLAN_ACCUMULATE_OUTPUT = 32, /* residue blocks of the inner form add their
+                                   contributions into the output array itself
+                                   instead of an FP64 accumulation buffer
+                                   (the paper's two-block data-flow
+                                   optimization, Sec. 6 loop optimizations):
+                                   16 L bytes less workspace; the sum is kept
+                                   in the output precision, and execution must
+                                   be out of place                          */
+  HDCONV_BATCH_GROUPED = 64      /* batched plans: one set of launches per size
+                                   group on side streams instead of the
+                                   persistent single launch (see below)     */
 };
 
 /* Centered convolutions (the paper's section on centered convolutions in one
@@ -147,7 +158,11 @@ typedef struct hdconv_options {
                         dimension is contiguous), inputs and output alike; 0:
                         dense.  2D uses stride[0] >= L[1] (stored extent);
                         3D stride[1] >= L[2], stride[0] >= L[1] stride[1]     */
-  int reserved[8];   /* zero                                                    */
+  int conj_pairs;    /* inner form, forward column pass: 0 computes residues v and
+                        n - v together (the conjugate symmetry optimization) when
+                        a block holds all n >= 3 residues of an ordinary
+                        dimension; -1 never                                   */
+  int reserved[7];   /* zero                                                    */
 } hdconv_options;
 
 /* tuners (Sec. 7: the paper's optimizer times candidate (m, D, ...) per
@@ -329,12 +344,24 @@ void hdconv_model_destroy(hdconv_model_t model);
  * length (dims = 1), L[i] and M[i] each as in hdconv_plan, all with the same
  * A in {2,3}, B = 1 (the product operator; HDCONV_EUNSUPPORTED otherwise)
  * and dtype.  Convolutions whose planned shape (variant, m, p, q and
- * kernel widths) coincides form one group; each group runs as one set of
- * launches over a device table of per-row pointers and lengths, groups run
- * on parallel branches (four side streams forked from and joined to the
- * execute stream), and from the second execute on the whole batch is one
- * hipGraph launch.  Allocates per-group tables, workspace, a device task
- * table and a pinned staging copy of it.  NULL on error.
+ * kernel widths) coincides form one group (a size bucket).
+ * Persistent form (the default for ordinary, not centered or Hermitian,
+ * batches with the heuristic tuner whose every convolution has a compiled
+ * shape: L up to 96 * 2048 in complex64, 2^16 in complex128, and M <= 8 * the
+ * power of two at or above L for whole rows): three launches of one
+ * persistent kernel (a grid of resident workgroups looping over a device
+ * task table), one per pass of the inner form of Sec. 6.1 -- column pass,
+ * row pass, back pass -- for every long convolution at once (rows of 2048
+ * points, complex128 1024); the short ones (L <= 2048, complex128 1024) run
+ * as whole rows (the direct form, Sec. 2) in the last launch.  The
+ * workspace holds every long convolution's A q m transformed words at once.
+ * Grouped form (HDCONV_BATCH_GROUPED, tuned plans, centered and Hermitian
+ * batches): each group runs as one set of launches over a device table of
+ * per-row pointers and lengths, groups on parallel branches (four side
+ * streams forked from and joined to the execute stream).  Either way, from
+ * the second execute on the batch is one hipGraph launch.  Allocates
+ * per-group tables, workspace, a device task table and a pinned staging copy
+ * of it.  NULL on error.
  * With opt->tuner EXHAUSTIVE or MODEL, each group of the heuristic plan (a
  * size bucket) is tuned: the candidates are the one-dimensional candidates
  * of its longest member plus row-packing variants of the whole-row kernel,
@@ -347,14 +374,26 @@ hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t c
 
 /* inputs: count*A device pointers (convolution i uses inputs[i*A + a]);
  * outputs: count*B device pointers; each of L[i] words (Hermitian batches:
- * ceil(L[i]/2) words).  Uploads the task
- * table (asynchronously, on `stream`) and launches; the pinned staging
- * buffer is reused, so an execute waits for the previous execute's upload. */
+ * ceil(L[i]/2) words).  When the pointers differ from the last execute's,
+ * uploads the pointer table (asynchronously, on `stream`; the pinned staging
+ * buffer is reused, so such an execute waits for the previous upload), then
+ * launches.  Executes of one batch must not overlap in time (they share the
+ * workspace). */
 int hdconv_execute_batched(hdconv_batch_t batch, const void* const* inputs, void* const* outputs, void* stream);
 
 /* Groups of a batched plan: shapes into groups[0..cap), member counts into
  * counts[0..cap), and the number of groups into *ngroups. */
 int hdconv_batch_info(hdconv_batch_t batch, hdconv_dim_info_t* groups, int64_t* counts, int cap, int* ngroups);
+
+/* Launch shape of a batched plan. */
+typedef struct hdconv_batch_stats {
+  int persistent;     /* 1: persistent launches; 0: grouped launches        */
+  int grid;           /* persistent: resident workgroups of a launch        */
+  int64_t tasks;      /* persistent: task-table entries of the launches     */
+  int64_t lds_bytes;  /* persistent: LDS bytes per workgroup                */
+  int64_t work_bytes; /* device workspace of all groups                     */
+} hdconv_batch_stats_t;
+int hdconv_batch_stats(hdconv_batch_t batch, hdconv_batch_stats_t* out);
 
 /* Release a batched plan (synchronises the device first).  NULL is ignored. */
 void hdconv_batch_destroy(hdconv_batch_t batch);

@@ -22,6 +22,8 @@ BATCH_NO_GRAPH = 2
 PLAN_CENTERED = 4
 PLAN_HERMITIAN = 8
 PLAN_NO_WORKSPACE = 16
+PLAN_ACCUMULATE_OUTPUT = 32
+BATCH_GROUPED = 64
 SCRATCH_BYTES = 64 << 20  # static scratch of hdconv_execute_noalloc
 MULT_PRODUCT, MULT_QUADRATIC = 0, 1
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
@@ -41,7 +43,7 @@ class Options(ctypes.Structure):
                 ("tuner", ctypes.c_int), ("tune_reps", ctypes.c_int), ("margin", ctypes.c_double),
                 ("model", ctypes.c_void_p), ("db_path", ctypes.c_char_p), ("copies", _i64), ("dist", _i64),
                 ("mult", ctypes.c_int), ("mult_coef", ctypes.POINTER(ctypes.c_double)), ("stride", _i64 * 2),
-                ("reserved", ctypes.c_int * 8)]
+                ("conj_pairs", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 class DimInfo(ctypes.Structure):
@@ -58,6 +60,11 @@ class PlanInfo(ctypes.Structure):
                 ("compulsory_bytes", ctypes.c_double), ("traffic_bytes", ctypes.c_double),
                 ("launches", ctypes.c_int), ("tuner", ctypes.c_int), ("tuned_candidates", ctypes.c_int),
                 ("timed_candidates", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int), ("grid", ctypes.c_int), ("tasks", _i64), ("lds_bytes", _i64),
+                ("work_bytes", _i64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -111,6 +118,7 @@ SIGNATURES = {
                                               ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "hdconv_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DimInfo), ctypes.POINTER(_i64),
                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "hdconv_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchStats)]),
     "hdconv_batch_destroy": (None, [ctypes.c_void_p]),
     "hdconv_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hdconv_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,

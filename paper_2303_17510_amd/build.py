@@ -17,10 +17,10 @@ OUT = os.path.join(HERE, "libhdconv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("HDCONV_ARCH", "gfx950")
 
-SOURCES = ["hd_k_fused.hip", "hd_k_lean.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_mlp.hip", "hd_api.cpp", "hd_plan.cpp"]
+SOURCES = ["hd_k_fused.hip", "hd_k_lean.hip", "hd_k_batch.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_mlp.hip", "hd_api.cpp", "hd_plan.cpp"]
 # the two largest kernel files compile as two objects each (FP32 / FP64
 # instances, selected by HD_PART), so the parallel build is not held up by them
-SPLIT = {"hd_k_fused.hip", "hd_k_lean.hip", "hd_k_multi.hip"}
+SPLIT = {"hd_k_fused.hip", "hd_k_lean.hip", "hd_k_batch.hip", "hd_k_multi.hip"}
 UNITS = [(s, part) for s in SOURCES for part in ((1, 2) if s in SPLIT else (0,))]
 
 

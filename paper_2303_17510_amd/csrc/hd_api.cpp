@@ -87,6 +87,7 @@ struct Plan {
   int64_t copies = 1, dist = 0;                       // copies per execute, words between them
   int64_t stride[2] = {0, 0};                         // element strides of dims 0, 1 (0: dense)
   int quad = 0;                                       // quadratic multiplication operator, B outputs
+  bool conj_pairs = true;                             // inner form: residues v and n - v together
   // the launches of the row pass per output: shares of at most three inputs
   // (one share with every input for products and A <= 3)
   std::vector<Share> shares[kMaxB];
@@ -233,6 +234,7 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       } else if (!choose_dim(Le, Me, kernel_inputs(P), tb, contiguous, lines_of(P, d), &dp, &why, ctr, P->dims)) {
         return set_err(HDCONV_EUNSUPPORTED, "dim %d: %s", d, why.c_str());
       }
+      if (opt && opt->D[d] > 0 && dp.variant == VAR_OUTER) dp.D = std::min<int64_t>(opt->D[d], dp.n);
       if (opt && (opt->E_m[d] || opt->E_p[d] || opt->S[d] || opt->rows_per_block[d] || opt->twiddles[d])) {
         // the chosen geometry with the caller's launch shape
         if (opt->E_m[d]) dp.E_m = opt->E_m[d];
@@ -286,6 +288,10 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
                        (long long)dp.p, (long long)dp.q, why.c_str());
     }
   }
+  // residue blocks (D < q) on the first outer dimension only
+  for (int d = 1; d + 1 < P->dims; ++d)
+    if (P->dp[d].D < P->dp[d].n)
+      return set_err(HDCONV_EUNSUPPORTED, "dim %d: residue blocks (D < q) apply to the first dimension only", d);
   return HDCONV_OK;
 }
 
@@ -393,13 +399,17 @@ static double plan_traffic(const Plan* P, int* launches) {
     nl += A + nout;
   }
   double nb = 1;  // planes entering the current level
+  // residue blocks of the first outer dimension: the pipeline runs once per
+  // block; each block reads the inputs, later blocks also read the output
+  const int64_t blocks0 = P->dims > 1 ? cdiv(P->dp[0].q, P->dp[0].D) : 1;
   for (int d = 0; d + 1 < P->dims; ++d) {
     const DimPlan& dp = P->dp[d];
     double rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (double)stored_extent(P->dp[e]);
     const double in_el = nb * Le[d] * rest, out_el = nb * dp.q * dp.m * rest;
-    bytes += A * (in_el + out_el) * w + nout * (out_el + in_el) * w;  // forward + backward
-    nl += groups + nout;
+    const double nbk = d == 0 ? (double)blocks0 : 1.0;
+    bytes += A * (nbk * in_el + out_el) * w + nout * (out_el + (2.0 * nbk - 1.0) * in_el) * w;  // forward + backward
+    nl += (int)blocks0 * (groups + nout);
     nb *= (double)(dp.q * dp.m);
   }
   const DimPlan& dl = P->dp[P->dims - 1];
@@ -408,7 +418,7 @@ static double plan_traffic(const Plan* P, int* launches) {
   if (dl.variant == VAR_FUSED) {
     // every share reads its inputs and writes; later shares also read the output
     bytes += rows * (share_in + shares + (shares - nout)) * Lr * w;
-    nl += shares;
+    nl += (int)blocks0 * shares;
   } else {
     const int64_t blocks = cdiv(dl.n, dl.D);
     const double wk = rows * (double)dl.q * dl.m;  // all residues' rows
@@ -422,7 +432,7 @@ static double plan_traffic(const Plan* P, int* launches) {
       const double contrib = (double)blocks * (double)P->shares[b].size();
       if (contrib > 1) bytes += (2.0 * contrib - 2) * rows * Lr * 16.0;
     }
-    nl += k1_runs * (int)blocks * groups + 2 * (int)blocks * shares;
+    nl += (int)blocks0 * (k1_runs * (int)blocks * groups + 2 * (int)blocks * shares);
   }
   if (launches) *launches = P->method == HDCONV_METHOD_EXPLICIT ? nl * (int)P->copies : nl;
   return bytes * (double)P->copies;
@@ -517,7 +527,8 @@ static std::vector<std::pair<void**, size_t>> workspace_parts(Plan* P) {
   for (int d = 0; d + 1 < P->dims; ++d) {
     size_t rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)stored_extent(P->dp[e]);
-    nb *= (size_t)(P->dp[d].q * P->dp[d].m);
+    // the first outer dimension holds one block of D residues at a time
+    nb *= (size_t)((d == 0 ? P->dp[d].D : P->dp[d].q) * P->dp[d].m);
     for (int a = 0; a < P->A; ++a) want.push_back({&P->lvl[d][a], nb * rest * w});
   }
   const DimPlan& dl = P->dp[P->dims - 1];
@@ -541,7 +552,9 @@ static std::vector<std::pair<void**, size_t>> workspace_parts(Plan* P) {
       acc_len = (size_t)P->dist;
     }
     // (also for outputs summed over several row-pass shares)
-    if (dl.D < dl.n || max_shares(P) > 1) want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
+    // (not with HDCONV_PLAN_ACCUMULATE_OUTPUT: the output array accumulates)
+    if ((dl.D < dl.n || max_shares(P) > 1) && !(P->flags & HDCONV_PLAN_ACCUMULATE_OUTPUT))
+      want.push_back({(void**)&P->acc64, acc_rows * acc_len * 16});
   }
   return want;
 }
@@ -731,6 +744,7 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
       k1.ctr = dp.ctr;
       k1.fold = centered_folds(dp) ? 1 : 0;
       k1.herm = dp.herm;
+      k1.pair = (P->conj_pairs && !dp.ctr && !k1.fold && !dp.herm && v0 == 0 && D == dp.n && dp.n >= 3) ? 1 : 0;
       k1.fd = dp.fd_p;
       k1.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
       k1.zq = (const cpx<T>*)P->dd[d].zq;
@@ -772,7 +786,10 @@ static int run_rows(Plan* P, const cpx<T>* const* in, cpx<T>* out, int64_t nrows
       k3.work = (const cpx<T>*)(P->quad ? P->rowout : P->rowwork[0]);
       k3.out = out;
       k3.acc = P->acc64;
-      k3.acc_mode = ncontrib == 1 ? ACC_WRITE : (ci == 0 ? ACC_FIRST : (ci == ncontrib - 1 ? ACC_LAST : ACC_ADD));
+      if (P->flags & HDCONV_PLAN_ACCUMULATE_OUTPUT)  // the first contribution writes, later ones add
+        k3.acc_mode = ci == 0 ? ACC_WRITE : ACC_OUT_ADD;
+      else
+        k3.acc_mode = ncontrib == 1 ? ACC_WRITE : (ci == 0 ? ACC_FIRST : (ci == ncontrib - 1 ? ACC_LAST : ACC_ADD));
       k3.out_stride = rs;
       k3.nrows = nrows;
       k3.L = dp.L;
@@ -871,9 +888,22 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
   } else {
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)inputs[a];
   }
+  // Residue blocks of the first outer dimension (Sec. 5: one block of D
+  // residues at a time through the inner dimensions, buffers reused): every
+  // block runs the whole pipeline, its inverse adds to the output.
+  const cpx<T>* cur0[kMaxIn];
+  for (int a = 0; a < A; ++a) cur0[a] = cur[a];
+  const int64_t q0 = P->dims > 1 ? P->dp[0].q : 1;
+  const int64_t D0 = P->dims > 1 ? P->dp[0].D : 1;
+  for (int64_t r0 = 0; r0 < q0; r0 += D0) {
+  const int Db = (int)std::min<int64_t>(D0, q0 - r0);
+  for (int a = 0; a < A; ++a) cur[a] = cur0[a];
   // outer dimensions, forward
   int64_t nb = nc;
   for (int d = 0; d + 1 < P->dims; ++d) {
+    // residues of this launch: the block's on the first dimension, all on the others
+    const int rr0 = d == 0 ? (int)r0 : 0;
+    const int nres = d == 0 ? Db : (int)P->dp[d].q;
     const DimPlan& dp = P->dp[d];
     int64_t rest = 1;
     for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
@@ -893,12 +923,14 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       o.R = rest;
       o.L = (uint32_t)Le[d];
       o.q = (int)dp.q;
+      o.r0 = rr0;
+      o.D = nres;
       o.fd = dp.fd_m;
       o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
       o.zqm = rtab<T>(P, d);
       {
         ProfScope ps(P, s, "outer_lean_fwd",
-                     (double)nb * na * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+                     (double)nb * na * ((double)Le[d] + (double)nres * dp.m) * rest * 2.0 * sizeof(T));
         e = launch_outer_lean<T>(o, dp.E_m, dp.S, true, P->cus, s);
       }
       if (e != hipSuccess) return hip_err(e, "outer_lean_fwd launch");
@@ -917,21 +949,21 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       o.L = Le[d];
       o.m = (int)dp.m;
       o.q = (int)dp.q;
-      o.r0 = 0;
-      o.D = (int)dp.q;
+      o.r0 = rr0;
+      o.D = nres;
       o.S = dp.S;
       o.ctr = dp.ctr;
       o.fd = dp.fd_m;
       o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
       o.zqm = rtab<T>(P, d);
       {
-        ProfScope ps(P, s, "outer_fwd", (double)nb * na * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+        ProfScope ps(P, s, "outer_fwd", (double)nb * na * ((double)Le[d] + (double)nres * dp.m) * rest * 2.0 * sizeof(T));
         e = launch_outer_fwd<T>(o, dp.E_m, (int)dp.p, na, s);
       }
       if (e != hipSuccess) return hip_err(e, "outer_fwd launch");
     }
     for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
-    nb *= dp.q * dp.m;
+    nb *= nres * dp.m;
   }
   const int64_t nb_rows = nb;
   for (int ob = 0; ob < nout; ++ob) {
@@ -951,7 +983,10 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
     const cpx<T>* yl = rows_out;
     for (int d = P->dims - 2; d >= 0; --d) {
       const DimPlan& dp = P->dp[d];
-      nb /= dp.q * dp.m;
+      const int rr0 = d == 0 ? (int)r0 : 0;
+      const int nres = d == 0 ? Db : (int)dp.q;
+      const bool add = d == 0 && r0 > 0;  // later blocks add to the output
+      nb /= nres * dp.m;
       int64_t rest = 1;
       for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
       const bool dense = d > 0 || (user.jstride == 0 && user.cgrp == 0);
@@ -964,12 +999,16 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
         o.R = rest;
         o.L = (uint32_t)Le[d];
         o.q = (int)dp.q;
+        o.r0 = rr0;
+        o.D = nres;
+        o.add = add ? 1 : 0;
         o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
         o.fd = dp.fd_m;
         o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
         o.zqm = rtab<T>(P, d);
         {
-          ProfScope ps(P, s, "outer_lean_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+          ProfScope ps(P, s, "outer_lean_bwd",
+                       (double)nb * ((add ? 2.0 : 1.0) * (double)Le[d] + (double)nres * dp.m) * rest * 2.0 * sizeof(T));
           e = launch_outer_lean<T>(o, dp.E_m, dp.S, false, P->cus, s);
         }
         if (e != hipSuccess) return hip_err(e, "outer_lean_bwd launch");
@@ -980,7 +1019,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       o.y = yl;
       o.out = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
       o.acc = nullptr;
-      o.acc_mode = ACC_WRITE;
+      o.acc_mode = add ? ACC_OUT_ADD : ACC_WRITE;
       o.nb = nb;
       o.out_bstride = d == 0 ? dist : Le[d] * rest;
       if (d == 0) o.lay = user;
@@ -988,8 +1027,8 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       o.L = Le[d];
       o.m = (int)dp.m;
       o.q = (int)dp.q;
-      o.r0 = 0;
-      o.D = (int)dp.q;
+      o.r0 = rr0;
+      o.D = nres;
       o.S = dp.S;
       o.ctr = dp.ctr;
       o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
@@ -997,7 +1036,8 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       o.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
       o.zqm = rtab<T>(P, d);
       {
-        ProfScope ps(P, s, "outer_bwd", (double)nb * ((double)Le[d] + (double)dp.q * dp.m) * rest * 2.0 * sizeof(T));
+        ProfScope ps(P, s, "outer_bwd",
+                     (double)nb * ((add ? 2.0 : 1.0) * (double)Le[d] + (double)nres * dp.m) * rest * 2.0 * sizeof(T));
         e = launch_outer_bwd<T>(o, dp.E_m, (int)dp.p, s);
       }
       if (e != hipSuccess) return hip_err(e, "outer_bwd launch");
@@ -1034,6 +1074,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       if (e != hipSuccess) return hip_err(e, "truncate launch");
     }
   }
+  }  // residue blocks of the first outer dimension
   return HDCONV_OK;
 }
 
@@ -1210,6 +1251,7 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
     o.dist = opt->dist;
     o.stride[0] = opt->stride[0];
     o.stride[1] = opt->stride[1];
+    o.conj_pairs = opt->conj_pairs;
     Plan* T = (Plan*)hdconv_plan_ex(L, M, A, B, dims, dtype, &o);
     if (T) {
       T->tuner = opt->tuner;
@@ -1231,6 +1273,7 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
   P->method = (opt && opt->method == HDCONV_METHOD_EXPLICIT) ? HDCONV_METHOD_EXPLICIT : HDCONV_METHOD_HYBRID;
   P->flags = opt ? opt->flags : 0;
   P->host_only = (P->flags & HDCONV_PLAN_HOST_ONLY) != 0;
+  P->conj_pairs = !(opt && opt->conj_pairs < 0);
   // coef is B x A x A (row-major); the pair (i, j), i <= j, weighs F_i F_j
   P->quad = quad ? 1 : 0;
   for (int b = 0; b < B; ++b) {
@@ -1281,6 +1324,14 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
   }
   int rc = build_dims(P, opt);
   if (rc == HDCONV_OK) rc = size_workspace(P);
+  // over the workspace cap: fewer residues per block of the first outer
+  // dimension (Sec. 5's buffer reuse), unless the caller fixed D there
+  while (rc == HDCONV_ENOMEM && P->dims > 1 && P->dp[0].variant == VAR_OUTER && P->dp[0].D > 1 &&
+         !(opt && opt->D[0] > 0)) {
+    P->dp[0].D = (P->dp[0].D + 1) / 2;
+    clear_err();
+    rc = size_workspace(P);
+  }
   if (rc != HDCONV_OK) {
     free_plan(P);
     return nullptr;
@@ -1376,7 +1427,10 @@ static int execute_plan(Plan* P, const void* const* inputs, void* const* outputs
   const char* o = (const char*)outputs[0];
   // several outputs, or one summed over several row-pass launches, are
   // written while inputs are still read: then no output may touch an input
-  const bool out_of_place = P->B > 1 || max_shares(P) > 1;
+  // (also: residue blocks of the first outer dimension read the inputs again
+  // after earlier blocks wrote the output)
+  const bool out_of_place = P->B > 1 || max_shares(P) > 1 || (P->dims > 1 && P->dp[0].D < P->dp[0].q) ||
+                            (P->flags & HDCONV_PLAN_ACCUMULATE_OUTPUT);
   for (int a = 0; a < P->A; ++a) {
     const char* i = (const char*)inputs[a];
     if (!out_of_place && i != o && overlap(i, o))
@@ -1846,6 +1900,16 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   int executes = 0;
   int tuner = 0, tuned_candidates = 0, timed_candidates = 0;
+  std::vector<char> shadow, uploaded;  // task tables of this execute and of the last upload
+  // persistent form: launches of k_batch over device task tables, one per
+  // pass of the inner form
+  bool persist = false;
+  char* pmem = nullptr;  // buckets, then the task tables
+  void* pbuckets = nullptr;
+  BatchTask* ptasks[3] = {};
+  int ntasks[3] = {};
+  int pgrid = 0, xwords = 0;
+  size_t plds = 0;
 };
 
 // A one-dimensional plan for `rows` independent rows sharing the shape dp.
@@ -1891,13 +1955,29 @@ static void free_batch(Batch* Bt) {
   if (Bt->capture) (void)hipStreamDestroy(Bt->capture);
   if (Bt->task_dev) (void)hipFree(Bt->task_dev);
   if (Bt->task_host) (void)hipHostFree(Bt->task_host);
+  if (Bt->pmem) (void)hipFree(Bt->pmem);
   delete Bt;
 }
 
-// Launch every group: fork from `s` onto the side streams, join back.
+// Launch every group: fork from `s` onto the side streams, join back (the
+// persistent form: its one launch).
 template <typename T>
 static int issue_batch(Batch* Bt, hipStream_t s) {
-  hipError_t e = hipEventRecord(Bt->fork, s);
+  hipError_t e;
+  if (Bt->persist) {
+    for (int ph = 0; ph < 3; ++ph) {
+      if (Bt->ntasks[ph] == 0) continue;
+      BatchArgs<T> a{};
+      a.buckets = (const BatchBucket<T>*)Bt->pbuckets;
+      a.tasks = Bt->ptasks[ph];
+      a.ntasks = Bt->ntasks[ph];
+      a.xwords = Bt->xwords;
+      const int grid = std::min(Bt->pgrid, Bt->ntasks[ph]);
+      if ((e = launch_batch<T>(a, Bt->A, grid, Bt->plds, s)) != hipSuccess) return hip_err(e, "k_batch launch");
+    }
+    return HDCONV_OK;
+  }
+  e = hipEventRecord(Bt->fork, s);
   if (e != hipSuccess) return hip_err(e, "hipEventRecord(fork)");
   for (size_t g = 0; g < Bt->groups.size(); ++g) {
     hipStream_t hs = Bt->side[g % kSideStreams];
@@ -1914,8 +1994,9 @@ static int issue_batch(Batch* Bt, hipStream_t s) {
 
 template <typename T>
 static void fill_tasks(Batch* Bt, const void* const* inputs, void* const* outputs) {
+  Bt->shadow.assign(Bt->task_bytes, 0);
   for (size_t g = 0; g < Bt->groups.size(); ++g) {
-    RowTask<T>* t = (RowTask<T>*)(Bt->task_host + Bt->task_off[g]);
+    RowTask<T>* t = (RowTask<T>*)(Bt->shadow.data() + Bt->task_off[g]);
     for (size_t k = 0; k < Bt->members[g].size(); ++k) {
       const int64_t i = Bt->members[g][k];
       RowTask<T> r{};
@@ -1930,15 +2011,20 @@ static void fill_tasks(Batch* Bt, const void* const* inputs, void* const* output
 template <typename T>
 static int run_batched(Batch* Bt, const void* const* inputs, void* const* outputs, hipStream_t s) {
   hipError_t e;
-  if (Bt->copy_pending) {  // the staging buffer is reused: wait for the previous upload
-    if ((e = hipEventSynchronize(Bt->copied)) != hipSuccess) return hip_err(e, "hipEventSynchronize");
-    Bt->copy_pending = false;
-  }
   fill_tasks<T>(Bt, inputs, outputs);
-  if ((e = hipMemcpyAsync(Bt->task_dev, Bt->task_host, Bt->task_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_err(e, "hipMemcpyAsync(tasks)");
-  if ((e = hipEventRecord(Bt->copied, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
-  Bt->copy_pending = true;
+  // the same pointers as the table on the device: no upload (and no wait)
+  if (Bt->shadow != Bt->uploaded) {
+    if (Bt->copy_pending) {  // the staging buffer is reused: wait for the previous upload
+      if ((e = hipEventSynchronize(Bt->copied)) != hipSuccess) return hip_err(e, "hipEventSynchronize");
+      Bt->copy_pending = false;
+    }
+    memcpy(Bt->task_host, Bt->shadow.data(), Bt->task_bytes);
+    if ((e = hipMemcpyAsync(Bt->task_dev, Bt->task_host, Bt->task_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_err(e, "hipMemcpyAsync(tasks)");
+    if ((e = hipEventRecord(Bt->copied, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+    Bt->copy_pending = true;
+    Bt->uploaded = Bt->shadow;
+  }
   const bool graph = !(Bt->flags & HDCONV_BATCH_NO_GRAPH);
   // the first execute runs eagerly (kernels loaded, LDS limits granted);
   // the second captures the launches into a graph that later executes replay
@@ -2142,6 +2228,168 @@ static int tune_batch_groups(int A, int B, int dtype, int device, const hdconv_o
   return HDCONV_OK;
 }
 
+// Shape of one convolution in the persistent form (false: no compiled
+// body, or its LDS exceeds 64 KiB): whole rows of N = max(64, 2^ceil(log2 L))
+// points up to 2048 (FP64 1024) with q = ceil(M/N) <= 8 residues, else the
+// inner form with rows of 2048 (FP64 1024) points and the least compiled p
+// at or above ceil(L/m) (powers of two, and in FP32 3 * 2^k from 12 to 96).
+static bool persist_dim(int64_t L, int64_t M, int A, int tb, DimPlan* dp) {
+  const int64_t nmax = tb == 4 ? 2048 : 1024;
+  int64_t N = 64;
+  while (N < L) N *= 2;
+  DimPlan c;
+  int body = 0, Em = 0, Ep = 0, S = 0;
+  c.L = L;
+  c.M = M;
+  if (N <= nmax) {
+    const Geometry g = geometry(L, M, N, 0, false);
+    if (g.inner || g.p != 1 || g.q > kLeanMaxQ || !batch_shape(0, N, 1, tb, &body, &Em, &Ep, &S)) return false;
+    c.m = N;
+    c.p = 1;
+    c.n = c.q = c.D = g.q;
+    c.variant = VAR_FUSED;
+    c.E_m = Em;
+    c.rows_per_block = kBatchThreads / (int)(N / Em);
+  } else {
+    // the least compiled p with p m >= L: a power of two or 3 * 2^k (12 .. 96)
+    const int64_t m = nmax;
+    int64_t p = 2;
+    while (p * m < L) p *= 2;
+    for (int64_t p3 = 12; p3 <= 96 && tb == 4; p3 *= 2)
+      if (p3 * m >= L && p3 < p) p = p3;
+    const Geometry g = geometry(L, M, m, p, true);
+    if (g.p != p || !batch_shape(1, m, p, tb, &body, &Em, &Ep, &S)) return false;
+    c.m = m;
+    c.p = p;
+    c.n = c.D = g.n;
+    c.q = g.q;
+    c.variant = VAR_MULTI;
+    c.E_m = Em;
+    c.E_p = Ep;
+    c.S = S;
+    c.rows_per_block = 1;
+  }
+  std::string why;
+  if (!finish_dim(&c, A, tb, &why)) return false;
+  int xw = 0, tw = 0;
+  batch_lds_words(body, (int)c.m, (int)c.p, (int)c.q, c.fd_m.ntw_stage, c.variant == VAR_MULTI ? c.fd_p.ntw_stage : 0,
+                  tb, &xw, &tw);
+  if ((size_t)(xw + tw) * 2 * tb > 64 * 1024) return false;
+  *dp = c;
+  return true;
+}
+
+// Bytes of traffic one task aims at (a few tens of microseconds of one
+// workgroup's share of the bandwidth).
+constexpr double kTaskBytes = 256.0 * 1024;
+
+// Buckets and the three task tables of the persistent form (device memory):
+// the column passes, the row passes, then the back passes followed by the
+// whole rows; the widest convolutions first in each.
+template <typename T>
+static int build_persist(Batch* Bt) {
+  const int tb = (int)sizeof(T), A = Bt->A;
+  const double w = 2.0 * tb;
+  const size_t ng = Bt->groups.size();
+  std::vector<BatchBucket<T>> bk(ng);
+  int xw = 0, tw = 0;
+  for (size_t g = 0; g < ng; ++g) {
+    Plan* P = Bt->groups[g];
+    const DimPlan& dp = P->dp[0];
+    BatchBucket<T>& b = bk[g];
+    b.inner = dp.variant == VAR_MULTI;
+    int body = 0, Em = 0, Ep = 0, S = 0;
+    if (!batch_shape(b.inner, dp.m, dp.p, tb, &body, &Em, &Ep, &S) || Em != dp.E_m ||
+        (b.inner && (Ep != dp.E_p || S != dp.S)))
+      return set_err(HDCONV_EUNSUPPORTED, "group %zu (m=%lld, p=%lld) has no persistent body", g, (long long)dp.m,
+                     (long long)dp.p);
+    b.body = body;
+    b.m = (int)dp.m;
+    b.p = (int)dp.p;
+    b.n = (int)dp.n;
+    b.q = (int)dp.q;
+    b.S = S;
+    b.scale = (T)(1.0 / (double)(dp.q * dp.m));
+    b.tw_m = (const cpx<T>*)P->dd[0].fft_m + dp.fd_m.ntw;
+    b.ntw_m = dp.fd_m.ntw_stage;
+    if (b.inner) {
+      b.tw_p = (const cpx<T>*)P->dd[0].fft_p + dp.fd_p.ntw;
+      b.ntw_p = dp.fd_p.ntw_stage;
+      b.zq = (const cpx<T>*)P->dd[0].zq;
+    }
+    b.zqm = rtab<T>(P, 0);
+    b.rows = (const RowTask<T>*)(Bt->task_dev + Bt->task_off[g]);
+    for (int a = 0; a < A; ++a) b.work[a] = (cpx<T>*)P->rowwork[a];
+    int x = 0, t = 0;
+    batch_lds_words(body, b.m, b.p, b.q, b.ntw_m, b.ntw_p, tb, &x, &t);
+    xw = std::max(xw, x);
+    tw = std::max(tw, t);
+  }
+  // inner-form convolutions, the widest buckets first
+  std::vector<std::pair<int, int64_t>> inner;
+  {
+    std::vector<size_t> gi;
+    for (size_t g = 0; g < ng; ++g)
+      if (bk[g].inner) gi.push_back(g);
+    std::stable_sort(gi.begin(), gi.end(), [&](size_t a, size_t b) { return bk[a].p * bk[a].m > bk[b].p * bk[b].m; });
+    for (size_t g : gi)
+      for (int64_t c = 0; c < (int64_t)Bt->members[g].size(); ++c) inner.push_back({(int)g, c});
+  }
+  std::vector<BatchTask> tl[3];
+  for (auto& ic : inner) {
+    const BatchBucket<T>& b = bk[ic.first];
+    const int tiles = b.m / b.S;
+    auto per = [](double bytes_per_unit, int units) {
+      return std::max(1, std::min(units, (int)(kTaskBytes / bytes_per_unit)));
+    };
+    const int c = (int)ic.second;
+    const int u1 = A * tiles, p1 = per((1.0 + b.n) * b.p * b.S * w, u1);
+    const int u2 = b.q, p2 = per((A + 1.0) * b.m * w, u2);
+    const int u3 = tiles, p3 = per((double)(b.n + 1) * b.p * b.S * w, u3);
+    for (int u = 0; u < u1; u += p1) tl[0].push_back({ic.first, BK_COLF, c, u, std::min(p1, u1 - u)});
+    for (int u = 0; u < u2; u += p2) tl[1].push_back({ic.first, BK_ROWP, c, u, std::min(p2, u2 - u)});
+    for (int u = 0; u < u3; u += p3) tl[2].push_back({ic.first, BK_COLB, c, u, std::min(p3, u3 - u)});
+  }
+  {
+    std::vector<size_t> gr;
+    for (size_t g = 0; g < ng; ++g)
+      if (!bk[g].inner) gr.push_back(g);
+    std::stable_sort(gr.begin(), gr.end(), [&](size_t a, size_t b) { return bk[a].m > bk[b].m; });
+    for (size_t g : gr) {
+      const int rpb = kBatchThreads / (bk[g].m / Bt->groups[g]->dp[0].E_m);
+      const int cnt = (int)Bt->members[g].size();
+      for (int c = 0; c < cnt; c += rpb) tl[2].push_back({(int)g, BK_ROWS, c, 0, std::min(rpb, cnt - c)});
+    }
+  }
+  for (auto& v : tl)
+    if (v.size() > (size_t)INT32_MAX) return set_err(HDCONV_EUNSUPPORTED, "too many tasks for one launch");
+  const size_t bbytes = align256(ng * sizeof(BatchBucket<T>));
+  size_t tbytes[3], total = bbytes;
+  for (int ph = 0; ph < 3; ++ph) total += (tbytes[ph] = align256(std::max<size_t>(1, tl[ph].size()) * sizeof(BatchTask)));
+  hipError_t e = hipMalloc((void**)&Bt->pmem, total);
+  if (e != hipSuccess) return set_err(HDCONV_ENOMEM, "persistent batch tables: %s", hipGetErrorString(e));
+  Bt->pbuckets = Bt->pmem;
+  if ((e = hipMemcpy(Bt->pbuckets, bk.data(), ng * sizeof(BatchBucket<T>), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_err(e, "persistent batch tables");
+  size_t off = bbytes;
+  for (int ph = 0; ph < 3; ++ph) {
+    Bt->ptasks[ph] = (BatchTask*)(Bt->pmem + off);
+    Bt->ntasks[ph] = (int)tl[ph].size();
+    if (!tl[ph].empty() &&
+        (e = hipMemcpy(Bt->ptasks[ph], tl[ph].data(), tl[ph].size() * sizeof(BatchTask), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      return hip_err(e, "persistent batch tables");
+    off += tbytes[ph];
+  }
+  Bt->xwords = xw;
+  Bt->plds = (size_t)(xw + tw) * sizeof(cpx<T>);
+  int cus = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, Bt->device) != hipSuccess || cus < 1) cus = 1;
+  Bt->pgrid = batch_grid_t<T>(A, Bt->plds, cus);
+  Bt->persist = true;
+  return HDCONV_OK;
+}
+
 extern "C" {
 
 hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t count, int A, int B, int dims, int dtype,
@@ -2201,12 +2449,21 @@ hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t c
     for (auto& v : Bt->L) v = herm_full(v);
   Bt->M.assign(M, M + count);
   const int tb = tbytes_of(dtype);
+  // the persistent form when every convolution has a compiled shape
+  bool persist = !(Bt->flags & HDCONV_BATCH_GROUPED) && !ctr && (!opt || opt->tuner == HDCONV_TUNER_HEURISTIC);
+  std::vector<DimPlan> pdims;
+  if (persist) {
+    pdims.resize((size_t)count);
+    for (int64_t i = 0; i < count && persist; ++i) persist = persist_dim(Bt->L[i], M[i], A, tb, &pdims[(size_t)i]);
+  }
   std::map<GroupKey, std::vector<int64_t>> byk;
   std::map<GroupKey, DimPlan> shape;
   for (int64_t i = 0; i < count; ++i) {
     DimPlan dp;
     std::string why;
-    if (!choose_dim(Bt->L[i], M[i], A, tb, true, count, &dp, &why, ctr)) {
+    if (persist) {
+      dp = pdims[(size_t)i];
+    } else if (!choose_dim(Bt->L[i], M[i], A, tb, true, count, &dp, &why, ctr)) {
       set_err(HDCONV_EUNSUPPORTED, "convolution %lld (L=%lld): %s", (long long)i, (long long)L[i], why.c_str());
       free_batch(Bt);
       return nullptr;
@@ -2273,6 +2530,10 @@ hdconv_batch_t hdconv_plan_batched(const int64_t* L, const int64_t* M, int64_t c
     free_batch(Bt);
     return nullptr;
   }
+  if (persist && (tb == 4 ? build_persist<float>(Bt) : build_persist<double>(Bt)) != HDCONV_OK) {
+    free_batch(Bt);
+    return nullptr;
+  }
   return (hdconv_batch_t)Bt;
 }
 
@@ -2321,6 +2582,19 @@ int hdconv_batch_info(hdconv_batch_t batch, hdconv_dim_info_t* groups, int64_t* 
     }
     if (counts) counts[g] = (int64_t)Bt->members[g].size();
   }
+  return HDCONV_OK;
+}
+
+int hdconv_batch_stats(hdconv_batch_t batch, hdconv_batch_stats_t* out) {
+  clear_err();
+  if (!batch || !out) return set_err(HDCONV_EINVAL, "batch and out must not be NULL");
+  const Batch* Bt = (const Batch*)batch;
+  memset(out, 0, sizeof(*out));
+  out->persistent = Bt->persist ? 1 : 0;
+  out->grid = Bt->pgrid;
+  out->tasks = (int64_t)Bt->ntasks[0] + Bt->ntasks[1] + Bt->ntasks[2];
+  out->lds_bytes = (int64_t)Bt->plds;
+  for (const Plan* P : Bt->groups) out->work_bytes += (int64_t)P->work_bytes;
   return HDCONV_OK;
 }
 

@@ -54,8 +54,10 @@ __host__ __device__ constexpr int pair_slot(int i, int j) { return i == 0 ? j : 
 //   ACC_FIRST : acc  = sum                      (first of several blocks)
 //   ACC_ADD   : acc += sum
 //   ACC_LAST  : out  = (acc + sum) * scale      (last block)
+//   ACC_OUT_ADD: out += sum * scale             (later residue blocks of the
+//                first outer dimension, accumulated in the output itself)
 // acc is an FP64 buffer laid out like out.
-enum AccMode { ACC_WRITE = 0, ACC_FIRST = 1, ACC_ADD = 2, ACC_LAST = 3 };
+enum AccMode { ACC_WRITE = 0, ACC_FIRST = 1, ACC_ADD = 2, ACC_LAST = 3, ACC_OUT_ADD = 4 };
 
 // One independent 1D convolution of a batched plan: its own inputs, output
 // and length (all rows of a launch share m, p, q).
@@ -122,6 +124,7 @@ struct ColFwdArgs {
   int ctr;   // 1: centered rows
   int fold;  // 1: two blocks per column position (centered, p below the span)
   int herm;  // 1: Hermitian rows
+  int pair;  // 1: residues v and n - v taken together (conjugate symmetry; block of all n residues)
   FftDesc fd;  // p points
   const cpx<T>* fft_tw;  // two-level table of zeta for fd.N (lo then hi)
   const cpx<T>* zq;  // zeta_q^k, k < q
@@ -222,6 +225,8 @@ struct OuterLeanArgs {
   int64_t R;                        // columns per plane (contiguous)
   uint32_t L;                       // length of the transformed dimension (<= m)
   int q;                            // residues
+  int r0, D;                        // residues r0 .. r0+D-1 of this launch (level planes b D + dr)
+  int add;                          // backward: add to the output (later residue blocks)
   T scale;                          // backward: 1/(q m)
   FftDesc fd;                       // m points (the kernel reads its per-stage twiddle tables)
   const cpx<T>* fft_tw;
@@ -240,6 +245,44 @@ struct BoxCopyArgs {
   int pad;             // 1: dst (N box) <- src (L box) with zeros; 0: dst (L box) <- src (N box)
   int herm;            // padding of a Hermitian array (stored box L, last axis c = 0 .. hH):
   int64_t hH;          // the expanded centered box, F(k, -c) = conj F(-k, c)
+};
+
+// Persistent batched execution (hd_k_batch.hip): launches of resident
+// workgroups over device task tables.  Convolutions of one size bucket share
+// a shape: whole rows (direct form, p = 1, the lean row body) or the inner
+// form (Sec. 6.1: column pass, row pass, back pass, each task a range of
+// units of one convolution); one launch per pass.
+constexpr int kBatchThreads = 256;  // threads of the persistent workgroup
+enum BatchKind { BK_ROWS = 0, BK_COLF = 1, BK_ROWP = 2, BK_COLB = 3 };
+
+template <typename T>
+struct BatchBucket {
+  int inner;        // 0: whole rows; 1: inner form
+  int body;         // compiled body of the bucket's shape (hd_k_batch.hip)
+  int m, p, n, q;   // shape shared by the bucket's convolutions (D = n)
+  int S;            // inner form: columns per column-pass unit
+  T scale;          // 1/(q m)
+  const cpx<T>* tw_m;  // per-stage twiddles of the m-point transform
+  const cpx<T>* tw_p;  // per-stage twiddles of the p-point transform (inner form)
+  int ntw_m, ntw_p;    // their words
+  const cpx<T>* zq;    // zeta_q^k, k < q (inner form)
+  RootTable<T> zqm;    // powers of zeta_{qm}
+  const RowTask<T>* rows;  // per convolution: inputs, output, length
+  cpx<T>* work[kMaxA];     // inner form: input a of convolution c, row j = v p + u, at work[a][(c q + j) m]
+};
+
+struct BatchTask {
+  int bucket, kind;  // BatchKind
+  int conv;          // whole rows: first convolution of the task; else the convolution
+  int u0, nu;        // units [u0, u0 + nu): rows (whole rows, row pass), (input, column tile) or column tiles
+};
+
+template <typename T>
+struct BatchArgs {
+  const BatchBucket<T>* buckets;
+  const BatchTask* tasks;  // this launch's table
+  int ntasks;
+  int xwords;  // LDS words of the largest exchange area (the tables follow)
 };
 
 // Launchers (return the launch status).  E, P and A select the template
@@ -269,6 +312,18 @@ template <typename T>
 hipError_t launch_outer_bwd(const OuterBwdArgs<T>& a, int E, int P, hipStream_t s);
 template <typename T>
 hipError_t launch_box_copy(const BoxCopyArgs<T>& a, hipStream_t s);
+// The persistent batched kernel for A inputs with `grid` workgroups and
+// `lds` bytes of LDS.  batch_shape() names the compiled body of a bucket
+// shape (false: none) and the points per lane and columns it uses;
+// batch_lds_words() its LDS words (exchange area, tables of its largest
+// kind); batch_grid_t() the resident workgroups of the instance on `cus`
+// compute units.
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T>& a, int A, int grid, size_t lds, hipStream_t s);
+bool batch_shape(int inner, int64_t m, int64_t p, int tbytes, int* body, int* E_m, int* E_p, int* S);
+void batch_lds_words(int body, int m, int p, int q, int ntw_m, int ntw_p, int tbytes, int* xwords, int* twords);
+template <typename T>
+int batch_grid_t(int A, size_t lds, int cus);
 
 // LDS bytes each launcher requests (host-side sizing and validation).
 size_t lds_fused1d(int m, int ps, int rows_per_block, int A, int ntw, int tbytes);

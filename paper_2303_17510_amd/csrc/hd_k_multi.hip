@@ -81,6 +81,40 @@ __device__ __forceinline__ void cols_fwd_residues(const ColFwdArgs<T>& a, const 
   }
 }
 
+// Conjugate-symmetry pairing (the paper's conjugate symmetry optimization,
+// complex case): residue n - v needs the p-point DFT of
+// zeta_q^{(n-v)t} f_t = zeta_p^t conj(zeta_q^{vt}) f_t, i.e. at frequency u
+// the DFT of conj(zeta_q^{vt}) f_t at u + 1.  So the twiddles of residue v
+// serve both: W'_t = conj(z_t) x_t is transformed and its frequency u is
+// stored as frequency u - 1 (mod p) of residue n - v.  For v = n - v (v = 0
+// or n/2) the pair is the residue alone.  Ordinary rows only (no centered
+// shift, no folding), a block of all n residues.
+template <typename T, int E>
+__device__ __forceinline__ void cols_fwd_pair(const ColFwdArgs<T>& a, const cpx<T> (&x)[E], int v, int g, int s,
+                                              int64_t row, int ai, const TwLds<T>& tw, const Xchg<T>& xb) {
+  const int G = a.fd.G, m = a.m, p = a.p, n = a.q / a.p;
+  const int v2 = v == 0 ? 0 : n - v;
+  cpx<T> y[1][E], y2[1][E];
+  zq_run<E>(a.zq, v, g, G, a.q, [&](int e, cpx<T> z) {
+    y[0][e] = cmul(x[e], z);
+    y2[0][e] = cmulc(x[e], z);
+  });
+  gfft_any<T, E, +1, 1, (sizeof(T) == 4 ? kCtCols : 0u)>(y, g, a.fd, tw, xb);
+  {
+    cpx<T>* dst = a.work[ai] + ((row * a.D + (v - a.v0)) * p) * (int64_t)m + s;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[(int64_t)(g + G * e) * m] = y[0][e];
+  }
+  if (v2 == v) return;
+  gfft_any<T, E, +1, 1, (sizeof(T) == 4 ? kCtCols : 0u)>(y2, g, a.fd, tw, xb);
+  cpx<T>* dst = a.work[ai] + ((row * a.D + (v2 - a.v0)) * p) * (int64_t)m + s;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int u = g + G * e;
+    dst[(int64_t)(u ? u - 1 : p - 1) * m] = y2[0][e];
+  }
+}
+
 // Grid x enumerates (row, column tile) pairs, column tiles fastest, so the
 // row count is not bound by the grid's y limit.
 template <typename T, int E, bool FOLD>
@@ -118,6 +152,14 @@ __global__ void __launch_bounds__(512) k_cols_fwd(ColFwdArgs<T> a) {
     }
   }
   __syncthreads();
+  if constexpr (!FOLD) {
+    if (a.pair) {
+      // residues v and n - v together (v <= n/2; the block holds all n)
+      const int n = a.q / a.p;
+      for (int v = 0; 2 * v <= n; ++v) cols_fwd_pair<T, E>(a, x, v, g, s, row, ai, tw, xb);
+      return;
+    }
+  }
   // FP32 transforms one residue at a time (fewer registers, twice the
   // resident workgroups: measured faster); FP64 two at a time.
   constexpr int NT = sizeof(T) == 4 ? 1 : 2;

@@ -124,6 +124,8 @@ __device__ __forceinline__ void acc_store(cpx<T>* out, double* acc, int mode, in
   } else if (mode == ACC_ADD) {
     acc[2 * i] += (double)v.x;
     acc[2 * i + 1] += (double)v.y;
+  } else if (mode == ACC_OUT_ADD) {
+    out[i] = out[i] + cscale(v, scale);
   } else {
     const double sx = acc[2 * i] + (double)v.x, sy = acc[2 * i + 1] + (double)v.y;
     out[i] = mk(T(sx * (double)scale), T(sy * (double)scale));

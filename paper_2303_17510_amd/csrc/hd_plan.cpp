@@ -300,7 +300,7 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
     case VAR_OUTER: {
       if (dp->p > 2) return fail("outer variant needs p <= 2");
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
-      if (dp->D != dp->n) return fail("outer variant processes all residues");
+      if (dp->D < 1 || dp->D > dp->n) return fail("outer variant needs 1 <= D <= q residues per block");
       if (dp->m < 8) return fail("outer variant needs m >= 8");
       if (dp->E_m == 0 && !pick_e_outer(dp->m, dp->p, dp->ctr != 0, tbytes, &dp->E_m)) return fail("unsupported m for the outer kernel");
       if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("outer points per lane must be 4, 8, 12 or 16");

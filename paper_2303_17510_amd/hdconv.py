@@ -101,6 +101,10 @@ class Plan:
     extent), and so does the output; ``M`` defaults to the minimum padding.
     ``no_workspace``: the plan allocates no workspace and runs only through
     :meth:`execute_noalloc` (the library's static device scratch).
+    ``conj_pairs``: the inner form's forward column pass computes residues v
+    and n - v together (conjugate symmetry) where a block holds all residues.
+    ``accumulate_output``: residue blocks add into the output array instead
+    of an FP64 accumulation buffer (out of place only).
     ``mult="quadratic"`` with real coefficients ``coef`` of shape
     ``(B, A, A)``: B outputs, output b = sum_{i <= j} coef[b][i][j] F_i F_j
     pointwise in transform space (entries below the diagonal unused); the
@@ -113,7 +117,7 @@ class Plan:
                  twiddles=None, tuner: str = "heuristic", model=None, tune_reps: int = 0, margin: float = 0.0,
                  db_path: str | None = None, centered: bool = False, hermitian: bool = False,
                  copies: int = 1, dist: int = 0, strides=None, mult: str = "product", coef=None,
-                 no_workspace: bool = False):
+                 no_workspace: bool = False, conj_pairs: bool = True, accumulate_output: bool = False):
         L = (int(L),) if isinstance(L, int) else tuple(int(v) for v in L)
         dims = len(L)
         if mult not in ("product", "quadratic"):
@@ -129,8 +133,10 @@ class Plan:
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.method = _METHODS[method]
         opt.flags = ((_L.PLAN_HOST_ONLY if host_only else 0) | (_L.PLAN_CENTERED if centered else 0) |
-                     (_L.PLAN_HERMITIAN if hermitian else 0) | (_L.PLAN_NO_WORKSPACE if no_workspace else 0))
+                     (_L.PLAN_HERMITIAN if hermitian else 0) | (_L.PLAN_NO_WORKSPACE if no_workspace else 0) |
+                     (_L.PLAN_ACCUMULATE_OUTPUT if accumulate_output else 0))
         self.centered, self.hermitian = bool(centered), bool(hermitian)
+        opt.conj_pairs = 0 if conj_pairs else -1
         # shape of the arrays passed in and out
         self.io_shape = L[:-1] + ((L[-1] + 1) // 2,) if hermitian else L
         self.copies, self.dist = int(copies), int(dist)
@@ -300,13 +306,17 @@ class Plan:
 class BatchPlan:
     """Many independent 1D convolutions of uneven length ``Ls`` (each padded to ``Ms``).
 
-    Convolutions with the same planned shape form a group; each execute is one
-    hipGraph launch (from the second execute on, unless ``graph=False``).
+    Convolutions with the same planned shape form a group.  Ordinary batches
+    with the heuristic tuner run as persistent kernel launches over device
+    task tables, one per pass (``grouped=True``, tuned, centered and
+    Hermitian batches: one set of launches per group on side streams); each
+    execute is one hipGraph launch (from the second execute on, unless
+    ``graph=False``).
     """
 
     def __init__(self, Ls, Ms=None, A: int = 2, B: int = 1, dtype="c64", graph: bool = True,
                  tuner: str = "heuristic", model=None, tune_reps: int = 5, margin: float = 0.05,
-                 centered: bool = False, hermitian: bool = False):
+                 centered: bool = False, hermitian: bool = False, grouped: bool = False):
         Ls = [int(v) for v in Ls]
         if Ms is None:
             Ms = [hermitian_min_padding(v, A) if hermitian else
@@ -319,7 +329,7 @@ class BatchPlan:
         opt = _L.Options()
         _L.lib().hdconv_options_init(ctypes.byref(opt))
         opt.flags = ((0 if graph else _L.BATCH_NO_GRAPH) | (_L.PLAN_CENTERED if centered else 0) |
-                     (_L.PLAN_HERMITIAN if hermitian else 0))
+                     (_L.PLAN_HERMITIAN if hermitian else 0) | (_L.BATCH_GROUPED if grouped else 0))
         self.centered, self.hermitian = bool(centered), bool(hermitian)
         self.io_lengths = [(v + 1) // 2 for v in Ls] if hermitian else list(Ls)
         opt.tuner = {"heuristic": _L.TUNER_HEURISTIC, "exhaustive": _L.TUNER_EXHAUSTIVE,
@@ -350,6 +360,13 @@ class BatchPlan:
                  "rows_per_block": arr[g].rows_per_block, "count": cnt[g], "Lmax": arr[g].L,
                  "centered": bool(arr[g].centered), "hermitian": arr[g].centered == 2}
                 for g in range(min(ng.value, cap))]
+
+    def stats(self) -> dict:
+        """Launch shape: persistent (one launch) or grouped, and its sizes."""
+        st = _L.BatchStats()
+        _L.check(_L.lib().hdconv_batch_stats(self._h, ctypes.byref(st)))
+        return {"persistent": bool(st.persistent), "grid": st.grid, "tasks": st.tasks, "lds_bytes": st.lds_bytes,
+                "work_bytes": st.work_bytes}
 
     def bind(self, inputs, outputs) -> "BoundBatch":
         """Validate the tensors once and keep their device pointers: executes
