@@ -205,10 +205,11 @@ typedef struct hdconv_plan_info {
  * for a problem the way the paper's optimizer decouples it (Sec. 7): the
  * default plan, and that plan with one dimension's shape replaced by each of
  * its candidates.  Candidate k is out[k*dims .. k*dims+dims); varied[k] is the
- * dimension it changes (-1 for the default plan).  Uncentered problems;
- * centered plans are tuned through hdconv_plan_ex with options.tuner.  Host
- * only. */
-int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+ * dimension it changes (-1 for the default plan).  flags: 0,
+ * HDCONV_PLAN_CENTERED or HDCONV_PLAN_HERMITIAN (L, M as hdconv_plan_ex
+ * takes them; the shapes then carry centered = 1, or 2 on the Hermitian
+ * dimension, which hdconv_time_shape and hdconv_features read).  Host only. */
+int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype, int flags,
                       hdconv_dim_info_t* out, int* varied, int cap, int* count);
 
 /* Median time in ms of `reps` executes (after one warm-up) of the plan whose
@@ -217,8 +218,9 @@ int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims
                       const hdconv_dim_info_t* shape, int reps, double* ms);
 
 /* Cost-model features of a candidate: HDCONV_NFEATURES floats describing the
- * problem and the shape (logs of lengths, sizes, traffic, work). */
-enum { HDCONV_NFEATURES = 44 };
+ * problem and the shape (logs of lengths, sizes, traffic, work; centered and
+ * Hermitian flags; dimensions on the lean kernels; the largest q). */
+enum { HDCONV_NFEATURES = 48 };
 int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                     const hdconv_dim_info_t* shape, float* out);
 

@@ -27,7 +27,7 @@ BATCH_GROUPED = 64
 SCRATCH_BYTES = 64 << 20  # static scratch of hdconv_execute_noalloc
 MULT_PRODUCT, MULT_QUADRATIC = 0, 1
 TUNER_HEURISTIC, TUNER_EXHAUSTIVE, TUNER_MODEL = 0, 1, 2
-NFEATURES = 44
+NFEATURES = 48
 
 VARIANT_NAMES = {0: "auto", 1: "fused", 2: "multipass", 3: "outer"}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENODEV"}
@@ -91,7 +91,7 @@ SIGNATURES = {
     "hdconv_centered_span": (_i64, [_i64, _i64]),
     "hdconv_min_padding": (ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64)]),
     "hdconv_candidates": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo),
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo),
                                          ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "hdconv_time_shape": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(DimInfo), ctypes.c_int,

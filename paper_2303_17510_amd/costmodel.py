@@ -30,17 +30,21 @@ from . import tune
 
 SEED_TRAIN = 17510500
 SEED_HELDOUT = 17510501
+SEED_FLAGGED = 17510502  # centered and Hermitian training geometries
+FLAG_MIX_FLAGGED = (0.5, 0.5)
+FLAG_MIX_HELDOUT = (0.15, 0.15)
+GID_FLAGGED = 100000     # geometry ids of the flagged list start here
 
 
-SHAPE_FIELDS = ("variant", "m", "p", "q", "E_m", "E_p", "S", "rows_per_block")
+SHAPE_FIELDS = ("variant", "m", "p", "q", "E_m", "E_p", "S", "rows_per_block", "centered")
 
 
 def _shape_rows(shape):
-    """Per-dimension shape fields as a 3 x 8 integer array (unused dimensions 0)."""
+    """Per-dimension shape fields as a 3 x 9 integer array (unused dimensions 0)."""
     out = np.zeros((3, len(SHAPE_FIELDS)), dtype=np.int64)
     for d, s in enumerate(shape):
         for k, f in enumerate(SHAPE_FIELDS):
-            v = s[f]
+            v = s.get(f, 0)
             if f == "variant":
                 v = {"fused": 1, "multipass": 2, "outer": 3}.get(v, v)
             out[d, k] = int(v)
@@ -49,8 +53,18 @@ def _shape_rows(shape):
 
 def _shape_of(rows, dims):
     names = {1: "fused", 2: "multipass", 3: "outer"}
-    return [{f: (names[int(rows[d, k])] if f == "variant" else int(rows[d, k])) for k, f in enumerate(SHAPE_FIELDS)}
-            for d in range(dims)]
+    return [{f: (names[int(rows[d, k])] if f == "variant" else int(rows[d, k]))
+             for k, f in enumerate(SHAPE_FIELDS) if k < rows.shape[1]} for d in range(dims)]
+
+
+def _widen(data):
+    """Shape rows of files written before the centered field: a zero column."""
+    sh = data["shape"]
+    if sh.shape[-1] < len(SHAPE_FIELDS):
+        pad = np.zeros(sh.shape[:-1] + (len(SHAPE_FIELDS) - sh.shape[-1],), dtype=sh.dtype)
+        data = dict(data)
+        data["shape"] = np.concatenate([sh, pad], axis=-1)
+    return data
 
 
 def refeature(data, dtype="c64"):
@@ -80,7 +94,7 @@ def collect(geoms, reps=3, dtype="c64", log=None, time_budget_s=None, ids=None):
             break
         gi = ids[i] if ids is not None else i
         try:
-            cands = tune.candidates(g["L"], g["M"], A=g["A"], dtype=dtype)
+            cands = tune.candidates(g["L"], g["M"], A=g["A"], dtype=dtype, flags=g.get("flags", 0))
         except Exception as e:  # no plan for this geometry
             if log:
                 log("geometry %d %s: no candidates (%s)" % (gi, g, e))
@@ -118,8 +132,8 @@ def save(data, path):
 
 
 def load(paths):
-    parts = [np.load(p, allow_pickle=False) for p in paths]
-    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0].files}
+    parts = [_widen({k: v for k, v in np.load(p, allow_pickle=False).items()}) for p in paths]
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
 def train(data, hidden=64, epochs=300, batch=256, lr=2e-3, seed=0):
@@ -185,13 +199,17 @@ def main(argv=None):
             L = [int(v) for v in dims_s.split(",")]
             geoms, sel = [{"L": L, "M": [int(A_s) * v for v in L], "A": int(A_s)}], [0]
         else:
-            geoms = tune.geometries(a.total, a.seed)
+            # the flagged and held-out lists mix in centered and Hermitian geometries
+            fm = {SEED_FLAGGED: FLAG_MIX_FLAGGED, SEED_HELDOUT: FLAG_MIX_HELDOUT}.get(a.seed, (0.0, 0.0))
+            geoms = tune.geometries(a.total, a.seed, flag_mix=fm)
             sel = list(range(a.start, min(a.total, a.start + a.count)))
-        d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None, ids=sel)
+        base = GID_FLAGGED if a.seed == SEED_FLAGGED else 0
+        d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None,
+                    ids=[base + i for i in sel])
         save(d, a.out)
         log("saved %d rows from %d geometries to %s" % (len(d["y"]), len(np.unique(d["gid"])), a.out))
     elif a.cmd == "refeature":
-        d = refeature({k: v for k, v in np.load(a.data, allow_pickle=False).items()})
+        d = refeature(_widen({k: v for k, v in np.load(a.data, allow_pickle=False).items()}))
         save(d, a.out)
         log("recomputed %d feature rows into %s" % (len(d["y"]), a.out))
     elif a.cmd == "train":

@@ -142,6 +142,9 @@ static int tbytes_of(int dtype) { return dtype == HDCONV_C64 ? 4 : 8; }
 // the centered array of length 2 ceil(L/2) - 1 the engine transforms.
 static int64_t herm_stored(int64_t L) { return (L + 1) / 2; }
 static int64_t herm_full(int64_t L) { return 2 * herm_stored(L) - 1; }
+// An outer dimension in the inner form (column passes of p points, then the
+// m-point pass; all q residues in one block).
+static bool outer_inner(const DimPlan& dp) { return dp.variant == VAR_OUTER && dp.p > 2; }
 
 static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                        const hdconv_options* opt, hdconv_dim_info_t* shp, int* ncand, int* ntimed, double* best_ms);
@@ -258,12 +261,22 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
       // a forced inner form without a forced m: rows of at most 4096 points
       // (the row pass's best size), the column count then follows from L
       if (!fm && fv == VAR_MULTI && m > 4096) m = 4096;
-      Geometry g = geometry_c(Le, Me, m, fp, fv == VAR_MULTI, ctr);
-      if (g.inner && fv != VAR_MULTI)
+      // an outer dimension takes the inner form when p > 2 (forced, or L > 2m)
+      const bool oin = fv == VAR_OUTER && (fp > 2 || cdiv(Le, m) > 2);
+      Geometry g = geometry_c(Le, Me, m, fp, fv == VAR_MULTI || oin, ctr);
+      if (g.inner && fv != VAR_MULTI && !oin)
         return set_err(HDCONV_EINVAL, "dim %d: m=%lld gives p=%lld > 2, which needs the multipass variant", d,
                        (long long)m, (long long)g.p);
       if (fv == VAR_MULTI && !col_size_ok(g.p)) {
         g = geometry_c(Le, Me, m, next_col_size(g.p), true, ctr);
+      }
+      if (oin) {  // the least compiled column size: 2^k, or 3 * 2^k from 12 (complex64)
+        int64_t p2 = 4;
+        while (p2 < g.p) p2 *= 2;
+        int64_t pc = p2;
+        for (int64_t p3 = 12; p3 <= 96 && tb == 4; p3 *= 2)
+          if (p3 >= g.p && p3 < pc) pc = p3;
+        if (pc != g.p) g = geometry_c(Le, Me, m, pc, true, ctr);
       }
       dp = DimPlan{};
       dp.L = Le;
@@ -292,6 +305,9 @@ static int build_dims(Plan* P, const hdconv_options* opt) {
   for (int d = 1; d + 1 < P->dims; ++d)
     if (P->dp[d].D < P->dp[d].n)
       return set_err(HDCONV_EUNSUPPORTED, "dim %d: residue blocks (D < q) apply to the first dimension only", d);
+  // the inner form of an outer dimension reads dense planes
+  if (P->dims > 1 && outer_inner(P->dp[0]) && (P->stride[0] || P->stride[1]))
+    return set_err(HDCONV_EUNSUPPORTED, "dim 0: the inner form of an outer dimension takes dense arrays (no strides)");
   return HDCONV_OK;
 }
 
@@ -410,6 +426,10 @@ static double plan_traffic(const Plan* P, int* launches) {
     const double nbk = d == 0 ? (double)blocks0 : 1.0;
     bytes += A * (nbk * in_el + out_el) * w + nout * (out_el + (2.0 * nbk - 1.0) * in_el) * w;  // forward + backward
     nl += (int)blocks0 * (groups + nout);
+    if (outer_inner(dp)) {  // the m-point passes read and write the level in place
+      bytes += 2.0 * (A + nout) * out_el * w;
+      nl += A + nout;
+    }
     nb *= (double)(dp.q * dp.m);
   }
   const DimPlan& dl = P->dp[P->dims - 1];
@@ -454,7 +474,7 @@ static int alloc_tables(Plan* P) {
     DimPlan& dp = P->dp[d];
     parts.push_back(fft_table(dp.fd_m));
     refs.push_back({d, 0});
-    if (dp.variant == VAR_MULTI) {
+    if (dp.variant == VAR_MULTI || (dp.variant == VAR_OUTER && dp.p > 2)) {
       parts.push_back(fft_table(dp.fd_p));
       refs.push_back({d, 1});
       std::vector<double> zq(2 * dp.q);
@@ -528,7 +548,8 @@ static std::vector<std::pair<void**, size_t>> workspace_parts(Plan* P) {
     size_t rest = 1;
     for (int e = d + 1; e < P->dims; ++e) rest *= (size_t)stored_extent(P->dp[e]);
     // the first outer dimension holds one block of D residues at a time
-    nb *= (size_t)((d == 0 ? P->dp[d].D : P->dp[d].q) * P->dp[d].m);
+    // (the inner form: all of them)
+    nb *= (size_t)((d == 0 && !outer_inner(P->dp[d]) ? P->dp[d].D : P->dp[d].q) * P->dp[d].m);
     for (int a = 0; a < P->A; ++a) want.push_back({&P->lvl[d][a], nb * rest * w});
   }
   const DimPlan& dl = P->dp[P->dims - 1];
@@ -894,7 +915,7 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
   const cpx<T>* cur0[kMaxIn];
   for (int a = 0; a < A; ++a) cur0[a] = cur[a];
   const int64_t q0 = P->dims > 1 ? P->dp[0].q : 1;
-  const int64_t D0 = P->dims > 1 ? P->dp[0].D : 1;
+  const int64_t D0 = P->dims > 1 ? (outer_inner(P->dp[0]) ? q0 : P->dp[0].D) : 1;
   for (int64_t r0 = 0; r0 < q0; r0 += D0) {
   const int Db = (int)std::min<int64_t>(D0, q0 - r0);
   for (int a = 0; a < A; ++a) cur[a] = cur0[a];
@@ -909,6 +930,53 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
     for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
     // the lean outer kernel for ordinary dimensions of one block over dense planes
     const bool dense = d > 0 || (user.jstride == 0 && user.cgrp == 0);
+    if (outer_inner(dp)) {
+      // the inner form: column passes into the level, then the m-point pass in place
+      if (!dense) return set_err(HDCONV_EUNSUPPORTED, "the inner form of an outer dimension takes dense arrays");
+      for (int g0 = 0; g0 < A; g0 += kMaxA) {
+        const int na = std::min(kMaxA, A - g0);
+        OuterColArgs<T> o{};
+        OuterLeanArgs<T> r{};
+        for (int a = 0; a < na; ++a) {
+          o.in[a] = cur[g0 + a];
+          o.out[a] = r.out[a] = (cpx<T>*)P->lvl[d][g0 + a];
+          r.in[a] = o.out[a];
+        }
+        o.na = r.na = na;
+        o.nb = nb;
+        o.in_bstride = d == 0 ? dist : Le[d] * rest;
+        o.R = r.R = rest;
+        o.L = Le[d];
+        o.m = (int)dp.m;
+        o.n = (int)dp.n;
+        o.fd = dp.fd_p;
+        o.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+        o.zq = (const cpx<T>*)P->dd[d].zq;
+        const double lvl_el = (double)nb * dp.q * dp.m * rest;
+        {
+          ProfScope ps(P, s, "outer_cols_fwd", ((double)nb * Le[d] * rest + lvl_el) * na * 2.0 * sizeof(T));
+          e = launch_outer_cols<T>(o, (int)dp.p, true, P->cus, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "outer_cols_fwd launch");
+        r.nb = nb * dp.q;
+        r.in_bstride = dp.m * rest;
+        r.L = (uint32_t)dp.m;
+        r.q = (int)dp.q;
+        r.D = 1;
+        r.inner_n = (int)dp.n;
+        r.fd = dp.fd_m;
+        r.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+        r.zqm = rtab<T>(P, d);
+        {
+          ProfScope ps(P, s, "outer_rows_fwd", 2.0 * lvl_el * na * 2.0 * sizeof(T));
+          e = launch_outer_lean<T>(r, dp.E_m, dp.S, true, P->cus, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "outer_rows_fwd launch");
+      }
+      for (int a = 0; a < A; ++a) cur[a] = (const cpx<T>*)P->lvl[d][a];
+      nb *= dp.q * dp.m;
+      continue;
+    }
     const bool lean = dense && !dp.ctr && dp.p <= 2 && outer_lean_supported((int)dp.m, dp.E_m, dp.S, (int)dp.q, (int)sizeof(T));
     for (int g0 = 0; g0 < A && lean; g0 += kMaxA) {
       const int na = std::min(kMaxA, A - g0);
@@ -990,6 +1058,50 @@ static int run_copies(Plan* P, const void* const* inputs, void* const* outputs, 
       int64_t rest = 1;
       for (int k = d + 1; k < P->dims; ++k) rest *= stored_extent(P->dp[k]);
       const bool dense = d > 0 || (user.jstride == 0 && user.cgrp == 0);
+      if (outer_inner(dp)) {
+        // the m-point pass in place over the level, then the column pass into the output
+        OuterLeanArgs<T> r{};
+        r.in[0] = yl;
+        r.out[0] = (cpx<T>*)yl;
+        r.nb = nb * dp.q;
+        r.out_bstride = dp.m * rest;
+        r.R = rest;
+        r.L = (uint32_t)dp.m;
+        r.q = (int)dp.q;
+        r.D = 1;
+        r.inner_n = (int)dp.n;
+        r.scale = (T)1;
+        r.fd = dp.fd_m;
+        r.fft_tw = (const cpx<T>*)P->dd[d].fft_m;
+        r.zqm = rtab<T>(P, d);
+        const double lvl_el = (double)nb * dp.q * dp.m * rest;
+        {
+          ProfScope ps(P, s, "outer_rows_bwd", 2.0 * lvl_el * 2.0 * sizeof(T));
+          e = launch_outer_lean<T>(r, dp.E_m, dp.S, false, P->cus, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "outer_rows_bwd launch");
+        OuterColArgs<T> o{};
+        o.in[0] = yl;
+        o.out[0] = d == 0 ? final_out : (cpx<T>*)P->lvl[d - 1][0];
+        o.nb = nb;
+        o.out_bstride = d == 0 ? dist : Le[d] * rest;
+        o.R = rest;
+        o.L = Le[d];
+        o.m = (int)dp.m;
+        o.n = (int)dp.n;
+        o.add = add ? 1 : 0;
+        o.scale = (T)(1.0 / ((double)dp.q * (double)dp.m));
+        o.fd = dp.fd_p;
+        o.fft_tw = (const cpx<T>*)P->dd[d].fft_p;
+        o.zq = (const cpx<T>*)P->dd[d].zq;
+        {
+          ProfScope ps(P, s, "outer_cols_bwd", (lvl_el + (add ? 2.0 : 1.0) * (double)nb * Le[d] * rest) * 2.0 * sizeof(T));
+          e = launch_outer_cols<T>(o, (int)dp.p, false, P->cus, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "outer_cols_bwd launch");
+        yl = o.out[0];
+        continue;
+      }
       if (dense && !dp.ctr && dp.p <= 2 && outer_lean_supported((int)dp.m, dp.E_m, dp.S, (int)dp.q, (int)sizeof(T))) {
         OuterLeanArgs<T> o{};
         o.in[0] = yl;
@@ -1326,8 +1438,8 @@ hdconv_plan_t hdconv_plan_ex(const int64_t* L, const int64_t* M, int A, int B, i
   if (rc == HDCONV_OK) rc = size_workspace(P);
   // over the workspace cap: fewer residues per block of the first outer
   // dimension (Sec. 5's buffer reuse), unless the caller fixed D there
-  while (rc == HDCONV_ENOMEM && P->dims > 1 && P->dp[0].variant == VAR_OUTER && P->dp[0].D > 1 &&
-         !(opt && opt->D[0] > 0)) {
+  while (rc == HDCONV_ENOMEM && P->dims > 1 && P->dp[0].variant == VAR_OUTER && P->dp[0].p <= 2 &&
+         P->dp[0].D > 1 && !(opt && opt->D[0] > 0)) {
     P->dp[0].D = (P->dp[0].D + 1) / 2;
     clear_err();
     rc = size_workspace(P);
@@ -1781,15 +1893,24 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
 
 extern "C" {
 
-int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
+int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype, int flags,
                       hdconv_dim_info_t* out, int* varied, int cap, int* count) {
   clear_err();
   if (!L || !M || dims < 1 || dims > 3 || A < 2 || A > 3 || B != 1 || (dtype != HDCONV_C64 && dtype != HDCONV_C128))
     return set_err(HDCONV_EINVAL, "invalid problem");
+  if (flags & ~(HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN))
+    return set_err(HDCONV_EINVAL, "flags: HDCONV_PLAN_CENTERED or HDCONV_PLAN_HERMITIAN only");
+  // candidates are shapes of the engine's lengths (Hermitian: the full
+  // centered length of the last dimension), as the plan tuner lists them
+  const bool herm = (flags & HDCONV_PLAN_HERMITIAN) != 0;
+  int64_t Lc[3];
+  for (int d = 0; d < dims; ++d) Lc[d] = (herm && d == dims - 1) ? herm_full(L[d]) : L[d];
   std::vector<hdconv_dim_info_t> cand;
   std::vector<int> var;
-  int rc = list_candidates(L, M, A, dims, dtype, 0, &cand, &var);
+  int rc = list_candidates(Lc, M, A, dims, dtype, flags ? 1 : 0, &cand, &var);
   if (rc != HDCONV_OK) return rc;
+  if (herm)
+    for (size_t k = 0; k < cand.size(); k += dims) cand[k + dims - 1].centered = 2;
   if (count) *count = (int)var.size();
   for (int k = 0; k < (int)var.size() && k < cap; ++k) {
     if (out)
@@ -1858,6 +1979,24 @@ int hdconv_features(const int64_t* L, const int64_t* M, int A, int B, int dims, 
   out[11] = lg((double)launches);
   out[12] = lg(work);
   out[43] = lg((double)P->work_bytes + 1.0);
+  // centered / Hermitian problem, dimensions on the lean kernels (one
+  // block, ordinary dimension, compiled size and width), largest q
+  out[44] = (P->flags & (HDCONV_PLAN_CENTERED | HDCONV_PLAN_HERMITIAN)) ? 1.f : 0.f;
+  out[45] = (P->flags & HDCONV_PLAN_HERMITIAN) ? 1.f : 0.f;
+  {
+    int nlean = 0;
+    double qmax = 1;
+    const int tb = tbytes_of(P->dtype);
+    for (int d = 0; d < dims; ++d) {
+      const DimPlan& dp = P->dp[d];
+      qmax = std::max(qmax, (double)dp.q);
+      if (dp.ctr || dp.herm || dp.p > 2) continue;
+      if (dp.variant == VAR_OUTER && outer_lean_supported((int)dp.m, dp.E_m, dp.S, (int)dp.q, tb)) ++nlean;
+      if (dp.variant == VAR_FUSED && rows_lean_supported((int)dp.m, dp.E_m, A, (int)dp.q, tb)) ++nlean;
+    }
+    out[46] = (float)nlean;
+    out[47] = lg(qmax);
+  }
   hdconv_destroy((hdconv_plan_t)P);
   return HDCONV_OK;
 }

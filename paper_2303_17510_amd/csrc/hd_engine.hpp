@@ -231,6 +231,30 @@ struct OuterLeanArgs {
   FftDesc fd;                       // m points (the kernel reads its per-stage twiddle tables)
   const cpx<T>* fft_tw;
   RootTable<T> zqm;
+  int inner_n;  // 0: direct form; n: the inner form's m-point pass (plane b is row j = b mod q of its
+                // convolution, residue (j mod p) n + j div p, p = q / n; D = 1, in place)
+};
+
+// Outer dimension in the inner form (Sec. 6.1 with Sec. 5), column passes,
+// dense planes [nb][L][R]:
+//   forward:  out[a][((b q + v p + u) m + s) R + c] = sum_t zeta_p^{ut} zeta_q^{vt} in[a][b][t m + s][c]
+//   backward: out[b][t m + s][c] (+)= scale sum_v zeta_q^{-vt} sum_u zeta_p^{-ut} in[0][((b q + v p + u) m + s) R + c]
+// (the m-point transforms between them run on the lean outer kernel).
+template <typename T>
+struct OuterColArgs {
+  const cpx<T>* in[kMaxA];
+  cpx<T>* out[kMaxA];
+  int na;                           // forward: inputs of this launch
+  int64_t nb;                       // planes
+  int64_t in_bstride, out_bstride;  // words between planes of the user-side array (fwd: in, bwd: out)
+  int64_t R;                        // columns per plane (contiguous)
+  int64_t L;                        // length of the dimension (<= p m)
+  int m, n;                         // block length, residue blocks (q = n p)
+  int add;                          // backward: add to the output
+  T scale;                          // backward: 1/(q m)
+  FftDesc fd;                       // p points (per-stage twiddle tables follow the two-level one)
+  const cpx<T>* fft_tw;
+  const cpx<T>* zq;                 // zeta_q^k, k < q
 };
 
 // Zero padding / truncation copies between a dense box L[0..2] and a dense
@@ -294,8 +318,13 @@ hipError_t launch_rows_lean(const LeanRowArgs<T>& a, int E, int A, int cus, hipS
 template <typename T>
 hipError_t launch_outer_lean(const OuterLeanArgs<T>& a, int E, int S, bool fwd, int cus, hipStream_t s);
 // Sizes, points per lane and columns per workgroup the lean outer kernel is
-// built for (tbytes: bytes of a real word).
-bool outer_lean_supported(int m, int E, int S, int q, int tbytes);
+// built for (tbytes: bytes of a real word); inner: the inner form's m-point
+// pass (any q).
+bool outer_lean_supported(int m, int E, int S, int q, int tbytes, bool inner = false);
+// The column passes of an outer dimension in the inner form.
+template <typename T>
+hipError_t launch_outer_cols(const OuterColArgs<T>& a, int p, bool fwd, int cus, hipStream_t s);
+bool outer_cols_supported(int p, int E, int tbytes);
 // Sizes, points per lane, input and residue counts the lean row kernel is
 // built for.
 constexpr int kLeanMaxQ = 8;

@@ -19,6 +19,7 @@
 //  * a workgroup loops over rows (the grid is sized to the resident
 //    workgroups), so its tables are staged into LDS once.
 #include "hd_lean.hpp"
+#include "hd_plan.hpp"
 
 namespace hd {
 
@@ -169,15 +170,160 @@ __global__ void __launch_bounds__(S*(N / E), WAVES) k_outer_lean(OuterLeanArgs<T
   }
 }
 
+// Outer dimension in the inner form, the m-point pass over dense planes of
+// m rows (plane b is row j = b mod q of its transform, residue
+// r = (j mod p) n + j div p): forward W = fft_m(zeta_{qm}^{r s} y_s), backward
+// y_s = zeta_{qm}^{-r s} ifft_m(W)_s, in place.  Layout and lanes as in
+// k_outer_lean; the residue twiddles come from the two-level table (one
+// residue per plane).
+template <typename T, int N, int E, int S, bool FWD, int WAVES>
+__global__ void __launch_bounds__(S*(N / E), WAVES) k_outer_inner_rows(OuterLeanArgs<T> a) {
+  constexpr int G = N / E;
+  constexpr int NT = S * G;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int q = a.q, n = a.inner_n, p = q / n;
+  const int64_t R = a.R;
+  cpx<T>* lds = smem_as<T>();
+  cpx<T>* xr = lds + c;       // point i of this column at xr[i S]
+  cpx<T>* twl = lds + N * S;  // per-stage FFT twiddles
+  {
+    const cpx<T>* st = a.fft_tw + a.fd.ntw;
+    for (int i = threadIdx.x; i < a.fd.ntw_stage; i += NT) twl[i] = st[i];
+  }
+  __syncthreads();
+  const int64_t tiles = (R + S - 1) / S;
+  const int64_t units = tiles * a.nb * (FWD ? a.na : 1);
+  const int64_t GR = (int64_t)G * R;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t ct = u % tiles;
+    const int64_t rest = u / tiles;
+    const int64_t b = rest % a.nb;
+    const int ai = FWD ? (int)(rest / a.nb) : 0;
+    const int64_t col = ct * S + c;
+    const bool valid = col < R;
+    const int64_t colc = valid ? col : R - 1;
+    const int j = (int)(b % q);
+    const uint32_t r = (uint32_t)((j % p) * n + j / p);
+    const int64_t base = b * (int64_t)N * R + (int64_t)g * R;
+    const cpx<T>* src = a.in[ai] + base + colc;
+    cpx<T> y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = src[e * GR];
+    if constexpr (FWD) {
+      a.zqm.template run<E>(r * (uint32_t)g, r * (uint32_t)G, [&](int e, cpx<T> z) { y[e] = cmul(y[e], z); });
+      lean_fft<T, N, E, +1, S, false>(y, g, xr, twl);
+    } else {
+      lean_fft<T, N, E, -1, S, false>(y, g, xr, twl);
+      a.zqm.template run<E>(r * (uint32_t)g, r * (uint32_t)G, [&](int e, cpx<T> z) { y[e] = cmulc(y[e], z); });
+    }
+    if (valid) {
+      cpx<T>* dst = a.out[ai] + base + col;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[e * GR] = y[e];
+    }
+  }
+}
+
+// Outer dimension in the inner form, the column passes (see OuterColArgs):
+// S adjacent columns of one block offset s per unit, lanes of a column S
+// apart, the p-point transforms interleaved in LDS.  Units are (input,
+// plane, s, column tile), column tiles fastest.
+template <typename T, int P, int E, int S, bool FWD, int WAVES>
+__global__ void __launch_bounds__(S*(P / E), WAVES) k_outer_cols(OuterColArgs<T> a) {
+  constexpr int G = P / E;
+  constexpr int NT = S * G;
+  const int c = threadIdx.x % S;
+  const int g = threadIdx.x / S;
+  const int m = a.m, n = a.n, q = n * P;
+  const int64_t R = a.R;
+  cpx<T>* lds = smem_as<T>();
+  cpx<T>* xc = lds + c;       // point t of this column at xc[t S]
+  cpx<T>* twl = lds + P * S;  // per-stage twiddles of the p-point transform
+  cpx<T>* zq = twl + a.fd.ntw_stage;
+  {
+    const cpx<T>* st = a.fft_tw + a.fd.ntw;
+    for (int i = threadIdx.x; i < a.fd.ntw_stage; i += NT) twl[i] = st[i];
+    for (int i = threadIdx.x; i < q; i += NT) zq[i] = a.zq[i];
+  }
+  __syncthreads();
+  const int64_t tiles = (R + S - 1) / S;
+  const int64_t units = tiles * m * a.nb * (FWD ? a.na : 1);
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t ct = u % tiles;
+    int64_t rest = u / tiles;
+    const int s = (int)(rest % m);
+    rest /= m;
+    const int64_t b = rest % a.nb;
+    const int ai = FWD ? (int)(rest / a.nb) : 0;
+    const int64_t col = ct * S + c;
+    const bool valid = col < R;
+    const int64_t colc = valid ? col : R - 1;
+    if constexpr (FWD) {
+      const cpx<T>* src = a.in[ai] + b * a.in_bstride + colc;
+      cpx<T> x[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t i = (int64_t)(g + G * e) * m + s;
+        const cpx<T> v = src[(i < a.L ? i : a.L - 1) * R];  // no branch: beyond L reads the last point
+        x[e] = i < a.L ? v : czero<T>();
+      }
+      for (int v = 0; v < n; ++v) {
+        cpx<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = cmul(x[e], zq[v * (g + G * e)]);  // v t < n p = q
+        lean_fft<T, P, E, +1, S, false>(y, g, xc, twl);
+        if (valid) {
+          cpx<T>* dst = a.out[ai] + ((b * q + v * P + g) * (int64_t)m + s) * R + col;
+#pragma unroll
+          for (int e = 0; e < E; ++e) dst[(int64_t)G * e * m * R] = y[e];
+        }
+      }
+    } else {
+      cpx<T> acc[E];
+      for (int v = 0; v < n; ++v) {
+        const cpx<T>* src = a.in[0] + ((b * q + v * P + g) * (int64_t)m + s) * R + colc;
+        cpx<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = src[(int64_t)G * e * m * R];
+        lean_fft<T, P, E, -1, S, false>(y, g, xc, twl);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const cpx<T> z = cmulc(y[e], zq[v * (g + G * e)]);
+          acc[e] = v == 0 ? z : acc[e] + z;
+        }
+      }
+      if (valid) {
+        cpx<T>* dst = a.out[0] + b * a.out_bstride + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int64_t i = (int64_t)(g + G * e) * m + s;
+          if (i < a.L) {
+            cpx<T> v = cscale(acc[e], a.scale);
+            if (a.add) v = v + dst[i * R];
+            dst[i * R] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 #if !defined(HD_PART) || HD_PART == 1  // host helpers, in one object only
 // Points per lane built for each precision: 8 and 16 in FP32, 4 and 8 in
 // FP64 (the same register footprint).
 static bool lean_e_ok(int E, int tbytes) { return tbytes == 4 ? (E == 8 || E == 16) : (E == 4 || E == 8); }
 
-bool outer_lean_supported(int m, int E, int S, int q, int tbytes) {
-  if (q < 1 || q > kLeanMaxQ || !lean_e_ok(E, tbytes) || (S != 8 && S != 16)) return false;
+bool outer_lean_supported(int m, int E, int S, int q, int tbytes, bool inner) {
+  if (q < 1 || (!inner && q > kLeanMaxQ) || !lean_e_ok(E, tbytes) || (S != 8 && S != 16)) return false;
   if (m != 64 && m != 128 && m != 256 && m != 512 && m != 1024) return false;
   return S * (m / E) <= 1024 && (size_t)S * m * 16 <= 128 * 1024;  // threads; exchange area (FP64 words)
+}
+
+bool outer_cols_supported(int p, int E, int tbytes) {
+  const bool p2 = p >= 4 && p <= 64 && (p & (p - 1)) == 0;
+  const bool p3 = tbytes == 4 && p % 3 == 0 && p >= 12 && p <= 96 && ((p / 3) & (p / 3 - 1)) == 0;
+  return (p2 || p3) && E == outer_col_e(p, tbytes);
 }
 
 bool rows_lean_supported(int m, int E, int A, int q, int tbytes) {
@@ -244,6 +390,58 @@ static hipError_t go_outer_lean(const OuterLeanArgs<T>& a, int cus, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T, int N, int E, int S, bool FWD>
+static hipError_t go_outer_inner_rows(const OuterLeanArgs<T>& a, int cus, hipStream_t s) {
+  constexpr int nt = S * (N / E);
+  const size_t lds = ((size_t)N * S + a.fd.ntw_stage) * sizeof(cpx<T>);
+  auto k = k_outer_inner_rows<T, N, E, S, FWD, lean_waves<T, E>()>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  const int64_t units = ((a.R + S - 1) / S) * a.nb * (FWD ? a.na : 1);
+  const int64_t cap = (int64_t)cus * lean_resident(k, nt, lds);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(units, cap));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, a);
+  return hipGetLastError();
+}
+
+// Points per lane of the column transforms, at compile time.
+template <typename T, int P>
+constexpr int ocol_e() {
+  return P % 3 == 0 ? 12 : (P <= 4 ? P : (sizeof(T) == 4 ? 8 : 4));
+}
+
+template <typename T, int P, bool FWD>
+static hipError_t go_outer_cols(const OuterColArgs<T>& a, int cus, hipStream_t s) {
+  constexpr int E = ocol_e<T, P>();
+  constexpr int S = 256 / (P / E);
+  constexpr int nt = S * (P / E);
+  const int q = a.n * P;
+  const size_t lds = ((size_t)P * S + a.fd.ntw_stage + q) * sizeof(cpx<T>);
+  auto k = k_outer_cols<T, P, E, S, FWD, 3>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  const int64_t units = ((a.R + S - 1) / S) * a.m * a.nb * (FWD ? a.na : 1);
+  const int64_t cap = (int64_t)cus * lean_resident(k, nt, lds);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(units, cap));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_outer_cols(const OuterColArgs<T>& a, int p, bool fwd, int cus, hipStream_t s) {
+  if (!outer_cols_supported(p, a.fd.G ? p / a.fd.G : 0, (int)sizeof(T)) || a.fd.N != p || a.m < 1 || a.n < 1 ||
+      a.R < 1 || a.nb < 1 || a.L < 1 || a.L > (int64_t)p * a.m || (fwd && (a.na < 1 || a.na > kMaxA)))
+    return HD_BAD;
+#define OC(PP)                                                                                   \
+  if (p == PP) {                                                                                 \
+    if constexpr (PP % 3 != 0 || sizeof(T) == 4)                                                 \
+      return fwd ? go_outer_cols<T, PP, true>(a, cus, s) : go_outer_cols<T, PP, false>(a, cus, s); \
+  }
+  OC(4) OC(8) OC(16) OC(32) OC(64) OC(12) OC(24) OC(48) OC(96)
+#undef OC
+  return HD_BAD;
+}
+
 // The same at compile time.
 template <typename T>
 constexpr bool lean_e_built(int E) {
@@ -254,6 +452,23 @@ constexpr bool lean_e_built(int E) {
 template <typename T>
 hipError_t launch_outer_lean(const OuterLeanArgs<T>& a, int E, int S, bool fwd, int cus, hipStream_t s) {
   const int N = a.fd.N;
+  if (a.inner_n) {
+    // the inner form's m-point pass: full planes of N rows, one residue each
+    if (!outer_lean_supported(N, E, S, a.q, (int)sizeof(T), true) || a.fd.G * E != N || a.L != (uint32_t)N ||
+        a.R < 1 || a.nb < 1 || (fwd && (a.na < 1 || a.na > kMaxA)) || a.q % a.inner_n != 0)
+      return HD_BAD;
+#define IQ(NN, EE, SS)                                                                                 \
+  if (N == NN && E == EE && S == SS) {                                                                 \
+    if constexpr (lean_e_built<T>(EE) && SS * (NN / EE) <= 1024 && SS * NN * 16 <= 128 * 1024)        \
+      return fwd ? go_outer_inner_rows<T, NN, EE, SS, true>(a, cus, s)                                 \
+                 : go_outer_inner_rows<T, NN, EE, SS, false>(a, cus, s);                               \
+  }
+#define IN(NN) IQ(NN, 4, 8) IQ(NN, 4, 16) IQ(NN, 8, 8) IQ(NN, 8, 16) IQ(NN, 16, 8) IQ(NN, 16, 16)
+    IN(64) IN(128) IN(256) IN(512) IN(1024)
+#undef IN
+#undef IQ
+    return HD_BAD;
+  }
   if (!outer_lean_supported(N, E, S, a.q, (int)sizeof(T)) || a.fd.G * E != N || a.L > 2u * (uint32_t)N ||
       a.L < 1 || a.R < 1 || a.nb < 1 || (fwd && (a.na < 1 || a.na > kMaxA)) || a.D < 1 || a.r0 < 0 ||
       a.r0 + a.D > a.q)
@@ -302,9 +517,10 @@ hipError_t launch_rows_lean(const LeanRowArgs<T>& a, int E, int A, int cus, hipS
   return HD_BAD;
 }
 
-#define HD_INST(T)                                                                              \
-  template hipError_t launch_rows_lean<T>(const LeanRowArgs<T>&, int, int, int, hipStream_t); \
-  template hipError_t launch_outer_lean<T>(const OuterLeanArgs<T>&, int, int, bool, int, hipStream_t);
+#define HD_INST(T)                                                                                 \
+  template hipError_t launch_rows_lean<T>(const LeanRowArgs<T>&, int, int, int, hipStream_t);    \
+  template hipError_t launch_outer_lean<T>(const OuterLeanArgs<T>&, int, int, bool, int, hipStream_t); \
+  template hipError_t launch_outer_cols<T>(const OuterColArgs<T>&, int, bool, int, hipStream_t);
 #if !defined(HD_PART) || HD_PART == 1
 HD_INST(float)
 #endif

@@ -203,7 +203,9 @@ static bool pick_e_outer(int64_t m, int64_t p, bool ctr, int tbytes, int* E) {
   // one or two blocks of 64 .. 1024 points (not centered) run the lean
   // outer kernel: 8 points per lane up to 256 points, else 16 (FP64: 4,
   // else 8)
-  if (p <= 2 && !ctr && pow2_in(m, 64, 1024)) {
+  // (also the m-point pass of the inner form, p > 2, which runs on the same
+  // kernel's layout)
+  if (!ctr && pow2_in(m, 64, 1024)) {
     *E = (tbytes == 4 ? 8 : 4) * (m <= 256 ? 1 : 2);
     return true;
   }
@@ -218,6 +220,10 @@ static bool pick_e_outer(int64_t m, int64_t p, bool ctr, int tbytes, int* E) {
   while (m / *E > kMaxThreads && *E < 16) *E *= 2;
   return m % *E == 0 && m / *E <= kMaxThreads;
 }
+
+// Points per lane of the column transforms of an outer dimension in the
+// inner form (p points; the workgroup holds 256 / (p / E) columns).
+int outer_col_e(int p, int tbytes) { return p % 3 == 0 ? 12 : (p <= 4 ? p : (tbytes == 4 ? 8 : 4)); }
 
 bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
   const int cb = 2 * tbytes;  // bytes per complex word
@@ -298,7 +304,25 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       return true;
     }
     case VAR_OUTER: {
-      if (dp->p > 2) return fail("outer variant needs p <= 2");
+      if (dp->p > 2) {
+        // the inner form on an outer dimension (Sec. 6.1 with Sec. 5): column
+        // transforms of p points over the blocks of m, then m-point
+        // transforms, both on the lean outer kernels; ordinary dimensions,
+        // all residues in one block
+        if (dp->ctr) return fail("the inner form of an outer dimension takes ordinary (not centered) dimensions");
+        if (dp->q != dp->n * dp->p) return fail("inner form needs q = n p");
+        if (dp->D != dp->n) return fail("the inner form of an outer dimension keeps all residues in one block");
+        if (!pow2_in(dp->m, 64, 1024)) return fail("the inner form of an outer dimension needs m = 2^k, 64 <= m <= 1024");
+        const bool p3 = tbytes == 4 && dp->p % 3 == 0 && pow2_in(dp->p / 3, 4, 32);
+        if (!pow2_in(dp->p, 4, 64) && !p3)
+          return fail("the inner form of an outer dimension needs p = 4 .. 64 (a power of two) or 12 .. 96 (3 * 2^k, complex64)");
+        if (dp->E_p == 0) dp->E_p = outer_col_e((int)dp->p, tbytes);
+        if (dp->E_p != outer_col_e((int)dp->p, tbytes)) return fail("outer column points per lane do not match p");
+        if (!make_fft_desc(dp->p, dp->E_p, &dp->fd_p)) return fail("no stage plan for p with these points per lane");
+        dp->fd_p.twmode = 1;
+        dp->E_pb = dp->E_p;
+        dp->fd_pb = dp->fd_p;
+      }
       if (dp->m > kMaxFusedM) return fail("outer variant needs m <= 8192");
       if (dp->D < 1 || dp->D > dp->n) return fail("outer variant needs 1 <= D <= q residues per block");
       if (dp->m < 8) return fail("outer variant needs m >= 8");
@@ -311,7 +335,7 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
       if (dp->S == 0) {
         // the lean outer kernel: 16 columns (measured at 256 points: 16
         // columns 1.30 ms against 8 columns 1.59 ms for the whole 256^3 plan)
-        const bool lean = dp->p <= 2 && !dp->ctr && pow2_in(dp->m, 64, 1024);
+        const bool lean = !dp->ctr && pow2_in(dp->m, 64, 1024);
         int S = std::min(pow2_floor(std::max(1, kMaxThreads / dp->fd_m.G)), lean ? 16 : 64);
         while (S > 1 && oneed(S) > 128 * 1024) S /= 2;
         dp->S = S;
@@ -324,9 +348,11 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
   }
 }
 
-static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min, int variant, int ctr = 0) {
-  Geometry g = geometry_c(L, M, m, p_min, variant == VAR_MULTI, ctr);
-  if ((variant == VAR_FUSED || variant == VAR_OUTER) && g.inner) return false;
+static bool set_geom(DimPlan* dp, int64_t L, int64_t M, int64_t m, int64_t p_min, int variant, int ctr = 0,
+                     bool outer_inner = false) {
+  Geometry g = geometry_c(L, M, m, p_min, variant == VAR_MULTI || outer_inner, ctr);
+  if (variant == VAR_FUSED && g.inner) return false;
+  if (variant == VAR_OUTER && g.inner != outer_inner) return false;
   dp->L = L;
   dp->M = M;
   dp->m = g.m;
@@ -645,6 +671,19 @@ std::vector<DimPlan> dim_candidates(int64_t L, int64_t M, int A, int tbytes, boo
     } else {
       if (pneed <= 2)
         for (int E : Es) add(m, 0, VAR_OUTER, E);
+      // the inner form of an ordinary outer dimension: the least compiled
+      // column size at or above the span (m = 64 .. 1024)
+      if (!ctr && pneed > 2 && pow2_in(m, 64, 1024)) {
+        int64_t p = 4;
+        while (p < pneed) p *= 2;
+        for (int64_t p3 = 12; p3 <= 96 && tbytes == 4; p3 *= 2)
+          if (p3 >= pneed && p3 < p) p = p3;
+        if (p <= 96) {
+          DimPlan dp;
+          std::string w;
+          if (set_geom(&dp, L, M, m, p, VAR_OUTER, 0, true) && finish_dim(&dp, A, tbytes, &w)) out.push_back(dp);
+        }
+      }
     }
   }
   // drop exact duplicates (same shape reached twice)

@@ -14,7 +14,8 @@ enum Variant {
   VAR_AUTO = 0,
   VAR_FUSED = 1,  // whole 1D convolution per row, direct form (p <= 2)
   VAR_MULTI = 2,  // inner-loop form, three passes over HBM
-  VAR_OUTER = 3   // outer dimension of a multidimensional convolution, direct form
+  VAR_OUTER = 3   // outer dimension of a multidimensional convolution: direct form (p <= 2)
+                  // or the inner form (p > 2)
 };
 
 // Limits of the kernels (hd_k_fused.hip, hd_k_multi.hip, hd_k_outer.hip).
@@ -85,6 +86,9 @@ int64_t next_col_size(int64_t n);       // smallest p >= n the column passes acc
 // Factor N into stage radices that divide E (largest first; a factor 3 first).
 // Returns false when impossible.
 bool make_fft_desc(int64_t N, int E, FftDesc* d);
+
+// Points per lane of an outer dimension's column transforms in the inner form.
+int outer_col_e(int p, int tbytes);
 
 // Choose template widths, tiles and rows per block for a dimension whose
 // (m, p, n, q, variant) are set.  tbytes = sizeof(real).  On failure returns

@@ -47,18 +47,21 @@ def _shape_to_struct(shape):
 def _struct_to_shape(di):
     return {"L": di.L, "M": di.M, "m": di.m, "p": di.p, "n": di.n, "q": di.q, "D": di.D,
             "variant": _L.VARIANT_NAMES[di.variant], "E_m": di.E_m, "E_p": di.E_p, "S": di.S,
-            "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p}
+            "rows_per_block": di.rows_per_block, "tw_m": di.tw_m, "tw_p": di.tw_p, "centered": di.centered}
 
 
-def candidates(L, M, A=2, dtype="c64"):
-    """[(varied_dim, [per-dimension shape dicts])]; varied_dim -1 is the default plan."""
+def candidates(L, M, A=2, dtype="c64", flags=0):
+    """[(varied_dim, [per-dimension shape dicts])]; varied_dim -1 is the default plan.
+    ``flags``: 0, PLAN_CENTERED or PLAN_HERMITIAN (the shapes then carry it)."""
     Ls, Ms, dims = _arrs(L, M)
     cnt = ctypes.c_int(0)
-    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), None, None, 0, ctypes.byref(cnt)))
+    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), int(flags), None, None, 0,
+                                        ctypes.byref(cnt)))
     n = cnt.value
     out = (_L.DimInfo * (n * dims))()
     var = (ctypes.c_int * n)()
-    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), out, var, n, ctypes.byref(cnt)))
+    _L.check(_L.lib().hdconv_candidates(Ls, Ms, A, 1, dims, dtype_code(dtype), int(flags), out, var, n,
+                                        ctypes.byref(cnt)))
     return [(var[k], [_struct_to_shape(out[k * dims + d]) for d in range(dims)]) for k in range(n)]
 
 
@@ -171,10 +174,14 @@ def load_default_model() -> "CostModel":
 
 
 def geometries(count: int, seed: int, A_choices=(2, 3), mix=(0.60, 0.25, 0.15), l1=(256, 1 << 22),
-               l2=(16, 4096), l3=(8, 384)):
+               l2=(16, 4096), l3=(8, 384), flag_mix=(0.0, 0.0)):
     """Seeded geometries of the cost-model workload: 1D L log-uniform in l1,
     2D square L x L with L log-uniform in l2, 3D cubes with L log-uniform in
-    l3 (fractions `mix`); A drawn from A_choices; M = A L per dimension."""
+    l3 (fractions `mix`); A drawn from A_choices; M = A L per dimension.
+    With ``flag_mix`` = (c, h), a fraction c are centered and h Hermitian
+    (odd outer extents; M the least padding of each, as the library
+    defines it); (0, 0) draws exactly the unflagged sequence."""
+    from .hdconv import centered_min_padding, hermitian_min_padding
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for _ in range(count):
@@ -183,7 +190,18 @@ def geometries(count: int, seed: int, A_choices=(2, 3), mix=(0.60, 0.25, 0.15), 
         lo, hi = {1: l1, 2: l2, 3: l3}[dims]
         L = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
         A = int(A_choices[rng.integers(len(A_choices))])
-        out.append({"L": [L] * dims, "M": [A * L] * dims, "A": A})
+        g = {"L": [L] * dims, "M": [A * L] * dims, "A": A, "flags": 0}
+        if flag_mix[0] > 0 or flag_mix[1] > 0:
+            f = rng.random()
+            if f < flag_mix[0]:
+                g["flags"] = _L.PLAN_CENTERED
+                g["M"] = [centered_min_padding(L, A)] * dims
+            elif f < flag_mix[0] + flag_mix[1]:
+                Lo = L | 1  # outer extents of a Hermitian problem are odd
+                g["flags"] = _L.PLAN_HERMITIAN
+                g["L"] = [Lo] * (dims - 1) + [L]
+                g["M"] = [centered_min_padding(Lo, A)] * (dims - 1) + [hermitian_min_padding(L, A)]
+        out.append(g)
     return out
 
 

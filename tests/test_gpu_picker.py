@@ -22,8 +22,10 @@ def say(*a):
 
 
 def small_heldout(count, max_points=1 << 21):
+    # the held-out list of the cost-model workload (ordinary, centered and
+    # Hermitian geometries), its smaller members
     out = []
-    for g in tune.geometries(500, costmodel.SEED_HELDOUT):
+    for g in tune.geometries(500, costmodel.SEED_HELDOUT, flag_mix=costmodel.FLAG_MIX_HELDOUT):
         if int(np.prod(g["L"])) <= max_points:
             out.append(g)
         if len(out) == count:
@@ -33,7 +35,7 @@ def small_heldout(count, max_points=1 << 21):
 
 def _time(g, shape):
     try:
-        return tune.time_shape(g["L"], g["M"], shape, A=g["A"], reps=7)
+        return tune.time_shape(g["L"], g["M"], shape, A=g["A"], reps=9)
     except Exception as e:  # reported by the assertion below
         say("candidate failed: %s %s" % (shape, e))
         return float("inf")
@@ -41,9 +43,9 @@ def _time(g, shape):
 
 def test_trained_picker_gain_over_default(gpu):
     m = tune.load_default_model()
-    regrets, gains = [], []
-    for g in small_heldout(12):
-        cands = tune.candidates(g["L"], g["M"], A=g["A"])
+    regrets, gains, gains_tunable = [], [], []
+    for g in small_heldout(16):
+        cands = tune.candidates(g["L"], g["M"], A=g["A"], flags=g["flags"])
         X = np.array([tune.features(g["L"], g["M"], s, A=g["A"]) for _, s in cands], dtype=np.float32)
         pred = m.predict(X)
         t = np.array([_time(g, s) for _, s in cands])
@@ -52,14 +54,17 @@ def test_trained_picker_gain_over_default(gpu):
         t_def = t[[k for k, (v, _) in enumerate(cands) if v == -1][0]]
         regrets.append(t_pick / t_best - 1.0)
         gains.append(t_def / t_pick)
-        say("L=%s A=%d: best %.4f  model %.4f  default %.4f ms" % (g["L"], g["A"], t_best, t_pick, t_def))
+        if t_def >= 1.05 * t_best:  # the exhaustive search beats the default by 5 % or more
+            gains_tunable.append(t_def / t_pick)
+        say("L=%s A=%d flags=%d: best %.4f  model %.4f  default %.4f ms" % (g["L"], g["A"], g["flags"], t_best,
+                                                                            t_pick, t_def))
     reg = math.exp(np.mean(np.log1p(regrets))) - 1.0
     gain = math.exp(np.mean(np.log(gains)))
-    say("geomean regret %.3f, gain over default %.3f" % (reg, gain))
-    # the shipped model's 5 % claim is over the 500 held-out geometries; a
-    # dozen live timings carry more noise
-    assert reg <= 0.10
-    assert gain >= 0.97
+    say("geomean regret %.3f, gain over default %.3f; where tuning pays (%d): gain %.3f" % (
+        reg, gain, len(gains_tunable), math.exp(np.mean(np.log(gains_tunable))) if gains_tunable else float("nan")))
+    assert reg <= 0.05
+    if gains_tunable:
+        assert math.exp(np.mean(np.log(gains_tunable))) > 1.0
 
 
 def test_model_tuner_times_few_candidates(gpu):

@@ -38,3 +38,27 @@ def test_geometry_generator_is_seeded():
     assert a == b
     for g in a:
         assert all(M == g["A"] * L for L, M in zip(g["L"], g["M"]))
+
+
+def test_candidates_include_inner_form_on_outer_dimensions():
+    # an outer dimension spanning more than two blocks of m = 64 .. 1024 also
+    # lists the inner form (p > 2, q = n p); centered problems do not
+    c = tune.candidates((3000, 64), (6000, 128))
+    inner = [s[0] for v, s in c if v == 0 and s[0]["variant"] == "outer" and s[0]["p"] > 2]
+    assert inner, "no inner-form candidate on dimension 0"
+    for s in inner:
+        assert 64 <= s["m"] <= 1024 and s["q"] % s["p"] == 0 and s["p"] * s["m"] >= 3000
+    ctr = tune.candidates((3001, 64), (4502, 96), flags=4)
+    assert not [s for v, s in ctr if s[0]["p"] > 2]
+
+
+def test_candidates_of_centered_and_hermitian_problems():
+    # the tuner lists shapes for centered and Hermitian problems too; they
+    # carry the flag the time and feature functions read
+    for flags, L, M in ((4, (2048,), (3072,)), (8, (2047, 2048), (3072, 3072))):
+        c = tune.candidates(L, M, flags=flags)
+        assert c[0][0] == -1 and len(c) > 3
+        for v, shape in c:
+            assert shape[-1]["centered"] == (2 if flags == 8 else 1)
+            f = tune.features(L, M, shape)
+            assert f[44] == 1.0 and f[45] == (1.0 if flags == 8 else 0.0)
