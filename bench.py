@@ -33,8 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 ALU_PEAK_F32 = 78.6
 ALU_PEAK_F64 = 78.6
-KERNEL_SOURCES = ["hd_k_fused.hip", "hd_k_lean.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_kcommon.hpp", "hd_fft.hpp",
-                  "hd_common.hpp", "hd_engine.hpp"]
+# sources that decide the kernels a plan runs and their code (the counter
+# summaries under profiles/ record the hash of these)
+KERNEL_SOURCES = ["hd_k_fused.hip", "hd_k_lean.hip", "hd_k_multi.hip", "hd_k_outer.hip", "hd_k_batch.hip",
+                  "hd_kcommon.hpp", "hd_lean.hpp", "hd_fft.hpp", "hd_common.hpp", "hd_engine.hpp", "hd_plan.cpp"]
 COMPARE_OUT = os.path.join(ROOT, "gpurun_out", "bench_compare.json")
 
 

@@ -144,7 +144,7 @@ typedef struct hdconv_options {
   int rows_per_block[3]; /* rows per workgroup of row kernels (0: choose)       */
   int twiddles[3];   /* FFT twiddles: 0 choose, 1 two-level root table, 2 exact per-stage tables */
   int tuner;         /* HDCONV_TUNER_*: how shapes left to the planner are chosen */
-  int tune_reps;     /* timed executes per candidate (0: 5)                     */
+  int tune_reps;     /* executes per timed block of a candidate (0: 5)          */
   double margin;     /* model tuner: time the top candidates when the predicted
                         log-time gap between the best two is below this (0: 0.05) */
   hdconv_model_t model; /* model tuner: a cost model from hdconv_model_create   */
@@ -212,8 +212,10 @@ typedef struct hdconv_plan_info {
 int hdconv_candidates(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype, int flags,
                       hdconv_dim_info_t* out, int* varied, int cap, int* count);
 
-/* Median time in ms of `reps` executes (after one warm-up) of the plan whose
- * per-dimension shapes are shape[0..dims), on zeroed device buffers. */
+/* Time in ms of one execute of the plan whose per-dimension shapes are
+ * shape[0..dims), on zeroed device buffers: after one warm-up, three blocks
+ * of `reps` executes run back to back and the median block average is
+ * returned (the steady state of a caller running many steps). */
 int hdconv_time_shape(const int64_t* L, const int64_t* M, int A, int B, int dims, int dtype,
                       const hdconv_dim_info_t* shape, int reps, double* ms);
 

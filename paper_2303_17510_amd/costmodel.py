@@ -132,7 +132,16 @@ def save(data, path):
 
 
 def load(paths):
+    """Rows of several files; a geometry id present in more than one file
+    keeps only the rows of the last file that holds it (re-collected
+    geometries replace their older timings)."""
     parts = [_widen({k: v for k, v in np.load(p, allow_pickle=False).items()}) for p in paths]
+    later = set()
+    for i in range(len(parts) - 1, -1, -1):
+        gids = parts[i]["gid"]
+        keep = ~np.isin(gids, np.array(sorted(later), dtype=gids.dtype))
+        later.update(int(g) for g in np.unique(gids))
+        parts[i] = {k: v[keep] for k, v in parts[i].items()}
     return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
@@ -143,23 +152,40 @@ def train(data, hidden=64, epochs=300, batch=256, lr=2e-3, seed=0):
 
 
 def evaluate(model, data):
-    """Per held-out geometry: regret of the model's pick and gain over the default plan."""
+    """Per held-out geometry: regret of the model's pick and gain over the default plan.
+
+    Two readings of "the pick":
+    * over all candidates of a geometry (the default plan and every
+      single-dimension variation), the one of least predicted time;
+    * per dimension, as the library's tuner decides: for each dimension d,
+      the least predicted among the default and the variations of d, judged
+      against the least timed of the same set ("decision" regret, one value
+      per dimension of each geometry)."""
     pred = model.predict(data["X"])
-    regrets, gains, rows = [], [], []
+    regrets, gains, rows, dec = [], [], [], []
     for g in np.unique(data["gid"]):
         idx = np.nonzero(data["gid"] == g)[0]
         t = np.exp(data["y"][idx].astype(np.float64))
         best = t.min()
         pick = t[np.argmin(pred[idx])]
-        dflt = idx[data["varied"][idx] == -1]
+        var = data["varied"][idx]
+        dflt = idx[var == -1]
         t_def = math.exp(float(data["y"][dflt[0]])) if len(dflt) else float("nan")
         regrets.append(pick / best - 1.0)
         gains.append(t_def / pick)
         rows.append((int(g), int(data["dims"][idx[0]]), float(best), float(pick), float(t_def)))
+        for d in range(int(data["dims"][idx[0]])):
+            sel = np.nonzero((var == -1) | (var == d))[0]
+            if len(sel) > 1:
+                dec.append(t[sel][np.argmin(pred[idx][sel])] / t[sel].min() - 1.0)
     r = np.array(regrets)
     gm = float(np.exp(np.mean(np.log1p(r))) - 1.0)
+    dr = np.array(dec) if dec else np.zeros(1)
     return {"geometries": len(r), "regret_geomean": gm, "regret_median": float(np.median(r)),
             "regret_p90": float(np.percentile(r, 90)), "regret_max": float(r.max()),
+            "decision_regret_geomean": float(np.exp(np.mean(np.log1p(dr))) - 1.0),
+            "decision_regret_p90": float(np.percentile(dr, 90)), "decision_regret_max": float(dr.max()),
+            "decisions": len(dec),
             "gain_over_default_geomean": float(np.exp(np.mean(np.log(np.array(gains))))),
             "exhaustive_gain_over_default_geomean": float(np.exp(np.mean(
                 [math.log(x[4] / x[2]) for x in rows if x[4] == x[4]]))),
@@ -178,6 +204,8 @@ def main(argv=None):
     c.add_argument("--count", type=int, default=2000)
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--budget", type=float, default=0, help="stop after this many seconds (0: none)")
+    c.add_argument("--min-dims", type=int, default=1, help="only geometries of at least this many dimensions")
+    c.add_argument("--gid", type=int, default=0, help="geometry id of the rows of --geometry")
     c.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
@@ -198,12 +226,13 @@ def main(argv=None):
             dims_s, A_s = a.geometry.split(":")
             L = [int(v) for v in dims_s.split(",")]
             geoms, sel = [{"L": L, "M": [int(A_s) * v for v in L], "A": int(A_s)}], [0]
+            base = a.gid
         else:
             # the flagged and held-out lists mix in centered and Hermitian geometries
             fm = {SEED_FLAGGED: FLAG_MIX_FLAGGED, SEED_HELDOUT: FLAG_MIX_HELDOUT}.get(a.seed, (0.0, 0.0))
             geoms = tune.geometries(a.total, a.seed, flag_mix=fm)
-            sel = list(range(a.start, min(a.total, a.start + a.count)))
-        base = GID_FLAGGED if a.seed == SEED_FLAGGED else 0
+            sel = [i for i in range(a.start, min(a.total, a.start + a.count)) if len(geoms[i]["L"]) >= a.min_dims]
+            base = GID_FLAGGED if a.seed == SEED_FLAGGED else 0
         d = collect([geoms[i] for i in sel], reps=a.reps, log=log, time_budget_s=a.budget or None,
                     ids=[base + i for i in sel])
         save(d, a.out)

@@ -18,12 +18,22 @@
 //    per workgroup;
 //  * a workgroup loops over rows (the grid is sized to the resident
 //    workgroups), so its tables are staged into LDS once.
+#include <map>
+#include <utility>
+
 #include "hd_lean.hpp"
 #include "hd_plan.hpp"
 
 namespace hd {
 
-template <typename T, int N, int E, int A, int RPB, int WAVES, bool FULL, int P>
+// The q = 2 twiddle table (N words) is kept in LDS only where it costs at
+// most 4 KB.
+template <typename T, int N>
+constexpr bool lean_zf() {
+  return N * (int)sizeof(cpx<T>) <= 4096;
+}
+
+template <typename T, int N, int E, int A, int RPB, int WAVES, bool FULL, int P, bool ZF = false>
 __global__ void __launch_bounds__(RPB*(N / E), WAVES) k_rows_lean(LeanRowArgs<T> a) {
   constexpr int G = N / E;
   constexpr int NT = RPB * G;
@@ -37,8 +47,11 @@ __global__ void __launch_bounds__(RPB*(N / E), WAVES) k_rows_lean(LeanRowArgs<T>
   cpx<T>* zA = twl + a.fd.ntw_stage;   // zeta_{qm}^{r g}, [r][g]
   cpx<T>* zB = zA + q * G;             // zeta_{qm}^{r G e}, [r][e]
   cpx<T>* zC = zB + q * E;             // zeta_q^r = zeta_{qm}^{r m} (second block, P = 2)
+  cpx<T>* zF = zC + q;                 // zeta_{qm}^s, s < N (q = 2, ZF)
   // the per-stage tables follow the two-level one
   lean_row_tables<T, N, E, P>(a.fft_tw + a.fd.ntw, a.fd.ntw_stage, a.zqm, q, (int)threadIdx.x, NT, twl, zA, zB, zC);
+  if constexpr (ZF)
+    if (q == 2) lean_row_q2_table<T, N>(a.zqm, (int)threadIdx.x, NT, zF);
   __syncthreads();
   const int64_t step = (int64_t)gridDim.x * RPB;
   for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < a.nrows; row0 += step) {
@@ -48,8 +61,8 @@ __global__ void __launch_bounds__(RPB*(N / E), WAVES) k_rows_lean(LeanRowArgs<T>
     const cpx<T>* src[A];
 #pragma unroll
     for (int ai = 0; ai < A; ++ai) src[ai] = a.in[ai] + rowc * a.in_stride + g;
-    lean_row<T, N, E, A, P, FULL>(src, a.out + rowc * a.out_stride + g, valid, a.L, q, a.scale, g, xr, twl, zA, zB,
-                                  zC);
+    lean_row<T, N, E, A, P, FULL, 8, ZF>(src, a.out + rowc * a.out_stride + g, valid, a.L, q, a.scale, g, xr, twl,
+                                         zA, zB, zC, zF + g);
   }
 }
 
@@ -315,7 +328,8 @@ __global__ void __launch_bounds__(S*(P / E), WAVES) k_outer_cols(OuterColArgs<T>
 static bool lean_e_ok(int E, int tbytes) { return tbytes == 4 ? (E == 8 || E == 16) : (E == 4 || E == 8); }
 
 bool outer_lean_supported(int m, int E, int S, int q, int tbytes, bool inner) {
-  if (q < 1 || (!inner && q > kLeanMaxQ) || !lean_e_ok(E, tbytes) || (S != 8 && S != 16)) return false;
+  if (q < 1 || (!inner && q > kLeanMaxQ) || !lean_e_ok(E, tbytes) || (S != 8 && S != 16 && !(S == 32 && !inner)))
+    return false;
   if (m != 64 && m != 128 && m != 256 && m != 512 && m != 1024) return false;
   return S * (m / E) <= 1024 && (size_t)S * m * 16 <= 128 * 1024;  // threads; exchange area (FP64 words)
 }
@@ -332,17 +346,19 @@ bool rows_lean_supported(int m, int E, int A, int q, int tbytes) {
 }
 #endif
 
-// Resident workgroups per CU of one kernel instance, asked once.
+// Resident workgroups per CU of one kernel instance with one LDS size,
+// asked once.
 template <typename K>
 static int lean_resident(K kernel, int threads, size_t lds) {
   static std::mutex mu;
-  static std::unordered_map<const void*, int> seen;
-  const void* key = reinterpret_cast<const void*>(kernel);
+  static std::map<std::pair<const void*, size_t>, int> seen;
+  const void* fn = reinterpret_cast<const void*>(kernel);
+  const auto key = std::make_pair(fn, lds);
   std::lock_guard<std::mutex> lk(mu);
   auto it = seen.find(key);
   if (it != seen.end()) return it->second;
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, key, threads, lds) != hipSuccess || n < 1) n = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds) != hipSuccess || n < 1) n = 1;
   seen[key] = n;
   return n;
 }
@@ -360,13 +376,14 @@ constexpr int lean_waves() {
   return (E * (int)sizeof(T) >= 64 || A >= 3) ? 3 : 4;
 }
 
-template <typename T, int N, int E, int A, bool FULL, int P>
-static hipError_t go_lean(const LeanRowArgs<T>& a, int cus, hipStream_t s) {
+template <typename T, int N, int E, int A, bool FULL, int P, bool ZF>
+static hipError_t go_lean_z(const LeanRowArgs<T>& a, int cus, hipStream_t s) {
   constexpr int RPB = lean_rpb<N, E>();
   constexpr int nt = RPB * (N / E);
+  const size_t zf = ZF ? N : 0;
   const size_t lds =
-      ((size_t)RPB * lean_xwords<N, E>() + a.fd.ntw_stage + (size_t)a.q * (N / E + E + 1)) * sizeof(cpx<T>);
-  auto k = k_rows_lean<T, N, E, A, RPB, lean_waves<T, E, A>(), FULL, P>;
+      ((size_t)RPB * lean_xwords<N, E>() + a.fd.ntw_stage + (size_t)a.q * (N / E + E + 1) + zf) * sizeof(cpx<T>);
+  auto k = k_rows_lean<T, N, E, A, RPB, lean_waves<T, E, A>(), FULL, P, ZF>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
   const int64_t need = (a.nrows + RPB - 1) / RPB;
@@ -374,6 +391,25 @@ static hipError_t go_lean(const LeanRowArgs<T>& a, int cus, hipStream_t s) {
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(need, cap));
   hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, a);
   return hipGetLastError();
+}
+
+// The q = 2 twiddle table trades a complex product per point and use for an
+// LDS read.  Measured row passes on gfx950 (256^3 and 128^3 plans, with
+// against without): FP64 256 points at 8 per lane 0.83 against 1.05 ms,
+// FP32 128 points at 16 per lane 0.048 against 0.051 ms; elsewhere it was
+// neutral or slower (FP32 256 points at 16 per lane 0.49 against 0.38 ms,
+// FP64 256 points at 4 per lane 1.40 against 1.04 ms), so only those two
+// shapes take it.
+template <typename T, int N, int E>
+constexpr bool lean_use_zf() {
+  return lean_zf<T, N>() && ((sizeof(T) == 8 && N == 256 && E == 8) || (sizeof(T) == 4 && N == 128 && E == 16));
+}
+
+template <typename T, int N, int E, int A, bool FULL, int P>
+static hipError_t go_lean(const LeanRowArgs<T>& a, int cus, hipStream_t s) {
+  if constexpr (A == 2 && lean_use_zf<T, N, E>())
+    if (a.q == 2) return go_lean_z<T, N, E, A, FULL, P, true>(a, cus, s);
+  return go_lean_z<T, N, E, A, FULL, P, false>(a, cus, s);
 }
 
 template <typename T, int N, int E, int S, bool FWD, bool FULL, int P>
@@ -488,7 +524,8 @@ hipError_t launch_outer_lean(const OuterLeanArgs<T>& a, int E, int S, bool fwd, 
                   : go_outer_lean<T, NN, EE, SS, false, false, 1>(a, cus, s);                          \
     }                                                                                                  \
   }
-#define ON(NN) OQ(NN, 4, 8) OQ(NN, 4, 16) OQ(NN, 8, 8) OQ(NN, 8, 16) OQ(NN, 16, 8) OQ(NN, 16, 16)
+#define ON(NN) OQ(NN, 4, 8) OQ(NN, 4, 16) OQ(NN, 8, 8) OQ(NN, 8, 16) OQ(NN, 16, 8) OQ(NN, 16, 16) \
+  OQ(NN, 8, 32) OQ(NN, 16, 32)
   ON(64) ON(128) ON(256) ON(512) ON(1024)
 #undef ON
 #undef OQ

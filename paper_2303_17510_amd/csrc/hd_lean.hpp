@@ -14,6 +14,16 @@ __host__ __device__ constexpr int lean_ps() {
   while ((1 << ps) < ct_radix(N, E)) ++ps;
   return ps;
 }
+// Pad period of the exchange after the stage of span Ns.  Stages of span
+// 32 or more (transforms of at most 8 points per lane, 32 or more lanes)
+// write butterfly outputs Ns points apart, where one slot every 32 points
+// keeps every group of 16 or 32 lanes on distinct LDS banks (one every 2^PS
+// leaves 2-way conflicts); the addresses stay one per-lane base plus
+// constants, and a longer period needs no more room.
+template <int N, int E, int Ns>
+__host__ __device__ constexpr int lean_ps_at() {
+  return (Ns >= 32 && E <= 8 && (N / E) % 32 == 0 && lean_ps<N, E>() < 5) ? 5 : lean_ps<N, E>();
+}
 template <int N, int E>
 __host__ __device__ constexpr int lean_xwords() {
   return N + (N >> lean_ps<N, E>());
@@ -34,7 +44,7 @@ __device__ __forceinline__ void lean_fft(cpx<T> (&v)[E], const int g, cpx<T>* __
   if constexpr (Ns < N) {
     constexpr int R = ct_radix(N / Ns, E);
     static_assert(R > 1 && (N / Ns) % R == 0 && E % R == 0, "no stage plan");
-    constexpr int G = N / E, NB = E / R, PS = PAD ? lean_ps<N, E>() : 30;
+    constexpr int G = N / E, NB = E / R, PS = PAD ? lean_ps_at<N, E, Ns>() : 30;
     constexpr bool last = Ns * R == N;
     // with G a multiple of Ns every butterfly of a lane has k = g mod Ns
     // (Ns is a power of two, or 3 times one after a first radix-3 stage)
@@ -106,6 +116,24 @@ __device__ __forceinline__ void lean_row_tables(const cpx<T>* st, int ntw, const
     for (int i = tid; i < q; i += NT) zC[i] = zqm.get((uint32_t)(i * N));
 }
 
+// A complex word read as one aligned pair (entries of the LDS tables are
+// aligned to their size, which the element type alone does not state).
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_pair(const cpx<T>* p) {
+  typedef T pair_t __attribute__((ext_vector_type(2)));
+  const pair_t v = *reinterpret_cast<const pair_t*>(p);
+  return mk(v.x, v.y);
+}
+
+// Whole-point table of the second residue when q = 2 (the usual M = 2L):
+// zF[s] = zeta_{qm}^{s}, s < N, so that a lane's twiddle at point
+// s = g + G e is one LDS read at a constant offset rather than a complex
+// product per use.
+template <typename T, int N>
+__device__ __forceinline__ void lean_row_q2_table(const RootTable<T>& zqm, int tid, int NT, cpx<T>* zF) {
+  for (int i = tid; i < N; i += NT) zF[i] = zqm.get((uint32_t)i);
+}
+
 // One row of the direct form (Sec. 2, Algorithms 3-6) with p = P <= 2
 // blocks of N points: for each residue r < q
 //   W_s = zeta_{qm}^{r s} (f_s + zeta_q^r f_{N+s}),  F_a = fft_N(W) per input,
@@ -116,10 +144,11 @@ __device__ __forceinline__ void lean_row_tables(const cpx<T>* st, int ntw, const
 // workgroup); `valid` is false for a row beyond the last (it reads its
 // clamped source and stores nothing).  FULL: one block and L = N.  Inputs of
 // at most KEEP words per lane are held in registers across the residues.
-template <typename T, int N, int E, int A, int P, bool FULL, int KEEP = 8>
+// ZF: zF points at this lane's entry of the q = 2 table of lean_row_q2_table.
+template <typename T, int N, int E, int A, int P, bool FULL, int KEEP = 8, bool ZF = false>
 __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* dst, bool valid, uint32_t L, int q,
                                          T scale, int g, cpx<T>* xr, const cpx<T>* twl, const cpx<T>* zA,
-                                         const cpx<T>* zB, const cpx<T>* zC) {
+                                         const cpx<T>* zB, const cpx<T>* zC, const cpx<T>* zF = nullptr) {
   constexpr int G = N / E;
   // Inputs of A P E <= KEEP words per lane stay in registers across the
   // residues; larger ones are read again (from cache) for each residue.
@@ -146,6 +175,11 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
   }
   cpx<T> acc[P][E];
   constexpr bool kTwo = A == 2;  // the two-residue path below (products of two inputs)
+  // this lane's second-residue twiddle at point g + G e
+  auto z1 = [&](cpx<T> za, int e) -> cpx<T> {
+    if constexpr (ZF) return ld_pair(zF + G * e);
+    else return cmul(za, zB[E + e]);
+  };
   if (kTwo && q == 2) {
     // Two residues (the usual M = 2L): each input is read once and
     // transformed for both residues, the two partial products are held
@@ -172,7 +206,7 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const cpx<T> xv = P == 2 ? xa[0][e] + cmul(xa[P - 1][e], zc) : xa[0][e];
-        w[e] = cmul(xv, cmul(za, zB[E + e]));
+        w[e] = cmul(xv, z1(za, e));
       }
       lean_fft<T, N, E, +1>(w, g, xr, twl);
 #pragma unroll
@@ -184,7 +218,7 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
     lean_fft<T, N, E, -1>(p1, g, xr, twl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cpx<T> y = cmulc(p1[e], cmul(za, zB[E + e]));
+      const cpx<T> y = cmulc(p1[e], z1(za, e));
       acc[0][e] = acc[0][e] + y;
       if constexpr (P == 2) acc[P - 1][e] = acc[P - 1][e] + cmulc(y, zc);
     }

@@ -151,15 +151,20 @@ static int pow2_floor(int64_t x) {
 // whole-row kernel with 8 (FP32, m >= 1024) or 4 points per lane.
 static bool pow2_in(int64_t m, int64_t lo, int64_t hi) { return m >= lo && m <= hi && (m & (m - 1)) == 0; }
 
-static bool pick_e_row(int64_t m, int64_t p, bool fused, bool ctr, int tbytes, int* E) {
+static bool pick_e_row(int64_t m, int64_t p, int64_t q, int A, bool fused, bool ctr, int tbytes, int* E) {
   // whole rows of one or two blocks (not centered) run the lean row kernel
-  // (hd_k_lean.hip): 8 points per lane in FP32, 4 in FP64 (measured at 256
-  // points, 256^2 rows: 0.46 ms against 0.90 ms for the general whole-row
-  // kernel)
+  // (hd_k_lean.hip; 256 points, 256^2 rows: 0.46 ms against 0.90 ms for the
+  // general whole-row kernel).  Measured row passes on gfx950: FP32 takes 8
+  // points per lane, except 16 for products of two inputs on single-block
+  // rows of 128 and 256 points with 2 .. 8 residues (256^3: 0.38 against 0.43 ms,
+  // 128^3: 0.048 against 0.066 ms; half the LDS exchanges); FP64 takes 8
+  // (256^3: 0.83 against 1.40 ms with 4), except 4 for single-residue rows
+  // of 1024 points.
   // (FP64 rows of 2048 points: the general kernel with 8 points per lane,
   // 0.29 against 0.32-0.34 ms for the 2048^2 row pass)
   if (fused && p <= 2 && !ctr && pow2_in(m, 64, tbytes == 4 ? 2048 : 1024)) {
-    *E = tbytes == 4 ? 8 : 4;
+    if (tbytes == 4) *E = (A == 2 && p == 1 && q >= 2 && q <= 8 && (m == 128 || m == 256)) ? 16 : 8;
+    else *E = (m == 1024 && q < 2) ? 4 : 8;
     return true;
   }
   if (m % 3 == 0) {
@@ -264,7 +269,7 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
         if (dp->m < 8 || dp->m > kMaxRowM) return fail("multipass variant needs 8 <= m <= 8192");
         if (dp->p > kMaxColP || !col_size_ok(dp->p)) return fail("unsupported p for the column passes");
       }
-      if (dp->E_m == 0 && !pick_e_row(dp->m, dp->p, fused, dp->ctr != 0, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
+      if (dp->E_m == 0 && !pick_e_row(dp->m, dp->p, dp->q, A, fused, dp->ctr != 0, tbytes, &dp->E_m)) return fail("unsupported m for the row kernel");
       if (!in_set(dp->E_m, {4, 8, 12, 16})) return fail("row points per lane must be 4, 8, 12 or 16");
       if (!make_fft_desc(dp->m, dp->E_m, &dp->fd_m)) return fail("no stage plan for m with these points per lane");
       auto need = [&](int r) {
@@ -340,7 +345,12 @@ bool finish_dim(DimPlan* dp, int A, int tbytes, std::string* why) {
         while (S > 1 && oneed(S) > 128 * 1024) S /= 2;
         dp->S = S;
       }
-      if (dp->S * dp->fd_m.G > kMaxThreads || oneed(dp->S) > kLdsBudget) return fail("outer column tile does not fit");
+      // (the lean outer kernel takes workgroups of up to 1024 lanes)
+      const bool lean_e = tbytes == 4 ? (dp->E_m == 8 || dp->E_m == 16) : (dp->E_m == 4 || dp->E_m == 8);
+      const bool lean_tile = !dp->ctr && pow2_in(dp->m, 64, 1024) && dp->p <= 2 && dp->q <= 8 && lean_e &&
+                             (size_t)dp->S * dp->m * 16 <= 128 * 1024;
+      if (dp->S * dp->fd_m.G > (lean_tile ? 2 * kMaxThreads : kMaxThreads) || oneed(dp->S) > kLdsBudget)
+        return fail("outer column tile does not fit");
       return true;
     }
     default:
@@ -584,13 +594,30 @@ bool choose_dim(int64_t L, int64_t M, int A, int tbytes, bool contiguous, int64_
     // transforms, two residues of half the power of two): 96^3 0.170 ->
     // 0.084 ms, 150^3 1.02 -> 0.61, 192^3 1.21 -> 0.63, 320^3 8.4 -> 3.8,
     // 384^3 10.5 -> 4.7; at 229^3 the tie goes to p = 1 (1.72 against 1.89).
+    // With 2^16 or more columns (FP32, from 256^3 on) the lean outer kernel
+    // takes 32 columns per workgroup where the tile fits (at most 1024 lanes
+    // and 128 KB of exchange), and ties then go to p = 2: measured at 256^3,
+    // forward outer passes 0.266 -> 0.256 ms (p = 1) and 0.246 ms (p = 2,
+    // m = 128), whole step 1.215 -> 1.202 -> 1.169 ms; at 128^3 (2^14 and
+    // 2^15 columns) 32 columns were 6 % slower.
     const int64_t mA = std::max<int64_t>(8, pow2_ceil(L));
     if (dims == 3 && mA >= 128 && mA <= 2048) {
       DimPlan a, b;
       std::string w2;
       const bool oka = mA <= 1024 && set_geom(&a, L, M, mA, 0, VAR_OUTER) && finish_dim(&a, A, tbytes, &w2);
       const bool okb = set_geom(&b, L, M, mA / 2, 0, VAR_OUTER) && b.p == 2 && finish_dim(&b, A, tbytes, &w2);
-      if (oka && (!okb || a.q * a.m <= b.q * b.m)) {
+      const bool wide = tbytes == 4 && lines >= 65536;
+      auto widen = [&](DimPlan* c) {
+        DimPlan t = *c;
+        t.S = 32;
+        std::string w3;
+        if (pow2_in(t.m, 64, 256) && finish_dim(&t, A, tbytes, &w3)) *c = t;
+      };
+      if (wide) {
+        if (oka) widen(&a);
+        if (okb) widen(&b);
+      }
+      if (oka && (!okb || a.q * a.m < b.q * b.m || (a.q * a.m == b.q * b.m && !(wide && b.S == 32)))) {
         *dp = a;
         return true;
       }

@@ -66,7 +66,8 @@ def candidates(L, M, A=2, dtype="c64", flags=0):
 
 
 def time_shape(L, M, shape, A=2, dtype="c64", reps=5) -> float:
-    """Median ms of `reps` executes of the plan with these per-dimension shapes."""
+    """Steady-state ms per execute of the plan with these per-dimension shapes
+    (median over three blocks of `reps` back-to-back executes)."""
     Ls, Ms, dims = _arrs(L, M)
     ms = ctypes.c_double(0)
     _L.check(_L.lib().hdconv_time_shape(Ls, Ms, A, 1, dims, dtype_code(dtype), _shape_to_struct(shape), reps,

@@ -153,6 +153,21 @@ def test_plan_info_host_only():
     p.close()
 
 
+@pytest.mark.parametrize("L,A,dtype,E", [
+    ((256, 256, 256), 2, "c64", 16),   # 256-point rows, two residues: 16 points per lane
+    ((128, 128, 128), 2, "c64", 16),
+    ((64, 64, 64), 2, "c64", 8),
+    ((256, 256, 256), 3, "c64", 8),    # three inputs keep 8
+    ((256, 256, 256), 2, "c128", 8),
+    ((64, 64, 64), 2, "c128", 8),
+])
+def test_default_row_points_per_lane(L, A, dtype, E):
+    # the planner's measured rule for the whole-row pass of 2D/3D plans
+    with Plan(L, tuple(A * v for v in L), A=A, dtype=dtype, host_only=True) as p:
+        d = p.info()["dims"][-1]
+    assert d["variant"] == "fused" and d["E_m"] == E
+
+
 def test_workspace_accounting_2d():
     # Sec. 5: the decomposition keeps q_x m_x rows of L_y per input
     p = Plan((2048, 2048), (4096, 4096), dtype="c64", host_only=True)

@@ -154,7 +154,8 @@ OUTER = [
 
 
 def outer_fits(shape, M, A, E, S):
-    # the planner allows at most 512 lanes per outer workgroup
+    # the planner allows at most 1024 lanes per lean outer workgroup (and
+    # 32 columns only up to 256 points)
     dims = len(shape)
     try:
         with Plan(shape, M, A=A, dtype="c64", E_m=tuple([E] * (dims - 1) + [0]),
@@ -164,7 +165,7 @@ def outer_fits(shape, M, A, E, S):
         return False
 
 
-@pytest.mark.parametrize("E,S", [(8, 16), (16, 16), (8, 8), (16, 8)])
+@pytest.mark.parametrize("E,S", [(8, 16), (16, 16), (8, 8), (16, 8), (8, 32), (16, 32)])
 @pytest.mark.parametrize("shape,M,A", OUTER, ids=["x".join(map(str, c[0])) + "_A%d" % c[2] for c in OUTER])
 def test_lean_outer_c64(gpu, shape, M, A, E, S):
     if not outer_fits(shape, M, A, E, S):
@@ -177,6 +178,13 @@ def test_lean_outer_c64(gpu, shape, M, A, E, S):
 @pytest.mark.parametrize("shape,M,A", OUTER[:2] + OUTER[5:6], ids=["256", "200", "A3"])
 def test_lean_outer_c128(gpu, shape, M, A):
     e = run_outer(shape, M, A, "c128", 8, 8, 7700)
+    say("   err %.2e" % e)
+    assert e <= TOL["c128"]
+
+
+def test_lean_outer_c128_wide_tiles(gpu):
+    # 32 columns of 256-point FP64 transforms: 1024 lanes, 128 KB of exchange
+    e = run_outer(OUTER[0][0], OUTER[0][1], 2, "c128", 8, 32, 7750)
     say("   err %.2e" % e)
     assert e <= TOL["c128"]
 
@@ -229,6 +237,30 @@ P2_OUTER = [
     ((150, 20, 30), (300, 40, 60), 2, (128, 0, 0)),    # 3D outer two 128-point blocks
     ((100, 30, 20), (298, 88, 58), 3, (64, 0, 0)),     # three inputs
 ]
+
+
+@pytest.mark.parametrize("shape,M,A", [((150, 40, 64), (300, 80, 128), 2), ((150, 20, 24), (448, 58, 70), 3)],
+                         ids=["A2", "A3"])
+def test_lean_outer_two_blocks_wide_tiles(gpu, shape, M, A):
+    # two 128-point blocks with 32 columns per workgroup (the 3D default
+    # from 256^3 on)
+    import torch
+    xs = [synth.unit_disk(shape, 8150 + a).astype(np.complex64) for a in range(A)]
+    dev = [torch.from_numpy(x).cuda() for x in xs]
+    with Plan(shape, M, A=A, dtype="c64", m=(128, 0, 0), E_m=(8, 0, 0), S=(32, 0, 0)) as p:
+        d = p.info()["dims"][0]
+        out = torch.full_like(dev[0], float("nan"))
+        p.profile_begin(1)
+        p.execute(dev, out)
+        torch.cuda.synchronize()
+        names = [s["name"] for s in p.profile_end()]
+    say("   %s outer m=%d p=%d q=%d E=%d S=%d kernels %s" % (shape, d["m"], d["p"], d["q"], d["E_m"], d["S"], names))
+    assert d["p"] == 2 and d["S"] == 32 and "outer_lean_fwd" in names
+    ins = [synth.as_oracle(x) for x in xs]
+    want = oracle.conv_direct(ins) if A == 3 else oracle.conv_explicit(ins)
+    e = oracle.rel_l2(out.cpu().numpy(), want)
+    say("   err %.2e" % e)
+    assert e <= TOL["c64"]
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
