@@ -137,6 +137,19 @@ class HdconvError(RuntimeError):
         self.code = code
 
 
+def _bind_runtime_first():
+    """Load PyTorch (when installed) before the library.  PyTorch ships its
+    own HIP runtime under the same soname as the system's; whichever is
+    loaded first serves the process.  Loaded first, the library binds to the
+    system runtime, PyTorch then finds no device, and the library's kernels
+    measured up to 30 % slower (256^3 plan 1.50 against 1.13 ms), so the
+    front end, whose tensors are PyTorch's, always loads PyTorch first."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib() -> ctypes.CDLL:
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -145,6 +158,7 @@ def lib() -> ctypes.CDLL:
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libhdconv.so is not built (run python -m paper_2303_17510_amd.build): %s"
                                   % LIB_PATH)
+            _bind_runtime_first()
             L = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in SIGNATURES.items():
                 fn = getattr(L, name)
