@@ -175,10 +175,20 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
   }
   cpx<T> acc[P][E];
   constexpr bool kTwo = A == 2;  // the two-residue path below (products of two inputs)
-  // this lane's second-residue twiddle at point g + G e
-  auto z1 = [&](cpx<T> za, int e) -> cpx<T> {
+  // this lane's second-residue twiddle at point g + G e.  Without the
+  // whole-point table the products zeta^{g} zeta^{G e} are formed again at
+  // each of their three uses: the LDS entries are read through an opaque
+  // offset, so the compiler cannot keep the E products live across the
+  // transforms (with 16 points per lane they spilled to scratch memory,
+  // 0.5 GB of extra HBM traffic per 256^3 row pass).
+  auto z1_base = [&]() -> const cpx<T>* {
+    int off = E;
+    asm volatile("" : "+v"(off));
+    return zB + off;
+  };
+  auto z1 = [&](cpx<T> za, const cpx<T>* zb1, int e) -> cpx<T> {
     if constexpr (ZF) return ld_pair(zF + G * e);
-    else return cmul(za, zB[E + e]);
+    else return cmul(za, zb1[e]);
   };
   if (kTwo && q == 2) {
     // Two residues (the usual M = 2L): each input is read once and
@@ -203,10 +213,11 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
       lean_fft<T, N, E, +1>(w, g, xr, twl);
 #pragma unroll
       for (int e = 0; e < E; ++e) p0[e] = ai == 0 ? w[e] : cmul(p0[e], w[e]);
+      const cpx<T>* zb1 = z1_base();
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const cpx<T> xv = P == 2 ? xa[0][e] + cmul(xa[P - 1][e], zc) : xa[0][e];
-        w[e] = cmul(xv, z1(za, e));
+        w[e] = cmul(xv, z1(za, zb1, e));
       }
       lean_fft<T, N, E, +1>(w, g, xr, twl);
 #pragma unroll
@@ -216,9 +227,10 @@ __device__ __forceinline__ void lean_row(const cpx<T>* const (&src)[A], cpx<T>* 
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[0][e] = acc[P - 1][e] = p0[e];
     lean_fft<T, N, E, -1>(p1, g, xr, twl);
+    const cpx<T>* zb1 = z1_base();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cpx<T> y = cmulc(p1[e], z1(za, e));
+      const cpx<T> y = cmulc(p1[e], z1(za, zb1, e));
       acc[0][e] = acc[0][e] + y;
       if constexpr (P == 2) acc[P - 1][e] = acc[P - 1][e] + cmulc(y, zc);
     }
