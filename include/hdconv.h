@@ -145,7 +145,7 @@ typedef struct hdconv_options {
   int twiddles[3];   /* FFT twiddles: 0 choose, 1 two-level root table, 2 exact per-stage tables */
   int tuner;         /* HDCONV_TUNER_*: how shapes left to the planner are chosen */
   int tune_reps;     /* executes per timed block of a candidate (0: 5)          */
-  double margin;     /* model tuner: time the top candidates when the predicted
+  double margin;     /* model tuner: also time the predicted top three when the
                         log-time gap between the best two is below this (0: 0.05) */
   hdconv_model_t model; /* model tuner: a cost model from hdconv_model_create   */
   const char* db_path; /* timed tuners: append every timing to this CSV (NULL: none) */
@@ -166,7 +166,9 @@ typedef struct hdconv_options {
 } hdconv_options;
 
 /* tuners (Sec. 7: the paper's optimizer times candidate (m, D, ...) per
- * dimension; the model tuner predicts those times and times only close calls) */
+ * dimension; the model tuner predicts those times, times its pick per
+ * dimension against the default plan (keeping the default unless the pick is
+ * faster), and on close calls times the predicted top three as well) */
 enum { HDCONV_TUNER_HEURISTIC = 0, HDCONV_TUNER_EXHAUSTIVE = 1, HDCONV_TUNER_MODEL = 2 };
 
 typedef struct hdconv_dim_info {

@@ -1869,11 +1869,18 @@ static int tune_shapes(const int64_t* L, const int64_t* M, int A, int B, int dim
     const std::vector<double>& key = model ? pred : meas;
     std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return key[a] < key[b]; });
     int best = ks[0];
-    if (model && ks.size() > 1 && pred[ks[1]] - pred[ks[0]] < margin) {
-      // close call: time the predicted top three and keep the fastest that runs
+    if (model && ks.size() > 1) {
+      // The model's pick is timed against the default plan, which it must
+      // beat to be taken (a guard against shapes the network ranks wrongly:
+      // timings taken under another runtime, or shapes it was never trained
+      // on); on a close call the predicted top three are timed as well.
+      // The fastest that runs is kept.
+      const bool close = pred[ks[1]] - pred[ks[0]] < margin;
+      std::vector<int> tk(ks.begin(), ks.begin() + (close ? std::min<size_t>(3, ks.size()) : 1));
+      for (int k : ks)
+        if (varied[k] == -1 && std::find(tk.begin(), tk.end(), k) == tk.end()) tk.push_back(k);
       double bm = 1e300;
-      for (size_t i = 0; i < ks.size() && i < 3; ++i) {
-        const int k = ks[i];
+      for (int k : tk) {
         if (!timed[k]) (void)time_one(k);
         if (meas[k] < bm) {
           bm = meas[k];

@@ -75,4 +75,5 @@ def test_model_tuner_times_few_candidates(gpu):
         im = pm.info()
     say("exhaustive timed %d of %d, model timed %d of %d" % (ie["timed_candidates"], ie["tuned_candidates"],
                                                                im["timed_candidates"], im["tuned_candidates"]))
-    assert im["timed_candidates"] <= 3 < ie["timed_candidates"]
+    # the pick and the default plan, or on a close call the top three and the default
+    assert im["timed_candidates"] <= 4 < ie["timed_candidates"]

@@ -62,3 +62,45 @@ def test_candidates_of_centered_and_hermitian_problems():
             assert shape[-1]["centered"] == (2 if flags == 8 else 1)
             f = tune.features(L, M, shape)
             assert f[44] == 1.0 and f[45] == (1.0 if flags == 8 else 0.0)
+
+
+def _rows(gids, ys, varied, dims):
+    n = len(gids)
+    return {"X": np.zeros((n, tune.NF), dtype=np.float32), "y": np.log(np.array(ys, dtype=np.float32)),
+            "gid": np.array(gids, dtype=np.int64), "varied": np.array(varied, dtype=np.int64),
+            "dims": np.array(dims, dtype=np.int64), "L": np.ones((n, 3), dtype=np.int64),
+            "M": np.ones((n, 3), dtype=np.int64), "A": np.full(n, 2, dtype=np.int64),
+            "shape": np.zeros((n, 3, 9), dtype=np.int64)}
+
+
+def test_costmodel_load_later_files_replace_geometries(tmp_path):
+    from paper_2303_17510_amd import costmodel
+    a = _rows([0, 0, 1, 1], [1.0, 2.0, 3.0, 4.0], [-1, 0, -1, 0], [1, 1, 1, 1])
+    b = _rows([1, 1, 1], [5.0, 6.0, 7.0], [-1, 0, 0], [1, 1, 1])
+    costmodel.save(a, str(tmp_path / "a.npz"))
+    costmodel.save(b, str(tmp_path / "b.npz"))
+    d = costmodel.load([str(tmp_path / "a.npz"), str(tmp_path / "b.npz")])
+    # geometry 0 keeps its two rows from a; geometry 1 has only b's three rows
+    assert sorted(d["gid"].tolist()) == [0, 0, 1, 1, 1]
+    assert np.allclose(np.sort(np.exp(d["y"][d["gid"] == 1])), [5.0, 6.0, 7.0], rtol=1e-5)
+
+
+class _FixedModel:
+    def __init__(self, pred):
+        self.pred = np.asarray(pred, dtype=np.float64)
+
+    def predict(self, X):
+        return self.pred
+
+
+def test_costmodel_evaluate_decision_regret():
+    from paper_2303_17510_amd import costmodel
+    # one 2D geometry: default (2 ms), two variations of dim 0 (1 ms, 3 ms), one of dim 1 (4 ms)
+    d = _rows([7, 7, 7, 7], [2.0, 1.0, 3.0, 4.0], [-1, 0, 0, 1], [2, 2, 2, 2])
+    # the model ranks the 3 ms variation first for dim 0 and the default first for dim 1
+    r = costmodel.evaluate(_FixedModel([np.log(2.0), np.log(1.5), np.log(0.5), np.log(5.0)]), d)
+    assert r["geometries"] == 1 and r["decisions"] == 2
+    assert abs(r["regret_max"] - 2.0) < 1e-6                 # picked 3 ms, best 1 ms
+    assert abs(r["decision_regret_max"] - 2.0) < 1e-6        # dim 0: 3 ms against 1 ms; dim 1: 2 against 2
+    assert abs(r["decision_regret_geomean"] - (np.sqrt(3.0) - 1.0)) < 1e-6
+    assert abs(r["gain_over_default_geomean"] - 2.0 / 3.0) < 1e-6
