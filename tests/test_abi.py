@@ -168,6 +168,17 @@ def test_default_row_points_per_lane(L, A, dtype, E):
     assert d["variant"] == "fused" and d["E_m"] == E
 
 
+@pytest.mark.parametrize("L,dtype,outer", [
+    ((256, 256, 256), "c64", (128, 2, 32)),   # 2^16+ columns: 32-column tiles, two half blocks on the tie
+    ((128, 128, 128), "c64", (128, 1, 16)),   # fewer columns: 16-column tiles, one block
+    ((256, 256, 256), "c128", (256, 1, 8)),   # FP64 keeps its tiles
+])
+def test_default_3d_outer_tiles(L, dtype, outer):
+    with Plan(L, tuple(2 * v for v in L), dtype=dtype, host_only=True) as p:
+        ds = p.info()["dims"]
+    assert all((d["variant"], d["m"], d["p"], d["S"]) == ("outer",) + outer for d in ds[:-1])
+
+
 def test_workspace_accounting_2d():
     # Sec. 5: the decomposition keeps q_x m_x rows of L_y per input
     p = Plan((2048, 2048), (4096, 4096), dtype="c64", host_only=True)
