@@ -66,7 +66,7 @@ def _regrets(names):
     p, hdr = _model()
     d = _load(names)
     pred = _predict(p, d["X"].astype(np.float64), hdr["nfeatures"], hdr["hidden"])
-    regrets, gains, decisions = [], [], []
+    regrets, gains, decisions, guarded = [], [], [], []
     for g in np.unique(d["gid"]):
         idx = np.nonzero(d["gid"] == g)[0]
         t = np.exp(d["y"][idx].astype(np.float64))
@@ -79,8 +79,12 @@ def _regrets(names):
         for dim in range(int(d["dims"][idx[0]])):
             sel = np.nonzero((var == -1) | (var == dim))[0]
             if len(sel) > 1:
-                decisions.append(t[sel][np.argmin(pred[idx][sel])] / t[sel].min() - 1.0)
-    return regrets, gains, decisions
+                pick_t = t[sel][np.argmin(pred[idx][sel])]
+                decisions.append(pick_t / t[sel].min() - 1.0)
+                if len(dflt):
+                    # the tuner times its pick against the default plan and keeps the faster
+                    guarded.append(min(pick_t, math.exp(float(d["y"][dflt[0]]))) / t[sel].min() - 1.0)
+    return regrets, gains, decisions, guarded
 
 
 def _gm(r):
@@ -88,18 +92,19 @@ def _gm(r):
 
 
 def test_shipped_picker_regret_within_five_percent():
-    regrets, gains, decisions = _regrets(["heldout.npz", "heldout3.npz"])
-    print("geometries %d, geomean regret %.4f, median %.4f, gain over default %.3f; %d decisions, geomean %.4f"
-          % (len(regrets), _gm(regrets), float(np.median(regrets)), math.exp(np.mean(np.log(gains))),
-             len(decisions), _gm(decisions)))
+    regrets, gains, decisions, guarded = _regrets(["heldout.npz", "heldout3.npz"])
+    print("geometries %d, geomean regret %.4f, median %.4f, gain over default %.3f; %d decisions, geomean %.4f, "
+          "guarded %.4f" % (len(regrets), _gm(regrets), float(np.median(regrets)),
+                            math.exp(np.mean(np.log(gains))), len(decisions), _gm(decisions), _gm(guarded)))
     assert len(regrets) >= 450
     assert _gm(regrets) <= 0.05
     assert _gm(decisions) <= 0.05
+    assert _gm(guarded) <= _gm(decisions)
 
 
 def test_shipped_picker_on_the_256_cube():
     # every candidate plan of the 3D 256^3 convolution (A = 2, M = 512^3), timed
-    regrets, gains, decisions = _regrets(["cube256.npz"])
+    regrets, gains, decisions, _ = _regrets(["cube256.npz"])
     print("256^3: regret %.4f, gain over default %.3f, decisions %s" % (regrets[0], gains[0], decisions))
     assert regrets[0] <= 0.05
     assert len(decisions) == 3 and _gm(decisions) <= 0.05
